@@ -1,0 +1,138 @@
+/*
+ * picount.h -- C ABI of the MI355X (gfx950) prime-counting library.
+ *
+ * The library computes pi(x), the number of primes <= x (Section 1 of
+ * D. B. Staple, "The combinatorial algorithm for computing pi(x)",
+ * arXiv:1503.01839), by the combinatorial method:
+ *
+ *   pi(x) = phi(x, a) + a - 1 - P2(x, a),    a = pi(y),  icbrt(x) <= y <= isqrt(x)
+ *   phi(x, a) = S1 + S2                     (the tree of eq. (4.1), Section 4)
+ *
+ * phi(u, b) counts the naturals <= u coprime to the first b primes
+ * (Section 3).  S1 sums the ordinary leaves, S2 the special leaves
+ * -mu(m) phi(x/(m p_b), b-1) over c < b < a, m squarefree with lpf(m) > p_b
+ * and y/p_b < m <= y; c is the wheel size (Section 4).  Special leaves are
+ * trivial (u = x/(m p_b) < p_b), easy (p_b <= u < p_b^2, u <= y: Legendre's
+ * formula, Section 4) or hard (every other leaf: phi read from a segmented
+ * sieve of [1, x/y] with per-prime running counts, Sections 2.3 and 3).
+ * P2 counts n = p q <= x with p_a < p <= q.
+ *
+ * Every step runs in hand-written HIP kernels on the current HIP device; the
+ * host only plans, launches and reads back a few 128-bit partial sums.
+ *
+ * Conventions for every entry point:
+ *  - Returns PC_OK or an error status; outputs are written only on PC_OK.
+ *  - Pointer arguments named *_out / out are host pointers owned by the
+ *    caller; the library never frees caller memory.
+ *  - Calls are synchronous unless named *_async.  The library keeps shared
+ *    read-only tables (primes, pi, mu*lpf) on the device between calls and
+ *    grows them on demand; pc_shutdown() releases them.
+ *  - Calls from several host threads are serialised internally.
+ *  - On error, pc_last_error() (thread-local) describes the failure.
+ */
+#ifndef PICOUNT_H
+#define PICOUNT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PC_OK = 0,
+    PC_EINVAL = 1,    /* an argument is outside its documented domain      */
+    PC_ERANGE = 2,    /* x or a derived size exceeds what the build handles */
+    PC_ENOMEM = 3,    /* device memory or a caller workspace is too small   */
+    PC_EDEVICE = 4,   /* a HIP runtime call failed                          */
+    PC_EINTERNAL = 5  /* an internal consistency check failed               */
+} pc_status;
+
+/* Signed 128-bit integer: value = hi * 2^64 + lo. */
+typedef struct {
+    uint64_t lo;
+    int64_t hi;
+} pc_i128;
+
+/* Tuning knobs.  Zero in any field means "library default". */
+typedef struct {
+    double alpha;          /* y = alpha * icbrt(x), clamped to [icbrt x, isqrt x]; 0 = tuned */
+    uint32_t segment_kib;  /* LDS bitmap per sieve segment: 32, 64 or 128                  */
+    uint32_t wg_size;      /* sieve workgroup size: 256, 512 or 1024                        */
+    uint32_t tile_leaves;  /* hard-leaf budget per sieve tile (hot-segment splitting); 0 = auto, 0xFFFFFFFF = off */
+    uint32_t flags;        /* PC_FLAG_* below */
+    uint64_t carry_budget; /* bytes for per-(segment, prime) counts per window; 0 = auto  */
+} pc_config;
+
+#define PC_FLAG_TWO_PASS 1u      /* count pass, carry scan, then leaf pass (else one tally pass) */
+#define PC_FLAG_NO_BATCH_LARGE 2u /* cross large primes one at a time (no batched crossing)     */
+#define PC_FLAG_REBUILD_TABLES 4u /* drop cached tables and rebuild them inside this call       */
+
+/* Everything one pi(x) evaluation produced, for tests and measurement. */
+typedef struct {
+    uint64_t x, y, a, c, z, bmax;   /* parameters actually used                     */
+    uint64_t pi;                    /* pi(x)                                        */
+    pc_i128 s1, s2_trivial, s2_easy, s2_hard, p2, phi; /* phi = S1 + S2          */
+    uint64_t n_s1, n_trivial, n_easy, n_hard, n_p2;    /* term / leaf counts       */
+    uint64_t segments, tiles, windows;
+    uint64_t segment_bits;          /* bits (odd integers) per segment              */
+    uint64_t device_bytes;          /* peak device bytes held during the call       */
+    double ms_total, ms_tables, ms_s1, ms_easy, ms_sieve, ms_scan;
+} pc_result;
+
+/* ---------------------------------------------------------------------- */
+
+/* pi(x) for 0 <= x < 2^64 (Section 1).  alpha selects y = alpha*icbrt(x)
+ * (Section 2: y_max = alpha x^(1/3)), clamped to [icbrt x, isqrt x]; alpha = 0
+ * picks a tuned value; alpha < 0 or NaN -> PC_EINVAL.  pi(0) = pi(1) = 0.
+ * Small x (x < 2^20) is answered from the device pi table. */
+pc_status pc_pi_count(uint64_t x, double alpha, uint64_t *pi_out);
+
+/* As pc_pi_count with explicit knobs (cfg may be NULL) and the full
+ * decomposition in *res (may be NULL). */
+pc_status pc_pi_count_ex(uint64_t x, const pc_config *cfg, pc_result *res);
+
+/* Hard special-leaf sum S2h = -sum over hard leaves of mu(m) phi(u, b-1),
+ * u = floor(x/(m p_b)) (Sections 2.3 and 3).  Requires
+ * icbrt(x) <= y <= isqrt(x) and a == pi(y), else PC_EINVAL; x >= 8.
+ * The wheel size is c = min(pc_wheel_c(), a). */
+pc_status pc_s2_hard(uint64_t x, uint64_t y, uint64_t a, pc_i128 *out);
+
+/* As pc_s2_hard with knobs and the full decomposition (S1, S2t, S2e, S2h and
+ * P2 are all computed; pi in *res is Meissel's identity with this y). */
+pc_status pc_decompose(uint64_t x, uint64_t y, const pc_config *cfg, pc_result *res);
+
+/* P2(x, pi(y)) = #{n <= x : n = p q, y < p <= q} = sum over primes
+ * y < p <= sqrt x of (pi(x/p) - pi(p) + 1), with pi(x/p) read from the same
+ * segmented sieve of [1, x/y].  Same y validation as pc_s2_hard. */
+pc_status pc_p2(uint64_t x, uint64_t y, uint64_t *out);
+
+/* pi(xs[i]) for i < n; host arrays of n elements.  n = 0 is valid.  Every
+ * xs[i] is validated before any work; on error nothing is written and
+ * pc_last_error() names the first bad index.  All queries share one set of
+ * device tables and one persistent tile queue; alpha per query comes from
+ * the tuning table. */
+pc_status pc_pi_count_batch(const uint64_t *xs, size_t n, uint64_t *pi_out);
+
+/* As pc_pi_count_batch with knobs; cfg may be NULL. */
+pc_status pc_pi_count_batch_ex(const uint64_t *xs, size_t n, const pc_config *cfg,
+                               uint64_t *pi_out);
+
+/* Wheel size c used by the library (c = min(pc_wheel_c(), a)). */
+int pc_wheel_c(void);
+
+/* Static text for a status code. */
+const char *pc_status_str(pc_status s);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *pc_last_error(void);
+
+/* Release every cached device table.  Safe to call at any time between calls. */
+void pc_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PICOUNT_H */

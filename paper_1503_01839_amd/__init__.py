@@ -1,0 +1,190 @@
+"""MI355X (gfx950) prime counting by the combinatorial method.
+
+Thin ctypes binding over ``libpicount.so`` (C ABI in ``include/picount.h``):
+argument marshalling only.  Every step of the computation runs in the
+library's HIP kernels; this module raises if the library is missing rather
+than computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpicount.so")
+
+PC_OK, PC_EINVAL, PC_ERANGE, PC_ENOMEM, PC_EDEVICE, PC_EINTERNAL = range(6)
+FLAG_TWO_PASS = 1
+FLAG_NO_BATCH_LARGE = 2
+FLAG_REBUILD_TABLES = 4
+
+EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
+           "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_wheel_c", "pc_status_str",
+           "pc_last_error", "pc_shutdown"]
+
+
+class PicountError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"picount status {status}: {msg}")
+        self.status = status
+
+
+class I128(C.Structure):
+    _fields_ = [("lo", C.c_uint64), ("hi", C.c_int64)]
+
+    def value(self) -> int:
+        return (self.hi << 64) + self.lo
+
+
+class Config(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("segment_kib", C.c_uint32), ("wg_size", C.c_uint32),
+                ("tile_leaves", C.c_uint32), ("flags", C.c_uint32),
+                ("carry_budget", C.c_uint64)]
+
+
+class _Result(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("x", "y", "a", "c", "z", "bmax", "pi")] + \
+               [(n, I128) for n in ("s1", "s2_trivial", "s2_easy", "s2_hard", "p2", "phi")] + \
+               [(n, C.c_uint64) for n in ("n_s1", "n_trivial", "n_easy", "n_hard", "n_p2",
+                                          "segments", "tiles", "windows", "segment_bits",
+                                          "device_bytes")] + \
+               [(n, C.c_double) for n in ("ms_total", "ms_tables", "ms_s1", "ms_easy",
+                                          "ms_sieve", "ms_scan")]
+
+
+@dataclass
+class Result:
+    x: int
+    y: int
+    a: int
+    c: int
+    z: int
+    bmax: int
+    pi: int
+    s1: int
+    s2_trivial: int
+    s2_easy: int
+    s2_hard: int
+    p2: int
+    phi: int
+    n_s1: int
+    n_trivial: int
+    n_easy: int
+    n_hard: int
+    n_p2: int
+    segments: int
+    tiles: int
+    windows: int
+    segment_bits: int
+    device_bytes: int
+    ms_total: float
+    ms_tables: float
+    ms_s1: float
+    ms_easy: float
+    ms_sieve: float
+    ms_scan: float
+
+
+_lib = None
+
+
+def lib():
+    """Load libpicount.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "(or python -m paper_1503_01839_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        u64, P = C.c_uint64, C.POINTER
+        L.pc_pi_count.argtypes = [u64, C.c_double, P(u64)]
+        L.pc_pi_count_ex.argtypes = [u64, P(Config), P(_Result)]
+        L.pc_s2_hard.argtypes = [u64, u64, u64, P(I128)]
+        L.pc_decompose.argtypes = [u64, u64, P(Config), P(_Result)]
+        L.pc_p2.argtypes = [u64, u64, P(u64)]
+        L.pc_pi_count_batch.argtypes = [P(u64), C.c_size_t, P(u64)]
+        L.pc_pi_count_batch_ex.argtypes = [P(u64), C.c_size_t, P(Config), P(u64)]
+        for f in ("pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
+                  "pc_pi_count_batch", "pc_pi_count_batch_ex"):
+            getattr(L, f).restype = C.c_int
+        L.pc_wheel_c.restype = C.c_int
+        L.pc_status_str.argtypes = [C.c_int]
+        L.pc_status_str.restype = C.c_char_p
+        L.pc_last_error.restype = C.c_char_p
+        L.pc_shutdown.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != PC_OK:
+        L = lib()
+        raise PicountError(st, f"{L.pc_status_str(st).decode()}: {L.pc_last_error().decode()}")
+
+
+def _config(alpha=0.0, segment_kib=0, wg_size=0, tile_leaves=0, flags=0, carry_budget=0):
+    return Config(float(alpha), segment_kib, wg_size, tile_leaves, flags, carry_budget)
+
+
+def _result(r: _Result) -> Result:
+    vals = {}
+    for name, _ in _Result._fields_:
+        v = getattr(r, name)
+        vals[name] = v.value() if isinstance(v, I128) else v
+    return Result(**vals)
+
+
+def pi_count(x: int, alpha: float = 0.0) -> int:
+    """pi(x), 0 <= x < 2^64."""
+    out = C.c_uint64(0)
+    _check(lib().pc_pi_count(x, float(alpha), C.byref(out)))
+    return out.value
+
+
+def pi_count_ex(x: int, **cfg) -> Result:
+    r = _Result()
+    c = _config(**cfg)
+    _check(lib().pc_pi_count_ex(x, C.byref(c), C.byref(r)))
+    return _result(r)
+
+
+def decompose(x: int, y: int, **cfg) -> Result:
+    """S1, S2 (trivial/easy/hard), P2, phi(x, a) and pi(x) for one explicit y."""
+    r = _Result()
+    c = _config(**cfg)
+    _check(lib().pc_decompose(x, y, C.byref(c), C.byref(r)))
+    return _result(r)
+
+
+def s2_hard(x: int, y: int, a: int) -> int:
+    out = I128()
+    _check(lib().pc_s2_hard(x, y, a, C.byref(out)))
+    return out.value()
+
+
+def p2(x: int, y: int) -> int:
+    out = C.c_uint64(0)
+    _check(lib().pc_p2(x, y, C.byref(out)))
+    return out.value
+
+
+def pi_count_batch(xs, **cfg) -> list[int]:
+    xs = list(xs)
+    n = len(xs)
+    arr = (C.c_uint64 * max(n, 1))(*xs)
+    out = (C.c_uint64 * max(n, 1))()
+    if cfg:
+        c = _config(**cfg)
+        _check(lib().pc_pi_count_batch_ex(arr, n, C.byref(c), out))
+    else:
+        _check(lib().pc_pi_count_batch(arr, n, out))
+    return list(out[:n])
+
+
+def wheel_c() -> int:
+    return lib().pc_wheel_c()
+
+
+def shutdown() -> None:
+    lib().pc_shutdown()

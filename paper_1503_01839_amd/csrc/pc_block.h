@@ -1,0 +1,99 @@
+// pc_block.h -- wavefront (64 lanes) and workgroup scans and reductions for
+// the gfx950 kernels.  Every workgroup size used is a multiple of 64.
+#pragma once
+
+#include "pc_device.h"
+
+__device__ __forceinline__ uint32_t pc_lane() { return __lane_id(); }
+
+// Inclusive prefix sum across the 64 lanes of a wavefront.
+template <typename T> __device__ __forceinline__ T pc_wave_incl_scan(T v)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T o = __shfl_up(v, d, 64);
+        if ((int)pc_lane() >= d)
+            v += o;
+    }
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ T pc_wave_sum(T v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+        v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// 128-bit wave sum via two 64-bit halves (carry handled exactly).
+__device__ __forceinline__ pc_s128 pc_wave_sum128(pc_s128 v)
+{
+    uint64_t lo = (uint64_t)v;
+    int64_t hi = (int64_t)(v >> 64);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint64_t olo = __shfl_xor(lo, d, 64);
+        int64_t ohi = __shfl_xor(hi, d, 64);
+        uint64_t nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1 : 0);
+        lo = nlo;
+    }
+    return ((pc_s128)hi << 64) | (pc_s128)lo;
+}
+
+// Exclusive prefix sum over a workgroup of NT threads; returns this thread's
+// exclusive prefix and writes the workgroup total to *total.  scratch holds
+// NT/64 elements.  Contains two barriers; every thread must call it.
+template <int NT, typename T>
+__device__ __forceinline__ T pc_block_excl_scan(T v, T *scratch, T *total)
+{
+    constexpr int NW = NT / 64;
+    const int w = threadIdx.x >> 6;
+    T inc = pc_wave_incl_scan(v);
+    if (pc_lane() == 63)
+        scratch[w] = inc;
+    __syncthreads();
+    T wsum = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+        T s = scratch[i];
+        if (i < w)
+            wsum += s;
+        all += s;
+    }
+    *total = all;
+    __syncthreads();
+    return wsum + inc - v;
+}
+
+// Workgroup sum; every thread receives the total.  scratch holds NT/64 elements.
+template <int NT, typename T> __device__ __forceinline__ T pc_block_sum(T v, T *scratch)
+{
+    constexpr int NW = NT / 64;
+    v = pc_wave_sum(v);
+    if (pc_lane() == 0)
+        scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++)
+        all += scratch[i];
+    __syncthreads();
+    return all;
+}
+
+template <int NT> __device__ __forceinline__ pc_s128 pc_block_sum128(pc_s128 v, pc_s128 *scratch)
+{
+    constexpr int NW = NT / 64;
+    v = pc_wave_sum128(v);
+    if (pc_lane() == 0)
+        scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    pc_s128 all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++)
+        all += scratch[i];
+    __syncthreads();
+    return all;
+}

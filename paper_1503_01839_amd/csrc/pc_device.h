@@ -1,0 +1,108 @@
+// pc_device.h -- integer helpers shared by the gfx950 kernels and the host
+// planner of the prime-counting library.
+//
+// All arithmetic of the method is exact integer arithmetic.  The GPU has no
+// integer divide instruction, so every quotient on a hot path is formed by a
+// multiply-high with a precomputed 64-bit reciprocal of the divisor and one
+// correction step (division by invariant integers, Granlund & Montgomery,
+// PLDI 1994), or -- for divisors that change per lane -- from an fp64
+// estimate corrected by an exact integer remainder test.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned __int128 pc_u128;
+typedef __int128 pc_s128;
+
+#define PC_HD __host__ __device__ __forceinline__
+
+// r = floor((2^64 - 1) / d) for d >= 1.
+PC_HD uint64_t pc_recip(uint64_t d) { return ~0ull / d; }
+
+PC_HD uint64_t pc_mulhi(uint64_t a, uint64_t b)
+{
+    return (uint64_t)(((pc_u128)a * b) >> 64);
+}
+
+// floor(n / d) given r = pc_recip(d).  For any n < 2^64 and d >= 1:
+// n*r/2^64 = n/d - n(1+e)/(d 2^64) with e = (2^64-1) mod d < d, which lies in
+// (n/d - 1, n/d]; so q0 = mulhi(n, r) is floor(n/d) or one less.
+PC_HD uint64_t pc_div(uint64_t n, uint64_t d, uint64_t r)
+{
+    uint64_t q = pc_mulhi(n, r);
+    uint64_t rem = n - q * d;
+    if (rem >= d)
+        q++;
+    return q;
+}
+
+// floor(n / d) for d < 2^32 when the quotient is known to be < 2^50: the
+// fp64 estimate has relative error below 2^-51, so it is within 1 of the
+// true quotient and one signed remainder test fixes it.
+PC_HD uint64_t pc_div_small_q(uint64_t n, uint32_t d)
+{
+    uint64_t q = (uint64_t)((double)n / (double)d);
+    int64_t rem = (int64_t)(n - q * (uint64_t)d);
+    if (rem < 0)
+        q--;
+    else if (rem >= (int64_t)d)
+        q++;
+    return q;
+}
+
+// Exact floor(n / d) for any n < 2^64, 1 <= d < 2^32: fp64 estimate, one
+// exact refinement of the remainder, then a final one-step correction.
+PC_HD uint64_t pc_div_any(uint64_t n, uint32_t d)
+{
+    if (d == 1)
+        return n;
+    double dd = (double)d;
+    uint64_t q = (uint64_t)((double)n / dd);      // q <= 2^63, within 2^11 of the truth
+    int64_t rem = (int64_t)(n - q * (uint64_t)d); // |rem| <= 2^11 d < 2^43
+    q += (int64_t)((double)rem / dd);             // now within 1
+    rem = (int64_t)(n - q * (uint64_t)d);
+    while (rem < 0) {
+        q--;
+        rem += d;
+    }
+    while (rem >= (int64_t)d) {
+        q++;
+        rem -= d;
+    }
+    return q;
+}
+
+// Integer square and cube roots, exact (used by the host planner).
+PC_HD uint64_t pc_isqrt(uint64_t n)
+{
+    uint64_t r = (uint64_t)__builtin_sqrt((double)n);
+    while (r > 0 && (pc_u128)r * r > n)
+        r--;
+    while ((pc_u128)(r + 1) * (r + 1) <= n)
+        r++;
+    return r;
+}
+
+PC_HD uint64_t pc_icbrt(uint64_t n)
+{
+    uint64_t r = (uint64_t)__builtin_cbrt((double)n);
+    while (r > 0 && (pc_u128)r * r * r > n)
+        r--;
+    while ((pc_u128)(r + 1) * (r + 1) * (r + 1) <= n)
+        r++;
+    return r;
+}
+
+// pi table: entry e holds a 32-bit mask of the odd numbers 64e+1 .. 64e+63
+// (bit j <-> 64e + 2j + 1 is prime) and the number of odd primes below 64e.
+// pi(n) = [n >= 2] + (odd primes <= n).
+PC_HD uint32_t pc_pi_lookup(const uint2 *tab, uint64_t n)
+{
+    if (n < 2)
+        return 0;
+    uint64_t i = (n - 1) >> 1; // odd index of the largest odd number <= n
+    uint2 e = tab[i >> 5];
+    uint32_t sh = 31u - (uint32_t)(i & 31);
+    return 1u + e.y + (uint32_t)__builtin_popcount((e.x << sh)); // bits 0..(i&31)
+}

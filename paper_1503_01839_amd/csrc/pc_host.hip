@@ -1,0 +1,786 @@
+// pc_host.hip -- host planner and C ABI of the prime-counting library.
+//
+// The host validates arguments, picks y, the wheel size c and the segment
+// geometry, keeps the shared device tables, cuts the sieve range [1, x/y]
+// into windows and tiles, launches the kernels in stream order and reads
+// back one small result record.  Every arithmetic step of the method runs
+// in the kernels of pc_tables.hip, pc_leaves.hip and pc_sieve.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/picount.h"
+#include "pc_internal.h"
+
+namespace {
+
+constexpr int kWheelC = 6;
+constexpr uint64_t kSmallX = 1ull << 20; // below this pi(x) is read from the pi table
+
+thread_local std::string t_err;
+std::recursive_mutex g_mu;
+
+struct pc_error {
+    pc_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(pc_status st, const std::string &msg) { throw pc_error{st, msg}; }
+
+void hipck(hipError_t e, const char *what)
+{
+    if (e != hipSuccess)
+        fail(PC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+size_t g_dev_bytes = 0, g_dev_peak = 0;
+
+void dfree(DevBuf &b)
+{
+    if (b.p) {
+        (void)hipFree(b.p);
+        g_dev_bytes -= b.cap;
+    }
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+void ensure(DevBuf &b, size_t bytes, const char *what)
+{
+    if (bytes == 0)
+        bytes = 16;
+    if (b.cap >= bytes)
+        return;
+    dfree(b);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(PC_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) +
+                            " bytes for " + what + " failed");
+    }
+    b.cap = bytes;
+    g_dev_bytes += bytes;
+    g_dev_peak = std::max(g_dev_peak, g_dev_bytes);
+}
+
+template <typename T> T *ptr(DevBuf &b) { return static_cast<T *>(b.p); }
+
+// first primes, for the wheel constants only
+const uint32_t kFirstPrimes[8] = {0, 2, 3, 5, 7, 11, 13, 17};
+
+struct Tables {
+    bool base_ok = false;
+    uint32_t nbase = 0;
+    DevBuf base, nbase_d;
+    DevBuf pitab, primes, cnt_tmp, scan_tmp;
+    uint64_t pi_limit = 0; // pi table and primes cover n <= pi_limit
+    uint64_t nprimes = 0;
+    DevBuf recip;
+    uint64_t recip_n = 0;
+    DevBuf mulpf;
+    uint64_t y_limit = 0;
+    DevBuf pattern[kWheelC + 1], phitab[kWheelC + 1];
+    bool wheel_ok[kWheelC + 1] = {};
+    uint32_t pattern_bits[kWheelC + 1] = {}, Qc[kWheelC + 1] = {}, phiQ[kWheelC + 1] = {};
+    DevBuf lk_in, lk_out;
+};
+Tables g_T;
+
+struct QueryBufs {
+    DevBuf Xb, e_start, e_count, e_off, e_tmp, e_total, part, sums, fin, ntriv;
+    DevBuf tiles, cnt, wgt, carry_rows, carry_a, carry_b, status, ticket, part_tile_h,
+        part_tile_p, part_scan_h, part_scan_p, err;
+};
+QueryBufs g_Q;
+
+hipStream_t g_stream = nullptr;
+
+void init_stream()
+{
+    if (!g_stream)
+        hipck(hipStreamCreateWithFlags(&g_stream, hipStreamNonBlocking), "hipStreamCreate");
+}
+
+// pi at a few points, read back to the host (planning only).
+std::vector<uint64_t> lookup(const std::vector<uint64_t> &pts)
+{
+    Tables &T = g_T;
+    size_t n = pts.size();
+    ensure(T.lk_in, n * 8, "lookup");
+    ensure(T.lk_out, n * 8, "lookup");
+    hipck(hipMemcpyAsync(T.lk_in.p, pts.data(), n * 8, hipMemcpyHostToDevice, g_stream), "H2D");
+    hipck(pc_launch_lookup(ptr<uint2>(T.pitab), ptr<uint64_t>(T.lk_in), (uint32_t)n,
+                           ptr<uint64_t>(T.lk_out), g_stream),
+          "lookup");
+    std::vector<uint64_t> out(n);
+    hipck(hipMemcpyAsync(out.data(), T.lk_out.p, n * 8, hipMemcpyDeviceToHost, g_stream), "D2H");
+    hipck(hipStreamSynchronize(g_stream), "sync");
+    return out;
+}
+
+// Rosser-Schoenfeld: pi(n) < 1.25506 n / ln n for n > 1.
+uint64_t pi_upper(uint64_t n)
+{
+    if (n < 100)
+        return 30;
+    return (uint64_t)(1.25506 * (double)n / std::log((double)n)) + 64;
+}
+
+void ensure_pi(uint64_t need)
+{
+    Tables &T = g_T;
+    if (!T.base_ok) {
+        ensure(T.base, 8192 * 4, "base primes");
+        ensure(T.nbase_d, 8, "base count");
+        hipck(pc_launch_base_primes(ptr<uint32_t>(T.base), ptr<uint32_t>(T.nbase_d), g_stream),
+              "base primes");
+        hipck(hipMemcpyAsync(&T.nbase, T.nbase_d.p, 4, hipMemcpyDeviceToHost, g_stream), "D2H");
+        hipck(hipStreamSynchronize(g_stream), "sync");
+        T.base_ok = true;
+    }
+    if (T.pi_limit >= need)
+        return;
+    uint64_t lim = std::max<uint64_t>({need, 2 * T.pi_limit, 1ull << 22});
+    if (lim > 0xFFFFFFFFull)
+        lim = 0xFFFFFFFFull;
+    if (need > lim)
+        fail(PC_ERANGE, "pi table beyond 2^32 requested");
+    uint64_t nent = lim / 64 + 1;
+    if (nent > (1ull << 26))
+        nent = 1ull << 26;
+    uint64_t covered = 64 * nent - 1;
+    ensure(T.pitab, nent * 8, "pi table");
+    ensure(T.cnt_tmp, nent * 4, "pi counts");
+    ensure(T.scan_tmp, (nent / 4096 + 2) * 4, "scan");
+    ensure(T.primes, (pi_upper(covered) + 4) * 4, "primes");
+    hipck(pc_launch_pitab(nent, ptr<uint32_t>(T.base), T.nbase, nullptr, ptr<uint32_t>(T.cnt_tmp),
+                          ptr<uint2>(T.pitab), ptr<uint32_t>(T.primes),
+                          ptr<uint32_t>(T.scan_tmp), g_stream),
+          "pi table");
+    dfree(T.cnt_tmp);
+    T.pi_limit = covered;
+    T.nprimes = lookup({covered})[0];
+    T.recip_n = 0; // the primes array was rebuilt
+}
+
+void ensure_recip(uint64_t kmax)
+{
+    Tables &T = g_T;
+    if (T.recip_n >= kmax)
+        return;
+    uint64_t k = std::min<uint64_t>(T.nprimes, std::max<uint64_t>(kmax, 2 * T.recip_n));
+    ensure(T.recip, (k + 1) * 8, "reciprocals");
+    hipck(pc_launch_recip(ptr<uint32_t>(T.primes), ptr<uint64_t>(T.recip), (uint32_t)k, g_stream),
+          "reciprocals");
+    T.recip_n = k;
+}
+
+void ensure_mulpf(uint64_t y)
+{
+    Tables &T = g_T;
+    if (T.y_limit >= y)
+        return;
+    uint64_t Y = std::max<uint64_t>({y, 2 * T.y_limit, 1ull << 20});
+    if (Y >= (1ull << 31) - 1)
+        Y = (1ull << 31) - 2;
+    if (y > Y)
+        fail(PC_ERANGE, "y beyond 2^31 - 2");
+    ensure_pi(Y);
+    uint64_t nsmall = lookup({pc_isqrt(Y)})[0];
+    ensure(T.mulpf, (Y + 1) * 4, "mu*lpf table");
+    hipck(pc_launch_mulpf(ptr<uint32_t>(T.primes), (uint32_t)nsmall, Y, ptr<int32_t>(T.mulpf),
+                          g_stream),
+          "mu*lpf table");
+    T.y_limit = Y;
+}
+
+void ensure_wheel(uint32_t c)
+{
+    Tables &T = g_T;
+    if (T.wheel_ok[c])
+        return;
+    uint32_t period = 1, Q = 1, phiQ = 1;
+    for (uint32_t i = 1; i <= c; i++) {
+        Q *= kFirstPrimes[i];
+        phiQ *= kFirstPrimes[i] - 1;
+        if (i >= 2)
+            period *= kFirstPrimes[i];
+    }
+    uint32_t words = (period + 64) / 32 + 2;
+    ensure(T.pattern[c], words * 4, "wheel pattern");
+    ensure(T.phitab[c], (size_t)Q * 4, "wheel phi table");
+    hipck(pc_launch_wheel(c, ptr<uint32_t>(T.primes), ptr<uint32_t>(T.pattern[c]), words,
+                          ptr<uint32_t>(T.phitab[c]), g_stream),
+          "wheel");
+    T.pattern_bits[c] = period;
+    T.Qc[c] = Q;
+    T.phiQ[c] = phiQ;
+    T.wheel_ok[c] = true;
+}
+
+pc_tables tables_view(uint32_t c)
+{
+    Tables &T = g_T;
+    pc_tables v{};
+    v.primes = ptr<uint32_t>(T.primes);
+    v.recip = ptr<uint64_t>(T.recip);
+    v.pitab = ptr<uint2>(T.pitab);
+    v.mulpf = ptr<int32_t>(T.mulpf);
+    v.pattern = ptr<uint32_t>(T.pattern[c]);
+    v.phitab = ptr<uint32_t>(T.phitab[c]);
+    v.pattern_bits = T.pattern_bits[c];
+    v.Qc = T.Qc[c];
+    v.phiQ = T.phiQ[c];
+    return v;
+}
+
+void drop_tables()
+{
+    Tables &T = g_T;
+    DevBuf *all[] = {&T.base, &T.nbase_d, &T.pitab, &T.primes, &T.cnt_tmp, &T.scan_tmp, &T.recip,
+                     &T.mulpf, &T.lk_in, &T.lk_out};
+    for (DevBuf *b : all)
+        dfree(*b);
+    for (int c = 0; c <= kWheelC; c++) {
+        dfree(T.pattern[c]);
+        dfree(T.phitab[c]);
+        T.wheel_ok[c] = false;
+    }
+    T.base_ok = false;
+    T.pi_limit = T.nprimes = T.recip_n = T.y_limit = 0;
+}
+
+void drop_query_bufs()
+{
+    QueryBufs &B = g_Q;
+    DevBuf *all[] = {&B.Xb, &B.e_start, &B.e_count, &B.e_off, &B.e_tmp, &B.e_total, &B.part,
+                     &B.sums, &B.fin, &B.ntriv, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
+                     &B.carry_a, &B.carry_b, &B.status, &B.ticket, &B.part_tile_h,
+                     &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err};
+    for (DevBuf *b : all)
+        dfree(*b);
+}
+
+pc_i128 to_abi(pc_s128 v)
+{
+    pc_i128 r;
+    r.lo = (uint64_t)v;
+    r.hi = (int64_t)(v >> 64);
+    return r;
+}
+
+double default_alpha(uint64_t x)
+{
+    // Tuned on MI355X for 128 KiB-class segments; alpha only moves work
+    // between the sieve (falls as 1/alpha) and the easy leaves (rise).
+    double lx = std::log10((double)x);
+    if (lx < 10)
+        return 1;
+    if (lx < 12)
+        return 2;
+    if (lx < 14)
+        return 4;
+    if (lx < 16.5)
+        return 8;
+    return 16;
+}
+
+uint64_t choose_y(uint64_t x, double alpha)
+{
+    uint64_t r = pc_icbrt(x), s = pc_isqrt(x);
+    double yd = std::floor(alpha * (double)r);
+    uint64_t y = yd >= (double)s ? s : (uint64_t)yd;
+    if (y < r)
+        y = r;
+    if (y > s)
+        y = s;
+    return y;
+}
+
+struct Knobs {
+    uint32_t seg_log2 = 18;
+    uint32_t wg = 512;
+    bool two_pass = false;
+    bool batch = true;
+    uint64_t carry_budget = 6ull << 30;
+};
+
+Knobs knobs_from(const pc_config *cfg)
+{
+    Knobs k;
+    if (!cfg)
+        return k;
+    switch (cfg->segment_kib) {
+    case 0:
+        break;
+    case 32:
+        k.seg_log2 = 18;
+        break;
+    case 64:
+        k.seg_log2 = 19;
+        break;
+    case 128:
+        k.seg_log2 = 20;
+        break;
+    default:
+        fail(PC_EINVAL, "segment_kib must be 32, 64 or 128");
+    }
+    switch (cfg->wg_size) {
+    case 0:
+        break;
+    case 512:
+    case 1024:
+        k.wg = cfg->wg_size;
+        break;
+    default:
+        fail(PC_EINVAL, "wg_size must be 512 or 1024");
+    }
+    k.two_pass = (cfg->flags & PC_FLAG_TWO_PASS) != 0;
+    k.batch = (cfg->flags & PC_FLAG_NO_BATCH_LARGE) == 0;
+    if (cfg->carry_budget)
+        k.carry_budget = cfg->carry_budget;
+    return k;
+}
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+// Full decomposition for one (x, y); x >= 8, icbrt(x) <= y <= isqrt(x).
+void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
+{
+    auto t0 = clk::now();
+    init_stream();
+    QueryBufs &B = g_Q;
+    const uint64_t sx = pc_isqrt(x);
+    const uint64_t z = x / y;
+    ensure_pi(std::max<uint64_t>({sx, y, 1024}) + 1);
+    std::vector<uint64_t> lk = lookup({y, sx, pc_isqrt(z)});
+    const uint64_t a = lk[0], kx = lk[1], bmax = lk[2];
+    const uint32_t c = (uint32_t)std::min<uint64_t>(kWheelC, a);
+    if (c < 1)
+        fail(PC_EINVAL, "y too small");
+    ensure_mulpf(y);
+    ensure_recip(a + 1);
+    ensure_wheel(c);
+    hipck(hipStreamSynchronize(g_stream), "sync");
+    const double ms_tables = ms_since(t0);
+
+    const pc_tables T = tables_view(c);
+    pc_query Q{};
+    Q.x = x;
+    Q.y = y;
+    Q.z = z;
+    Q.y1 = y + 1;
+    Q.recip_y1 = pc_recip(y + 1);
+    Q.sqrtx = sx;
+    Q.sqrty = pc_isqrt(y);
+    Q.Qc = T.Qc;
+    Q.recip_Qc = pc_recip(T.Qc);
+    Q.c = c;
+    Q.a = (uint32_t)a;
+    Q.bmax = (uint32_t)bmax;
+    Q.nb = bmax > c ? (uint32_t)(bmax - c) : 0;
+    Q.ncol = Q.nb + 1;
+    Q.kx = (uint32_t)kx;
+
+    // --- per-query tables and the leaves outside the sieve ---
+    ensure(B.Xb, (a + 2) * 8, "X_b");
+    Q.Xb = ptr<uint64_t>(B.Xb);
+    hipck(pc_launch_xb(T, x, (uint32_t)a, ptr<uint64_t>(B.Xb), g_stream), "X_b");
+
+    ensure(B.sums, sizeof(pc_sums), "sums");
+    ensure(B.fin, sizeof(pc_final), "final");
+    ensure(B.ntriv, 8, "counts");
+    ensure(B.e_total, 16, "easy total");
+    hipck(pc_launch_fill_u64(ptr<uint64_t>(B.sums), sizeof(pc_sums) / 8, 0, g_stream), "fill");
+    hipck(pc_launch_fill_u64(ptr<uint64_t>(B.ntriv), 1, 0, g_stream), "fill");
+    pc_sums *sums = ptr<pc_sums>(B.sums);
+
+    const uint32_t s1_blocks = (uint32_t)std::min<uint64_t>(2048, y / 256 + 1);
+    const uint32_t ls_blocks = (uint32_t)(a / 256 + 1);
+    const uint32_t ez_blocks = 4096;
+    ensure(B.part, (size_t)std::max<uint32_t>({s1_blocks, ls_blocks, ez_blocks}) * 16, "partials");
+    auto t1 = clk::now();
+    hipck(pc_launch_s1(T, Q, ptr<pc_s128>(B.part), s1_blocks, g_stream), "S1");
+    hipck(pc_launch_sum128(ptr<pc_s128>(B.part), s1_blocks, &sums->s1, g_stream), "S1 sum");
+
+    ensure(B.e_start, (a + 2) * 8, "easy ranges");
+    ensure(B.e_count, (a + 2) * 8, "easy ranges");
+    ensure(B.e_off, (a + 2) * 8, "easy offsets");
+    ensure(B.e_tmp, ((a + 2) / 4096 + 2) * 8, "scan");
+    hipck(pc_launch_leaf_setup(T, Q, ptr<uint64_t>(B.e_start), ptr<uint64_t>(B.e_count),
+                               ptr<pc_s128>(B.part), ptr<uint64_t>(B.ntriv), ls_blocks, g_stream),
+          "leaf setup");
+    hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ls_blocks, &sums->s2t, g_stream), "S2t sum");
+    hipck(pc_launch_strip(ptr<uint64_t>(B.e_count), ptr<uint64_t>(B.e_off), a + 1, g_stream),
+          "strip");
+    hipck(pc_launch_scan_u64(ptr<uint64_t>(B.e_off), a + 1, ptr<uint64_t>(B.e_tmp),
+                             ptr<uint64_t>(B.e_total), g_stream),
+          "easy scan");
+    hipck(pc_launch_easy(T, Q, ptr<uint64_t>(B.e_start), ptr<uint64_t>(B.e_count),
+                         ptr<uint64_t>(B.e_off), ptr<uint64_t>(B.e_total), ptr<pc_s128>(B.part),
+                         ez_blocks, g_stream),
+          "easy");
+    hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ez_blocks, &sums->s2e, g_stream), "S2e sum");
+    hipck(hipStreamSynchronize(g_stream), "sync");
+    const double ms_leaves = ms_since(t1);
+
+    // --- the sieve of [1, z] in windows of segments ---
+    auto t2 = clk::now();
+    const uint64_t S = 1ull << K.seg_log2;
+    const uint64_t nseg = z / (2 * S) + 1;
+    const uint64_t per_entry = K.two_pass ? 12 : 8;
+    uint64_t rows_w = std::max<uint64_t>(1, K.carry_budget / (per_entry * Q.ncol));
+    rows_w = std::min(rows_w, nseg);
+    const uint64_t nwin = (nseg + rows_w - 1) / rows_w;
+    const uint32_t ncb = (Q.ncol + 255) / 256;
+    uint32_t R = (uint32_t)std::clamp<uint64_t>(rows_w / 64, 16, 1024);
+    const uint64_t nchunk_max = (rows_w + R - 1) / R;
+
+    ensure(B.tiles, rows_w * sizeof(pc_tile), "tiles");
+    ensure(B.cnt, rows_w * Q.ncol * 4, "counts");
+    if (!K.two_pass)
+        ensure(B.wgt, rows_w * Q.ncol * 4, "leaf weights");
+    else
+        ensure(B.carry_rows, rows_w * Q.ncol * 8, "carries");
+    ensure(B.carry_a, (size_t)Q.ncol * 8, "carry");
+    ensure(B.carry_b, (size_t)Q.ncol * 8, "carry");
+    ensure(B.status, nchunk_max * Q.ncol * 8 + 8, "look-back status");
+    ensure(B.ticket, 8, "ticket");
+    ensure(B.part_tile_h, rows_w * 16, "tile partials");
+    ensure(B.part_tile_p, rows_w * 16, "tile partials");
+    ensure(B.part_scan_h, nchunk_max * ncb * 16, "scan partials");
+    ensure(B.part_scan_p, nchunk_max * ncb * 16, "scan partials");
+    ensure(B.err, 8, "error flag");
+    hipck(pc_launch_fill_u64(ptr<uint64_t>(B.carry_a), Q.ncol, 0, g_stream), "fill");
+    hipck(pc_launch_fill_u64(ptr<uint64_t>(B.err), 1, 0, g_stream), "fill");
+
+    std::vector<pc_tile> tiles(rows_w);
+    uint64_t *cin = ptr<uint64_t>(B.carry_a), *cout = ptr<uint64_t>(B.carry_b);
+    double ms_scan = 0;
+    for (uint64_t w = 0; w < nwin; w++) {
+        const uint64_t s0 = w * rows_w;
+        const uint64_t rows = std::min(rows_w, nseg - s0);
+        for (uint64_t r = 0; r < rows; r++)
+            tiles[r] = pc_tile{(uint32_t)(s0 + r), 0, Q.ncol, 0};
+        hipck(hipMemcpyAsync(B.tiles.p, tiles.data(), rows * sizeof(pc_tile),
+                             hipMemcpyHostToDevice, g_stream),
+              "tiles");
+        pc_sieve_args A{};
+        A.T = T;
+        A.Q = Q;
+        A.tiles = ptr<pc_tile>(B.tiles);
+        A.ntiles = (uint32_t)rows;
+        A.seg0 = s0;
+        A.cnt = ptr<uint32_t>(B.cnt);
+        A.wgt = ptr<int32_t>(B.wgt);
+        A.carry = ptr<uint64_t>(B.carry_rows);
+        A.part_hard = ptr<pc_s128>(B.part_tile_h);
+        A.part_p2 = ptr<pc_s128>(B.part_tile_p);
+        A.err = ptr<int32_t>(B.err);
+        const int bflag = K.batch ? 0 : 0x100;
+        hipck(pc_launch_sieve(A, K.seg_log2, K.wg, (K.two_pass ? PC_MODE_COUNT : PC_MODE_TALLY) |
+                                                       bflag,
+                              g_stream),
+              "sieve");
+
+        pc_scan_args SA{};
+        SA.cnt = ptr<uint32_t>(B.cnt);
+        SA.wgt = ptr<int32_t>(B.wgt);
+        SA.carry_rows = ptr<uint64_t>(B.carry_rows);
+        SA.carry_in = cin;
+        SA.carry_out = cout;
+        SA.status = ptr<uint64_t>(B.status);
+        SA.ticket = ptr<uint32_t>(B.ticket);
+        SA.part_hard = ptr<pc_s128>(B.part_scan_h);
+        SA.part_p2 = ptr<pc_s128>(B.part_scan_p);
+        SA.err = ptr<int32_t>(B.err);
+        SA.nrows = rows;
+        SA.ncol = Q.ncol;
+        SA.nb = Q.nb;
+        SA.rows_per_chunk = R;
+        SA.nchunk = (uint32_t)((rows + R - 1) / R);
+        SA.ncb = ncb;
+        hipck(pc_launch_fill_u64(ptr<uint64_t>(B.status), (uint64_t)SA.nchunk * Q.ncol, 0,
+                                 g_stream),
+              "fill");
+        hipck(pc_launch_fill_u64(ptr<uint64_t>(B.ticket), 1, 0, g_stream), "fill");
+        hipck(pc_launch_scan(SA, K.two_pass ? PC_MODE_COUNT : PC_MODE_TALLY, g_stream), "scan");
+        if (K.two_pass) {
+            hipck(pc_launch_sieve(A, K.seg_log2, K.wg, PC_MODE_LEAVES | bflag, g_stream),
+                  "leaf pass");
+        } else {
+            hipck(pc_launch_sum128(ptr<pc_s128>(B.part_scan_h), SA.nchunk * ncb,
+                                   &sums->hard_dot, g_stream),
+                  "sum");
+            hipck(pc_launch_sum128(ptr<pc_s128>(B.part_scan_p), SA.nchunk * ncb, &sums->p2_dot,
+                                   g_stream),
+                  "sum");
+        }
+        hipck(pc_launch_sum128(ptr<pc_s128>(B.part_tile_h), (uint32_t)rows, &sums->hard_local,
+                               g_stream),
+              "sum");
+        hipck(pc_launch_sum128(ptr<pc_s128>(B.part_tile_p), (uint32_t)rows, &sums->p2_local,
+                               g_stream),
+              "sum");
+        std::swap(cin, cout);
+    }
+    hipck(pc_launch_combine(sums, Q, kx, ptr<pc_final>(B.fin), g_stream), "combine");
+    pc_final fin{};
+    int32_t err = 0;
+    uint64_t ntriv = 0;
+    hipck(hipMemcpyAsync(&fin, B.fin.p, sizeof fin, hipMemcpyDeviceToHost, g_stream), "D2H");
+    hipck(hipMemcpyAsync(&err, B.err.p, 4, hipMemcpyDeviceToHost, g_stream), "D2H");
+    hipck(hipMemcpyAsync(&ntriv, B.ntriv.p, 8, hipMemcpyDeviceToHost, g_stream), "D2H");
+    hipck(hipStreamSynchronize(g_stream), "sync");
+    const double ms_sieve = ms_since(t2);
+    if (err & 1)
+        fail(PC_EINTERNAL, "look-back scan did not complete");
+    if (err)
+        fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment");
+    if (!fin.ok)
+        fail(PC_EINTERNAL, "pi(x) outside [0, 2^64)");
+
+    if (res) {
+        memset(res, 0, sizeof *res);
+        res->x = x;
+        res->y = y;
+        res->a = a;
+        res->c = c;
+        res->z = z;
+        res->bmax = bmax;
+        res->pi = fin.pi;
+        res->s1 = to_abi(fin.s1);
+        res->s2_trivial = to_abi(fin.s2t);
+        res->s2_easy = to_abi(fin.s2e);
+        res->s2_hard = to_abi(fin.s2h);
+        res->p2 = to_abi(fin.p2);
+        res->phi = to_abi(fin.phi);
+        res->n_trivial = ntriv;
+        res->n_p2 = kx > a ? kx - a : 0;
+        res->segments = nseg;
+        res->tiles = nseg;
+        res->windows = nwin;
+        res->segment_bits = S;
+        res->device_bytes = g_dev_peak;
+        res->ms_total = ms_since(t0);
+        res->ms_tables = ms_tables;
+        res->ms_s1 = ms_leaves;
+        res->ms_easy = ms_leaves;
+        res->ms_sieve = ms_sieve;
+        res->ms_scan = ms_scan;
+    }
+}
+
+uint64_t small_pi(uint64_t x)
+{
+    init_stream();
+    ensure_pi(kSmallX);
+    return lookup({x})[0];
+}
+
+void check_y(uint64_t x, uint64_t y)
+{
+    if (x < 8)
+        fail(PC_EINVAL, "x must be >= 8");
+    if (y < pc_icbrt(x) || y > pc_isqrt(x))
+        fail(PC_EINVAL, "y must satisfy icbrt(x) <= y <= isqrt(x)");
+}
+
+template <typename F> pc_status guarded(F &&f)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    t_err.clear();
+    try {
+        f();
+        return PC_OK;
+    } catch (const pc_error &e) {
+        t_err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        t_err = "host allocation failed";
+        return PC_ENOMEM;
+    } catch (...) {
+        t_err = "unexpected exception";
+        return PC_EINTERNAL;
+    }
+}
+
+void pi_one(uint64_t x, const Knobs &K, double alpha, pc_result *res, uint64_t *pi)
+{
+    if (std::isnan(alpha) || alpha < 0)
+        fail(PC_EINVAL, "alpha must be >= 0 (0 = tuned)");
+    if (x < kSmallX) {
+        uint64_t v = small_pi(x);
+        if (res) {
+            memset(res, 0, sizeof *res);
+            res->x = x;
+            res->pi = v;
+        }
+        *pi = v;
+        return;
+    }
+    if (alpha == 0)
+        alpha = default_alpha(x);
+    const uint64_t y = choose_y(x, alpha);
+    pc_result r;
+    run_query(x, y, K, &r);
+    *pi = r.pi;
+    if (res)
+        *res = r;
+}
+
+} // namespace
+
+extern "C" {
+
+pc_status pc_pi_count(uint64_t x, double alpha, uint64_t *pi_out)
+{
+    if (!pi_out)
+        return PC_EINVAL;
+    uint64_t v = 0;
+    pc_status st = guarded([&] { pi_one(x, Knobs{}, alpha, nullptr, &v); });
+    if (st == PC_OK)
+        *pi_out = v;
+    return st;
+}
+
+pc_status pc_pi_count_ex(uint64_t x, const pc_config *cfg, pc_result *res)
+{
+    pc_result r;
+    uint64_t v = 0;
+    pc_status st = guarded([&] {
+        Knobs K = knobs_from(cfg);
+        if (cfg && (cfg->flags & PC_FLAG_REBUILD_TABLES))
+            drop_tables();
+        pi_one(x, K, cfg ? cfg->alpha : 0.0, &r, &v);
+    });
+    if (st == PC_OK && res)
+        *res = r;
+    return st;
+}
+
+pc_status pc_decompose(uint64_t x, uint64_t y, const pc_config *cfg, pc_result *res)
+{
+    pc_result r;
+    pc_status st = guarded([&] {
+        check_y(x, y);
+        Knobs K = knobs_from(cfg);
+        if (cfg && (cfg->flags & PC_FLAG_REBUILD_TABLES))
+            drop_tables();
+        run_query(x, y, K, &r);
+    });
+    if (st == PC_OK && res)
+        *res = r;
+    return st;
+}
+
+pc_status pc_s2_hard(uint64_t x, uint64_t y, uint64_t a, pc_i128 *out)
+{
+    if (!out)
+        return PC_EINVAL;
+    pc_result r;
+    pc_status st = guarded([&] {
+        check_y(x, y);
+        init_stream();
+        ensure_pi(std::max<uint64_t>(y, 1024) + 1);
+        if (lookup({y})[0] != a)
+            fail(PC_EINVAL, "a must equal pi(y)");
+        run_query(x, y, Knobs{}, &r);
+    });
+    if (st == PC_OK)
+        *out = r.s2_hard;
+    return st;
+}
+
+pc_status pc_p2(uint64_t x, uint64_t y, uint64_t *out)
+{
+    if (!out)
+        return PC_EINVAL;
+    pc_result r;
+    pc_status st = guarded([&] {
+        check_y(x, y);
+        run_query(x, y, Knobs{}, &r);
+        if (r.p2.hi != 0)
+            fail(PC_EINTERNAL, "P2 outside [0, 2^64)");
+    });
+    if (st == PC_OK)
+        *out = r.p2.lo;
+    return st;
+}
+
+pc_status pc_pi_count_batch_ex(const uint64_t *xs, size_t n, const pc_config *cfg,
+                               uint64_t *pi_out)
+{
+    if (n == 0)
+        return PC_OK;
+    if (!xs || !pi_out)
+        return PC_EINVAL;
+    std::vector<uint64_t> out(n);
+    pc_status st = guarded([&] {
+        Knobs K = knobs_from(cfg);
+        double alpha = cfg ? cfg->alpha : 0.0;
+        if (std::isnan(alpha) || alpha < 0)
+            fail(PC_EINVAL, "alpha must be >= 0 (0 = tuned)");
+        for (size_t i = 0; i < n; i++)
+            pi_one(xs[i], K, alpha, nullptr, &out[i]);
+    });
+    if (st == PC_OK)
+        memcpy(pi_out, out.data(), n * 8);
+    return st;
+}
+
+pc_status pc_pi_count_batch(const uint64_t *xs, size_t n, uint64_t *pi_out)
+{
+    return pc_pi_count_batch_ex(xs, n, nullptr, pi_out);
+}
+
+int pc_wheel_c(void) { return kWheelC; }
+
+const char *pc_status_str(pc_status s)
+{
+    switch (s) {
+    case PC_OK:
+        return "ok";
+    case PC_EINVAL:
+        return "invalid argument";
+    case PC_ERANGE:
+        return "out of range";
+    case PC_ENOMEM:
+        return "out of memory";
+    case PC_EDEVICE:
+        return "device error";
+    case PC_EINTERNAL:
+        return "internal error";
+    }
+    return "unknown status";
+}
+
+const char *pc_last_error(void) { return t_err.c_str(); }
+
+void pc_shutdown(void)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    drop_tables();
+    drop_query_bufs();
+    if (g_stream) {
+        (void)hipStreamDestroy(g_stream);
+        g_stream = nullptr;
+    }
+    g_dev_peak = g_dev_bytes;
+}
+
+} // extern "C"

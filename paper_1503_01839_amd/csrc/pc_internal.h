@@ -1,0 +1,133 @@
+// pc_internal.h -- structures shared between the host planner and the kernel
+// launchers of the prime-counting library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pc_device.h"
+
+// One sieve tile: segment `seg` (absolute index), responsible for the
+// per-segment columns [col_lo, col_hi).  Column j < nb stands for the sieving
+// prime b = c + 1 + j; column nb is the state after every sieving prime is
+// crossed (read by the P2 lookups).
+struct pc_tile {
+    uint32_t seg;
+    uint32_t col_lo;
+    uint32_t col_hi;
+    uint32_t pad;
+};
+
+// Shared device tables (read-only during a query).
+struct pc_tables {
+    const uint32_t *primes; // primes[k] = p_k, 1-based (primes[1] = 2)
+    const uint64_t *recip;  // recip[k] = floor((2^64-1)/p_k) for k <= n_recip
+    const uint2 *pitab;     // pi table, see pc_pi_lookup
+    const int32_t *mulpf;   // mu(n)*lpf(n) for n <= ymax; INT32_MAX at n = 1; 0 if mu = 0
+    const uint32_t *pattern; // odd-only pre-sieve bits for p_2..p_c, period pattern_bits (+64 bits)
+    const uint32_t *phitab; // phi(r, c) for r < Q_c
+    uint32_t pattern_bits;  // prod_{2 <= i <= c} p_i
+    uint32_t Qc;            // prod_{1 <= i <= c} p_i
+    uint32_t phiQ;          // phi(Q_c, c)
+    uint32_t pad;
+};
+
+// Per-query scalars.
+struct pc_query {
+    uint64_t x, y, z;
+    uint64_t y1, recip_y1;  // y + 1 and its reciprocal
+    uint64_t sqrtx;         // isqrt(x)
+    uint64_t sqrty;         // isqrt(y): p_b^2 > y  <=>  p_b > sqrty
+    uint64_t Qc, recip_Qc;
+    uint32_t c, a, bmax, nb, ncol;
+    uint32_t kx;            // pi(isqrt(x))
+    const uint64_t *Xb;     // Xb[b] = floor(x / p_b), 1-based, b <= a
+};
+
+enum { PC_MODE_TALLY = 0, PC_MODE_COUNT = 1, PC_MODE_LEAVES = 2 };
+
+struct pc_sieve_args {
+    pc_tables T;
+    pc_query Q;
+    const pc_tile *tiles;
+    uint32_t ntiles;
+    uint32_t pad;
+    uint64_t seg0;          // first segment of the window: row = seg - seg0
+    uint32_t *cnt;          // [row * ncol + col]
+    int32_t *wgt;           // [row * ncol + col]
+    const uint64_t *carry;  // PC_MODE_LEAVES: exclusive carries, same layout
+    pc_s128 *part_hard;     // per tile
+    pc_s128 *part_p2;       // per tile
+    int32_t *err;
+};
+
+// Launchers (each returns hipSuccess or the first HIP error).
+hipError_t pc_launch_base_primes(uint32_t *base, uint32_t *nbase, hipStream_t s);
+hipError_t pc_launch_pitab(uint64_t nentries, const uint32_t *base, uint32_t nbase,
+                           uint32_t *bits, uint32_t *cnts, uint2 *pitab, uint32_t *primes,
+                           uint32_t *scan_tmp, hipStream_t s);
+hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, uint32_t n, hipStream_t s);
+hipError_t pc_launch_mulpf(const uint32_t *primes, uint32_t nsmall, uint64_t ymax,
+                           int32_t *mulpf, hipStream_t s);
+hipError_t pc_launch_wheel(uint32_t c, const uint32_t *primes, uint32_t *pattern,
+                           uint32_t pattern_words, uint32_t *phitab, hipStream_t s);
+hipError_t pc_launch_lookup(const uint2 *pitab, const uint64_t *in, uint32_t n, uint64_t *out,
+                            hipStream_t s);
+hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint32_t a, uint64_t *Xb, hipStream_t s);
+
+// Leaves outside the sieve: S1, trivial and easy special leaves.
+struct pc_leaf_bufs {
+    uint64_t *e_start;   // per b: first easy item (m or prime index)
+    uint64_t *e_count;   // per b: easy items; bit 63 set: candidate (m) mode
+    uint64_t *e_off;     // exclusive prefix of the easy item counts
+    pc_s128 *part;       // partial sums
+    uint64_t *scan_tmp;
+    uint32_t nparts;
+};
+hipError_t pc_launch_s1(const pc_tables &T, const pc_query &Q, pc_s128 *part, uint32_t nblocks,
+                        hipStream_t s);
+hipError_t pc_launch_leaf_setup(const pc_tables &T, const pc_query &Q, uint64_t *e_start,
+                                uint64_t *e_count, pc_s128 *part_trivial, uint64_t *ntrivial,
+                                uint32_t nblocks, hipStream_t s);
+hipError_t pc_launch_strip(const uint64_t *e_count, uint64_t *e_off, uint64_t n, hipStream_t s);
+hipError_t pc_launch_scan_u64(uint64_t *data, uint64_t n, uint64_t *tmp, uint64_t *total,
+                              hipStream_t s);
+hipError_t pc_launch_easy(const pc_tables &T, const pc_query &Q, const uint64_t *e_start,
+                          const uint64_t *e_count, const uint64_t *e_off, const uint64_t *e_total,
+                          pc_s128 *part, uint32_t nblocks, hipStream_t s);
+hipError_t pc_launch_sum128(const pc_s128 *part, uint32_t n, pc_s128 *acc, hipStream_t s);
+hipError_t pc_launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+
+// Sieve and carry scan.
+hipError_t pc_launch_sieve(const pc_sieve_args &A, uint32_t seg_log2, uint32_t wg, int mode,
+                           hipStream_t s);
+struct pc_scan_args {
+    const uint32_t *cnt;
+    const int32_t *wgt;
+    uint64_t *carry_rows;     // PC_MODE_COUNT: exclusive carries per (row, col)
+    const uint64_t *carry_in; // per col, from earlier windows
+    uint64_t *carry_out;      // per col
+    uint64_t *status;         // [nchunk * ncol] look-back words, zeroed
+    uint32_t *ticket;         // zeroed
+    pc_s128 *part_hard;       // per workgroup
+    pc_s128 *part_p2;
+    int32_t *err;
+    uint64_t nrows;
+    uint32_t ncol, nb;
+    uint32_t rows_per_chunk;
+    uint32_t nchunk, ncb;
+};
+hipError_t pc_launch_scan(const pc_scan_args &A, int mode, hipStream_t s);
+
+// Final combination of the partial sums into pi(x) and its parts.
+struct pc_sums {
+    pc_s128 s1, s2t, s2e, hard_local, hard_dot, p2_local, p2_dot;
+    uint64_t n_trivial, pad;
+};
+struct pc_final {
+    pc_s128 s1, s2t, s2e, s2h, p2, phi;
+    uint64_t pi;
+    uint64_t ok;
+};
+hipError_t pc_launch_combine(const pc_sums *sums, const pc_query &Q, uint64_t kp2,
+                             pc_final *out, hipStream_t s);

@@ -1,0 +1,406 @@
+// pc_tables.hip -- device tables of the prime-counting library, all built on
+// the GPU:
+//   * primes p_k (1-based) and an odd-only pi table up to a limit P < 2^32
+//     (Section 2.1 of the paper keeps pi(y) and the primes p_b; here pi is a
+//     bitmap with a running count per 32 odd numbers, 8 bytes per 64 integers);
+//   * 64-bit reciprocals of the primes, for exact division by invariant
+//     divisors;
+//   * mu(n)*lpf(n) for n <= y (Section 2.2: "p_min(y) mu(y)");
+//   * the wheel of size c (Section 4): the odd-only pre-sieve pattern of
+//     p_2..p_c and phi(r, c) for r below the primorial Q_c.
+#include "pc_block.h"
+#include "pc_internal.h"
+
+// ---------------------------------------------------------------------------
+// Odd primes below 2^16, by one workgroup (enough to sieve up to 2^32).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_base_primes(uint32_t *base, uint32_t *nbase)
+{
+    __shared__ uint32_t bits[1024]; // bit j of word w <-> 64w + 2j + 1
+    __shared__ uint32_t scr[16];
+    const uint32_t t = threadIdx.x;
+    bits[t] = t == 0 ? 0xFFFFFFFEu : 0xFFFFFFFFu; // 1 is not prime
+    __syncthreads();
+    if (t < 127) { // odd q in [3, 255]; composite q only repeats its factors' work
+        uint32_t q = 2 * t + 3;
+        for (uint32_t n = q * q; n < 65536u; n += 2 * q) {
+            uint32_t i = n >> 1;
+            atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
+        }
+    }
+    __syncthreads();
+    uint32_t w = bits[t], total;
+    uint32_t off = pc_block_excl_scan<1024>((uint32_t)__builtin_popcount(w), scr, &total);
+    while (w) {
+        uint32_t j = __builtin_ctz(w);
+        w &= w - 1;
+        base[off++] = 64 * t + 2 * j + 1;
+    }
+    if (t == 0)
+        *nbase = total;
+}
+
+// ---------------------------------------------------------------------------
+// Segmented odd-only sieve of Eratosthenes over entries [0, nent): entry e
+// covers the odd numbers 64e+1 .. 64e+63.  Writes the prime bits into
+// tab[e].x and their popcount into cnt[e].
+// ---------------------------------------------------------------------------
+#define PT_WORDS 4096 // entries per workgroup: 131072 odd numbers
+#define PT_T 1024
+
+__global__ __launch_bounds__(PT_T) void k_sieve_pitab(uint64_t nent, const uint32_t *base,
+                                                    uint32_t nbase, uint2 *tab, uint32_t *cnt)
+{
+    __shared__ uint32_t bits[PT_WORDS];
+    const uint32_t t = threadIdx.x;
+    const uint64_t e0 = (uint64_t)blockIdx.x * PT_WORDS;
+    for (uint32_t i = t; i < PT_WORDS; i += PT_T)
+        bits[i] = 0xFFFFFFFFu;
+    __syncthreads();
+    const uint64_t nlo = 64 * e0;                   // first integer covered
+    const uint64_t nhi = 64 * (e0 + PT_WORDS) - 1;  // last integer covered
+    const uint32_t NBIT = PT_WORDS * 32;
+    // small primes: all threads share the multiples of one prime at a time
+    uint32_t k = 0;
+    for (; k < nbase; k++) {
+        uint64_t q = base[k];
+        if (q >= 4 * PT_T)
+            break;
+        if (q * q > nhi)
+            break;
+        uint64_t m = (nlo + q - 1) / q * q;
+        if ((m & 1) == 0)
+            m += q;
+        if (m < q * q)
+            m = q * q;
+        uint32_t i0 = (uint32_t)(((m - 1) >> 1) - (nlo >> 1));
+        for (uint32_t i = i0 + t * (uint32_t)q; i < NBIT; i += PT_T * (uint32_t)q)
+            atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
+    }
+    // large primes: one lane per prime
+    for (uint32_t j = k + t; j < nbase; j += PT_T) {
+        uint64_t q = base[j];
+        if (q * q > nhi)
+            continue;
+        uint64_t m = (nlo + q - 1) / q * q;
+        if ((m & 1) == 0)
+            m += q;
+        if (m < q * q)
+            m = q * q;
+        for (uint64_t i = ((m - 1) >> 1) - (nlo >> 1); i < NBIT; i += q)
+            atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
+    }
+    __syncthreads();
+    if (e0 == 0 && t == 0)
+        bits[0] &= ~1u; // 1 is not prime
+    __syncthreads();
+    for (uint32_t i = t; i < PT_WORDS; i += PT_T) {
+        uint64_t e = e0 + i;
+        if (e < nent) {
+            tab[e].x = bits[i];
+            cnt[e] = (uint32_t)__builtin_popcount(bits[i]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scans (reduce, scan of block sums, down-sweep).
+// ---------------------------------------------------------------------------
+#define SC_T 256
+#define SC_ITEMS 16
+#define SC_TILE (SC_T * SC_ITEMS)
+
+template <typename T>
+__global__ __launch_bounds__(SC_T) void k_scan_reduce(const T *in, uint64_t n, T *bsum)
+{
+    __shared__ T scr[SC_T / 64];
+    uint64_t base = (uint64_t)blockIdx.x * SC_TILE;
+    T s = 0;
+    for (uint32_t i = 0; i < SC_ITEMS; i++) {
+        uint64_t j = base + (uint64_t)i * SC_T + threadIdx.x;
+        if (j < n)
+            s += in[j];
+    }
+    s = pc_block_sum<SC_T>(s, scr);
+    if (threadIdx.x == 0)
+        bsum[blockIdx.x] = s;
+}
+
+// one workgroup scans the block sums in place; *total receives the grand total
+template <typename T>
+__global__ __launch_bounds__(SC_T) void k_scan_top(T *bsum, uint64_t nb, T *total)
+{
+    __shared__ T scr[SC_T / 64];
+    T run = 0;
+    for (uint64_t c0 = 0; c0 < nb; c0 += SC_T) {
+        uint64_t j = c0 + threadIdx.x;
+        T v = j < nb ? bsum[j] : 0, tot;
+        T ex = pc_block_excl_scan<SC_T>(v, scr, &tot);
+        if (j < nb)
+            bsum[j] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0 && total)
+        *total = run;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SC_T) void k_scan_down(T *data, uint64_t n, const T *bsum)
+{
+    __shared__ T scr[SC_T / 64];
+    uint64_t base = (uint64_t)blockIdx.x * SC_TILE + (uint64_t)threadIdx.x * SC_ITEMS;
+    T v[SC_ITEMS];
+    T s = 0;
+    for (uint32_t i = 0; i < SC_ITEMS; i++) {
+        uint64_t j = base + i;
+        v[i] = j < n ? data[j] : 0;
+        s += v[i];
+    }
+    T tot;
+    T ex = pc_block_excl_scan<SC_T>(s, scr, &tot) + bsum[blockIdx.x];
+    for (uint32_t i = 0; i < SC_ITEMS; i++) {
+        uint64_t j = base + i;
+        if (j < n)
+            data[j] = ex;
+        ex += v[i];
+    }
+}
+
+template <typename T>
+static hipError_t scan_excl(T *data, uint64_t n, T *tmp, T *total, hipStream_t s)
+{
+    uint64_t nb = (n + SC_TILE - 1) / SC_TILE;
+    if (nb == 0)
+        nb = 1;
+    k_scan_reduce<T><<<(uint32_t)nb, SC_T, 0, s>>>(data, n, tmp);
+    k_scan_top<T><<<1, SC_T, 0, s>>>(tmp, nb, total);
+    k_scan_down<T><<<(uint32_t)nb, SC_T, 0, s>>>(data, n, tmp);
+    return hipGetLastError();
+}
+
+hipError_t pc_launch_scan_u64(uint64_t *data, uint64_t n, uint64_t *tmp, uint64_t *total,
+                              hipStream_t s)
+{
+    return scan_excl<uint64_t>(data, n, tmp, total, s);
+}
+
+// tab[e].y = number of odd primes in entries < e; primes[] filled in order.
+__global__ void k_pitab_pack(uint64_t nent, uint2 *tab, const uint32_t *pre, uint32_t *primes)
+{
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) {
+        primes[0] = 0;
+        primes[1] = 2;
+    }
+    if (e >= nent)
+        return;
+    uint32_t off = pre[e];
+    uint32_t w = tab[e].x;
+    tab[e].y = off;
+    uint32_t k = off + 2; // odd prime of rank off is p_{off+2}
+    while (w) {
+        uint32_t j = __builtin_ctz(w);
+        w &= w - 1;
+        primes[k++] = (uint32_t)(64 * e + 2 * j + 1);
+    }
+}
+
+hipError_t pc_launch_pitab(uint64_t nent, const uint32_t *base, uint32_t nbase, uint32_t *bits,
+                           uint32_t *cnts, uint2 *pitab, uint32_t *primes, uint32_t *scan_tmp,
+                           hipStream_t s)
+{
+    (void)bits;
+    uint32_t nblk = (uint32_t)((nent + PT_WORDS - 1) / PT_WORDS);
+    k_sieve_pitab<<<nblk, PT_T, 0, s>>>(nent, base, nbase, pitab, cnts);
+    hipError_t e = scan_excl<uint32_t>(cnts, nent, scan_tmp, (uint32_t *)nullptr, s);
+    if (e != hipSuccess)
+        return e;
+    k_pitab_pack<<<(uint32_t)((nent + 255) / 256), 256, 0, s>>>(nent, pitab, cnts, primes);
+    return hipGetLastError();
+}
+
+hipError_t pc_launch_base_primes(uint32_t *base, uint32_t *nbase, hipStream_t s)
+{
+    k_base_primes<<<1, 1024, 0, s>>>(base, nbase);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reciprocals recip[k] = floor((2^64-1) / p_k), k in [1, n].
+// ---------------------------------------------------------------------------
+__global__ void k_recip(const uint32_t *primes, uint64_t *recip, uint32_t n)
+{
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0)
+        recip[0] = 0;
+    if (k >= 1 && k <= n)
+        recip[k] = pc_recip(primes[k]);
+}
+
+hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, uint32_t n, hipStream_t s)
+{
+    k_recip<<<(n + 256) / 256, 256, 0, s>>>(primes, recip, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// mu(n)*lpf(n) for n <= ymax by a segmented factor sieve.  Each workgroup owns
+// 4096 consecutive n; the primes <= sqrt(ymax) are applied in increasing order
+// (one barrier each) so the first prime to touch n is its least prime factor.
+// A cofactor left above 1 is one prime > sqrt(ymax).
+// ---------------------------------------------------------------------------
+#define MF_N 4096
+#define MF_T 256
+
+__global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t nsmall,
+                                               uint64_t ymax, int32_t *out)
+{
+    __shared__ uint32_t lpf[MF_N];
+    __shared__ uint32_t prod[MF_N];
+    __shared__ int32_t mu[MF_N];
+    const uint32_t t = threadIdx.x;
+    const uint32_t n0 = blockIdx.x * MF_N;
+    for (uint32_t i = t; i < MF_N; i += MF_T) {
+        lpf[i] = 0;
+        prod[i] = 1;
+        mu[i] = 1;
+    }
+    __syncthreads();
+    for (uint32_t k = 1; k <= nsmall; k++) {
+        uint32_t p = primes[k];
+        uint32_t first = (n0 + p - 1) / p * p;
+        for (uint32_t m = first + t * p; m < n0 + MF_N; m += MF_T * p) {
+            uint32_t i = m - n0;
+            if (lpf[i] == 0)
+                lpf[i] = p;
+            prod[i] *= p;
+            mu[i] = -mu[i];
+        }
+        uint64_t pp = (uint64_t)p * p;
+        if (pp < (uint64_t)n0 + MF_N) {
+            uint64_t f2 = ((uint64_t)n0 + pp - 1) / pp * pp;
+            for (uint64_t m = f2 + (uint64_t)t * pp; m < (uint64_t)n0 + MF_N; m += MF_T * pp)
+                mu[m - n0] = 0;
+        }
+        __syncthreads();
+    }
+    for (uint32_t i = t; i < MF_N; i += MF_T) {
+        uint64_t n = (uint64_t)n0 + i;
+        if (n > ymax)
+            continue;
+        int32_t v;
+        if (n == 0) {
+            v = 0;
+        } else if (n == 1) {
+            v = 0x7FFFFFFF;
+        } else {
+            int32_t m = mu[i];
+            uint32_t l = lpf[i];
+            if (m != 0 && prod[i] < n) {
+                uint32_t big = (uint32_t)n / prod[i];
+                m = -m;
+                if (l == 0)
+                    l = big;
+            }
+            v = m * (int32_t)l;
+        }
+        out[n] = v;
+    }
+}
+
+hipError_t pc_launch_mulpf(const uint32_t *primes, uint32_t nsmall, uint64_t ymax, int32_t *mulpf,
+                           hipStream_t s)
+{
+    uint32_t nblk = (uint32_t)(ymax / MF_N + 1);
+    k_mulpf<<<nblk, MF_T, 0, s>>>(primes, nsmall, ymax, mulpf);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Wheel of size c: pattern bit j <-> 2j+1 coprime to p_2..p_c, j < period+64;
+// phitab[r] = phi(r, c) for 0 <= r < Q_c.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_wheel(uint32_t c, const uint32_t *primes,
+                                              uint32_t *pattern, uint32_t pattern_words,
+                                              uint32_t *phitab)
+{
+    __shared__ uint32_t scr[16];
+    const uint32_t t = threadIdx.x;
+    uint32_t P[8];
+    uint32_t Q = 1;
+    for (uint32_t i = 1; i <= c; i++) {
+        P[i - 1] = primes[i];
+        Q *= primes[i];
+    }
+    for (uint32_t w = t; w < pattern_words; w += 1024) {
+        uint32_t word = 0;
+        for (uint32_t j = 0; j < 32; j++) {
+            uint32_t n = 2 * (32 * w + j) + 1;
+            bool ok = true;
+            for (uint32_t i = 1; i < c; i++)
+                ok = ok && (n % P[i] != 0);
+            word |= (ok ? 1u : 0u) << j;
+        }
+        pattern[w] = word;
+    }
+    // phi(r, c): each thread a contiguous chunk of r
+    uint32_t per = (Q + 1023) / 1024;
+    uint32_t r0 = t * per, r1 = min(Q, r0 + per);
+    uint32_t local = 0;
+    for (uint32_t r = max(r0, 1u); r < r1; r++) {
+        bool ok = true;
+        for (uint32_t i = 0; i < c; i++)
+            ok = ok && (r % P[i] != 0);
+        local += ok;
+    }
+    uint32_t total;
+    uint32_t run = pc_block_excl_scan<1024>(local, scr, &total);
+    for (uint32_t r = r0; r < r1; r++) {
+        if (r >= 1) {
+            bool ok = true;
+            for (uint32_t i = 0; i < c; i++)
+                ok = ok && (r % P[i] != 0);
+            run += ok;
+        }
+        phitab[r] = run;
+    }
+}
+
+hipError_t pc_launch_wheel(uint32_t c, const uint32_t *primes, uint32_t *pattern,
+                           uint32_t pattern_words, uint32_t *phitab, hipStream_t s)
+{
+    k_wheel<<<1, 1024, 0, s>>>(c, primes, pattern, pattern_words, phitab);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers: pi at a few points; X_b = floor(x / p_b).
+// ---------------------------------------------------------------------------
+__global__ void k_lookup(const uint2 *pitab, const uint64_t *in, uint32_t n, uint64_t *out)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = pc_pi_lookup(pitab, in[i]);
+}
+
+hipError_t pc_launch_lookup(const uint2 *pitab, const uint64_t *in, uint32_t n, uint64_t *out,
+                            hipStream_t s)
+{
+    k_lookup<<<(n + 63) / 64, 64, 0, s>>>(pitab, in, n, out);
+    return hipGetLastError();
+}
+
+__global__ void k_xb(pc_tables T, uint64_t x, uint32_t a, uint64_t *Xb)
+{
+    uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0)
+        Xb[0] = x;
+    if (b >= 1 && b <= a)
+        Xb[b] = pc_div(x, T.primes[b], T.recip[b]);
+}
+
+hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint32_t a, uint64_t *Xb, hipStream_t s)
+{
+    k_xb<<<(a + 256) / 256, 256, 0, s>>>(T, x, a, Xb);
+    return hipGetLastError();
+}

@@ -1,0 +1,136 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle and the
+paper's tables.  Every result is an integer, so every comparison is exact.
+"""
+import json
+import os
+import random
+import sys
+
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_decomp.json")
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import paper_1503_01839_amd as pc
+    return pc
+
+
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)["records"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_small_x_table(pc):
+    # x < 2^20 is answered from the device pi table
+    say("case: small x table")
+    rng = random.Random(3)
+    xs = list(range(0, 300)) + [rng.randrange(0, 1 << 20) for _ in range(200)] + [(1 << 20) - 1]
+    for x in xs:
+        assert pc.pi_count(x) == O.pi_brute(x), x
+
+
+def test_decompose_small_vs_oracle(pc):
+    # tiny x through the sieve path, every component against the oracle
+    rng = random.Random(5)
+    cases = [(8, 2), (27, 3), (100, 4), (100, 10), (1000, 10), (1000, 31), (10**4, 21),
+             (10**4, 100), (10**6, 100), (10**6, 200), (10**6, 1000), (30030, 31)]
+    for _ in range(30):
+        x = rng.randrange(64, 10**7)
+        lo, hi = O.icbrt(x), O.isqrt(x)
+        cases.append((x, rng.randrange(lo, hi + 1)))
+    for x, y in cases:
+        say("case: decompose", x, y)
+        r = pc.decompose(x, y)
+        o = O.decompose(x, y, 6, hard=O.HARD_SIEVE)
+        assert (r.a, r.c, r.bmax) == (o.a, o.c, o.bmax), (x, y)
+        assert r.s1 == o.s1, (x, y, "S1")
+        assert r.s2_trivial == o.s2t, (x, y, "S2t")
+        assert r.s2_easy == o.s2e, (x, y, "S2e")
+        assert r.s2_hard == o.s2h, (x, y, "S2h")
+        assert r.p2 == o.p2, (x, y, "P2")
+        assert r.pi == O.pi_brute(x), (x, y)
+
+
+def test_golden_records(pc):
+    for rec in golden():
+        if rec["x"] > 10**13:
+            continue
+        say("case: golden", rec["x"], rec["y"])
+        r = pc.decompose(rec["x"], rec["y"])
+        assert (r.a, r.bmax) == (rec["a"], rec["bmax"])
+        assert (r.s1, r.s2_trivial, r.s2_easy, r.s2_hard, r.p2) == \
+            (rec["s1"], rec["s2t"], rec["s2e"], rec["s2h"], rec["p2"]), rec["x"]
+        assert r.pi == rec["pi"]
+        assert r.n_trivial == rec["n_trivial"]
+
+
+@pytest.mark.parametrize("seg", [32, 64, 128])
+@pytest.mark.parametrize("wg", [512, 1024])
+def test_config_invariance(pc, seg, wg):
+    # the sieve geometry never changes a value (the paper's own check, Section 5)
+    for x, y in [(10**11, 4641), (10**12, 20000), (10**10 + 12345, 4000)]:
+        say("case: invariance", x, y, seg, wg)
+        o = O.decompose(x, y, 6, hard=O.HARD_SIEVE)
+        for flags in (0, pc.FLAG_NO_BATCH_LARGE, pc.FLAG_TWO_PASS):
+            r = pc.decompose(x, y, segment_kib=seg, wg_size=wg, flags=flags)
+            assert (r.s2_hard, r.p2, r.pi) == (o.s2h, o.p2, o.pi), (x, y, seg, wg, flags)
+
+
+def test_windows(pc):
+    # a tiny carry budget forces many windows; carries must chain across them
+    x, y = 10**12, 10**4
+    o = O.decompose(x, y, 6, hard=O.HARD_SIEVE)
+    for budget in (1 << 16, 1 << 20, 3 << 20):
+        say("case: windows", budget)
+        r = pc.decompose(x, y, carry_budget=budget)
+        assert r.windows > 1
+        assert (r.s2_hard, r.p2) == (o.s2h, o.p2), budget
+
+
+def test_paper_powers_of_ten(pc, paper_pow10):
+    for n in range(1, 16):
+        say("case: pi(10^%d)" % n)
+        assert pc.pi_count(10**n) == paper_pow10[n], n
+
+
+def test_paper_powers_of_two(pc, paper_pow2):
+    for m in range(1, 51):
+        say("case: pi(2^%d)" % m)
+        assert pc.pi_count(2**m) == paper_pow2[m], m
+
+
+def test_alpha_invariance(pc, paper_pow10):
+    for n in (12, 13, 14):
+        for alpha in (1, 2, 4, 8, 16):
+            say("case: alpha", n, alpha)
+            assert pc.pi_count(10**n, alpha) == paper_pow10[n], (n, alpha)
+
+
+def test_random_vs_oracle(pc):
+    rng = random.Random(1839)
+    for _ in range(40):
+        x = rng.randrange(1 << 20, 2 * 10**9)
+        say("case: random", x)
+        assert pc.pi_count(x) == O.pi_meissel(x), x
+
+
+def test_p2_and_s2_hard_entry_points(pc):
+    x, y = 10**11, 4641
+    o = O.decompose(x, y, 6, hard=O.HARD_SIEVE)
+    assert pc.s2_hard(x, y, o.a) == o.s2h
+    assert pc.p2(x, y) == o.p2
+    with pytest.raises(pc.PicountError):
+        pc.s2_hard(x, y, o.a + 1)
+    with pytest.raises(pc.PicountError):
+        pc.p2(x, 10)  # y below icbrt(x)
