@@ -1,0 +1,144 @@
+#!/usr/bin/env python3
+"""Benchmark: pi(1e18) on one MI355X through the C ABI.
+
+A step is one complete pi(x) evaluation at x = 1e18: device tables (primes and
+pi up to sqrt x, mu*lpf up to y, wheel), S1, trivial and easy leaves, the
+segmented sieve with hard leaves and P2, the carry scan and the final
+combination.  The input is the single integer x, resident before timing.
+
+Prints one JSON line.  `value` is special leaves (trivial + easy + hard, the
+whole S2 tree at the chosen alpha) per second of pi(1e18) wall time; the
+alpha-independent pi(x) wall time is `ms_per_step`.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "S2 special leaves/s + π(x) wall time at x=1e18; batched queries/s, p50/p99"
+X = 10**18
+PI_1E18 = 24739954287740860  # Table 1 of the paper
+
+# MI355X: 256 CUs at 2.4 GHz; LDS 64 banks x 4 bytes per CU per clock.
+CUS, CLOCK_HZ, LDS_DWORDS_PER_CLK = 256, 2.4e9, 64
+LDS_PEAK_OPS = CUS * CLOCK_HZ * LDS_DWORDS_PER_CLK  # 32-bit LDS read-modify-writes per second
+
+# Bounded oracle sample of the same workload (alpha = 8): the special leaves
+# with 1000 <= b < 2500, hard ones with u <= 1e7.
+CPU_SAMPLE = dict(y=8000000, c=6, b_lo=1000, b_hi=2500, u_max=10**7)
+
+
+def sync():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+
+
+def cpu_baseline():
+    import oracle
+    s = CPU_SAMPLE
+    t0 = time.perf_counter()
+    d = oracle.leaf_sample(X, s["y"], s["c"], s["b_lo"], s["b_hi"], s["u_max"])
+    dt = time.perf_counter() - t0
+    leaves = d.n_trivial + d.n_easy + d.n_hard
+    return {"value": leaves / dt, "unit": "special leaves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"pi(1e18), alpha=8 (y={s['y']}): special leaves with "
+                       f"{s['b_lo']} <= b < {s['b_hi']}, hard leaves only for u <= {s['u_max']} "
+                       f"({d.n_easy} easy + {d.n_hard} hard + {d.n_trivial} trivial) "
+                       f"in {dt:.2f} s, single-threaded C oracle")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--alpha", type=float, default=0.0, help="0 = library's tuned value")
+    ap.add_argument("--segment-kib", type=int, default=0)
+    ap.add_argument("--wg", type=int, default=0)
+    ap.add_argument("--keep-tables", action="store_true",
+                    help="reuse device tables across steps (default: rebuild every step)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(pi(x) shards by segment range, see DESIGN.md); rerun with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1503_01839_amd as pc
+
+    flags = 0 if args.keep_tables else pc.FLAG_REBUILD_TABLES
+    cfg = dict(alpha=args.alpha, segment_kib=args.segment_kib, wg_size=args.wg, flags=flags)
+    for i in range(args.warmup):
+        r = pc.pi_count_ex(X, **cfg)
+        print(f"warmup {i}: {r.ms_total:.1f} ms", file=sys.stderr, flush=True)
+    sync()
+    results = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = pc.pi_count_ex(X, **cfg)
+        results.append(r)
+        print(f"step {i}: {r.ms_total:.1f} ms (tables {r.ms_tables:.1f}, leaves {r.ms_leaves:.1f}, "
+              f"sieve {r.ms_sieve:.1f})", file=sys.stderr, flush=True)
+    sync()
+    wall = time.perf_counter() - t0
+    r = results[-1]
+    ok = all(q.pi == PI_1E18 for q in results)
+    ms_step = 1e3 * wall / args.steps
+    leaves = r.n_trivial + r.n_easy + r.n_hard
+    value = leaves / (ms_step / 1e3)
+
+    # roofline of the dominant kernel (the sieve): LDS bit-crossings
+    k_ms = sum(q.ms_k_sieve for q in results) / len(results)
+    launches = r.sieve_launches
+    avg_launch_ms = k_ms / max(launches, 1)
+    crossings_per_launch = r.crossings / max(launches, 1)
+    achieved = crossings_per_launch / (avg_launch_ms / 1e3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": LDS_PEAK_OPS / 1e12,
+            "unit": "T LDS-RMW/s", "frac": achieved / LDS_PEAK_OPS, "traffic": None,
+            "kernel": "k_sieve", "launches": launches, "avg_launch_ms": avg_launch_ms,
+            "work_per_launch": crossings_per_launch,
+            "work": "odd multiples of p_{c+1}..p_bmax crossed in LDS (one 32-bit RMW each)"}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "special leaves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64/i128",
+        "data": "synthetic",
+        "config": {"workload": "pi(x) single query, x = 1e18 (Table 1 row 10^18)", "x": X,
+                   "alpha": r.y / 1e6, "y": r.y, "a": r.a, "c": r.c, "z": r.z, "bmax": r.bmax,
+                   "segment_bits": r.segment_bits, "segments": r.segments,
+                   "windows": r.windows, "tables_rebuilt_each_step": not args.keep_tables},
+        "pi": r.pi, "pi_matches_table1": ok,
+        "pi_wall_ms": ms_step,
+        "leaves": {"trivial": r.n_trivial, "easy": r.n_easy, "hard": r.n_hard, "s1_terms": r.n_s1,
+                   "p2_terms": r.n_p2},
+        "hard_leaves_per_s": r.n_hard / (ms_step / 1e3),
+        "easy_hard_leaves_per_s": (r.n_easy + r.n_hard) / (ms_step / 1e3),
+        "sieve_bits_per_s": (r.segments * r.segment_bits) / (ms_step / 1e3),
+        "crossings_per_s": r.crossings / (ms_step / 1e3),
+        "phase_ms": {"tables": r.ms_tables, "leaves": r.ms_leaves, "sieve": r.ms_sieve,
+                     "k_sieve": r.ms_k_sieve, "k_scan": r.ms_k_scan, "k_easy": r.ms_k_easy,
+                     "k_s1": r.ms_k_s1},
+        "device_bytes": r.device_bytes,
+        "roofline": roof,
+        "paper_context": "Table 3: pi(1e18) took 108 node-s (v2015.01.30) on 2x Xeon E5-2670 "
+                         "(16 cores); not a target",
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

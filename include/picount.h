@@ -58,16 +58,19 @@ typedef struct {
 /* Tuning knobs.  Zero in any field means "library default". */
 typedef struct {
     double alpha;          /* y = alpha * icbrt(x), clamped to [icbrt x, isqrt x]; 0 = tuned */
-    uint32_t segment_kib;  /* LDS bitmap per sieve segment: 32, 64 or 128                  */
-    uint32_t wg_size;      /* sieve workgroup size: 256, 512 or 1024                        */
+    uint32_t segment_kib;  /* LDS bitmap per sieve segment: 32 or 64                       */
+    uint32_t wg_size;      /* sieve workgroup: 256|512 (32 KiB segments), 512|1024 (64)   */
     uint32_t tile_leaves;  /* hard-leaf budget per sieve tile (hot-segment splitting); 0 = auto, 0xFFFFFFFF = off */
     uint32_t flags;        /* PC_FLAG_* below */
     uint64_t carry_budget; /* bytes for per-(segment, prime) counts per window; 0 = auto  */
+    uint32_t small_span;   /* one-wavefront segments cover [0, small_span * y); 0 = auto   */
+    uint32_t small_kib;    /* size of those segments: 4 or 8 KiB; 0 = auto                  */
 } pc_config;
 
 #define PC_FLAG_TWO_PASS 1u      /* count pass, carry scan, then leaf pass (else one tally pass) */
 #define PC_FLAG_NO_BATCH_LARGE 2u /* cross large primes one at a time (no batched crossing)     */
 #define PC_FLAG_REBUILD_TABLES 4u /* drop cached tables and rebuild them inside this call       */
+#define PC_FLAG_NO_SMALL_SEGMENTS 8u /* sieve the leaf-dense low end with workgroup segments too  */
 
 /* Everything one pi(x) evaluation produced, for tests and measurement. */
 typedef struct {
@@ -76,9 +79,13 @@ typedef struct {
     pc_i128 s1, s2_trivial, s2_easy, s2_hard, p2, phi; /* phi = S1 + S2          */
     uint64_t n_s1, n_trivial, n_easy, n_hard, n_p2;    /* term / leaf counts       */
     uint64_t segments, tiles, windows;
-    uint64_t segment_bits;          /* bits (odd integers) per segment              */
-    uint64_t device_bytes;          /* peak device bytes held during the call       */
-    double ms_total, ms_tables, ms_s1, ms_easy, ms_sieve, ms_scan;
+    uint64_t segment_bits;          /* bits (odd integers) per workgroup segment     */
+    uint64_t small_segments;        /* leading one-wavefront segments (of the total) */
+    uint64_t crossings;             /* odd multiples of p_{c+1}..p_bmax below the sieve end */
+    uint64_t device_bytes;          /* peak device bytes held by the library        */
+    uint32_t sieve_launches, scan_launches;
+    double ms_total, ms_tables, ms_leaves, ms_sieve;   /* host wall clock per phase   */
+    double ms_k_sieve, ms_k_scan, ms_k_easy, ms_k_s1;  /* kernel time, HIP events     */
 } pc_result;
 
 /* ---------------------------------------------------------------------- */

@@ -72,6 +72,8 @@ def lib():
         L.or_decompose.argtypes = [u64, u64, u64, C.c_int, C.c_int, C.c_int, u64,
                                    C.POINTER(_Decomp), P, P, P, P, u64]
         L.or_decompose.restype = C.c_int
+        L.or_leaf_sample.argtypes = [u64, u64, u64, u64, u64, u64, C.POINTER(_Decomp)]
+        L.or_leaf_sample.restype = C.c_int
         L.or_pi_meissel.argtypes = [u64, u64, u64]
         L.or_pi_meissel.restype = u64
         _lib = L
@@ -186,3 +188,16 @@ def pi_meissel(x: int, y: int | None = None, c: int = 6) -> int:
     if y is None:
         y = icbrt(x)
     return lib().or_pi_meissel(x, y, c)
+
+
+def leaf_sample(x: int, y: int, c: int, b_lo: int, b_hi: int, u_max: int) -> Decomp:
+    """The special leaves with b_lo <= b < b_hi (hard ones only up to u_max):
+    a bounded slice of one (x, y, c) for timing the oracle on large x."""
+    D = _Decomp()
+    rc = lib().or_leaf_sample(x, y, c, b_lo, b_hi, u_max, C.byref(D))
+    if rc != 0:
+        raise ValueError(f"or_leaf_sample failed with code {rc}")
+    vals = {f: getattr(D, f) for f, _ in _Decomp._fields_}
+    for k in ("s1", "s2t", "s2e", "s2h", "p2", "phi"):
+        vals[k] = vals[k].value()
+    return Decomp(**vals)

@@ -483,6 +483,7 @@ typedef struct {
     uint64_t nt, ne, nh;
     leaf_vec hard; /* filled only when collecting */
     i128 *per_b_t, *per_b_e; /* optional, indexed by b */
+    uint64_t u_max;          /* hard leaves with u > u_max are skipped (sampling only) */
 } leaves_acc;
 
 /* One special leaf (b, m): -mu(m) phi(x/(m p_b), b-1). */
@@ -504,6 +505,8 @@ static void one_leaf(const ctx_t *C, leaves_acc *A, uint64_t b, uint64_t m,
         if (A->per_b_e)
             A->per_b_e[b] += w * v;
     } else { /* hard */
+        if (u > A->u_max)
+            return;
         A->nh++;
         if (collect)
             leaf_push(&A->hard, u, (uint32_t)b, w);
@@ -515,10 +518,15 @@ static void one_leaf(const ctx_t *C, leaves_acc *A, uint64_t b, uint64_t m,
  * p_b^2 > y every member of M_b is prime (m <= y < p_b^2 and lpf(m) > p_b), so
  * the primes in (max(p_b, y/p_b), y] are walked; the trailing run of them with
  * u < p_b is trivial and is counted, not walked. */
-static void special_leaves(const ctx_t *C, leaves_acc *A, int collect)
+static void special_leaves(const ctx_t *C, leaves_acc *A, int collect, uint64_t b_lo,
+                           uint64_t b_hi)
 {
     uint64_t x = C->x, y = C->y;
-    for (uint64_t b = C->c + 1; b < C->a; b++) {
+    if (b_lo < C->c + 1)
+        b_lo = C->c + 1;
+    if (b_hi > C->a)
+        b_hi = C->a;
+    for (uint64_t b = b_lo; b < b_hi; b++) {
         uint64_t p = C->p[b];
         uint64_t mlo = y / p + 1;
         if ((u128)p * p <= y) {
@@ -585,9 +593,8 @@ static uint64_t fw_sum(const fenwick *F, uint64_t i) /* sum of positions [0, i] 
 /* Sum of -mu(m) phi(u, b-1) over the hard leaves.  per_b[b] (optional)
  * receives the per-prime sums, per_seg[s] (optional) the per-segment sums. */
 static i128 hard_direct(const ctx_t *C, leaf_vec *L, uint64_t seglen, uint64_t bmax,
-                        i128 *per_b, i128 *per_seg, uint64_t nseg_cap)
+                        uint64_t z, i128 *per_b, i128 *per_seg, uint64_t nseg_cap)
 {
-    uint64_t z = C->x / C->y;
     qsort(L->v, L->n, sizeof *L->v, leaf_cmp);
     /* leaves are now ascending in u; within one segment they are regrouped by b */
     unsigned char *flag = malloc(seglen);
@@ -721,8 +728,9 @@ int or_decompose(uint64_t x, uint64_t y, uint64_t c, int hard_route, int want_ph
     memset(&A, 0, sizeof A);
     A.per_b_t = pbt;
     A.per_b_e = pbe;
+    A.u_max = UINT64_MAX;
     int collect = hard_route == 1 || hard_route == 3;
-    special_leaves(&C, &A, collect);
+    special_leaves(&C, &A, collect, C.c + 1, C.a);
     out->s2t = pack(A.s2t);
     out->s2e = pack(A.s2e);
     out->n_trivial = A.nt;
@@ -734,7 +742,7 @@ int or_decompose(uint64_t x, uint64_t y, uint64_t c, int hard_route, int want_ph
         i128 *pbh = per_b_h ? calloc(nb, sizeof(i128)) : NULL;
         i128 *psg = per_seg ? calloc(nseg_cap, sizeof(i128)) : NULL;
         hard_direct_unplaced = 0;
-        s2h = hard_direct(&C, &A.hard, seglen, out->bmax, pbh, psg, nseg_cap);
+        s2h = hard_direct(&C, &A.hard, seglen, out->bmax, z, pbh, psg, nseg_cap);
         if (hard_direct_unplaced) {
             free(pbh);
             free(psg);
@@ -796,4 +804,44 @@ uint64_t or_pi_meissel(uint64_t x, uint64_t y, uint64_t c)
     i128 phi = ((i128)D.phi.hi << 64) | D.phi.lo;
     i128 p2 = ((i128)D.p2.hi << 64) | D.p2.lo;
     return (uint64_t)(phi + (i128)D.a - 1 - p2);
+}
+
+/* A bounded slice of the special leaves of one (x, y, c): the leaves with
+ * b_lo <= b < b_hi, and of the hard ones only those with u <= u_max (their
+ * phi from the direct sieve of [1, u_max]).  Used to time the oracle on a
+ * sample of a workload too large to run whole.  out->n_* count the leaves
+ * of the slice; out->s2t/s2e/s2h are the slice's sums. */
+int or_leaf_sample(uint64_t x, uint64_t y, uint64_t c, uint64_t b_lo, uint64_t b_hi,
+                   uint64_t u_max, or_decomp *out)
+{
+    if (y < 1 || (u128)y * y > x || (u128)(y + 1) * (y + 1) * (y + 1) <= x)
+        return 1;
+    ctx_t C;
+    ctx_init(&C, x, y, y + 2);
+    C.c = c < C.a ? c : C.a;
+    memset(out, 0, sizeof *out);
+    out->x = x;
+    out->y = y;
+    out->a = C.a;
+    out->c = C.c;
+    out->z = x / y;
+    leaves_acc A;
+    memset(&A, 0, sizeof A);
+    A.u_max = u_max;
+    special_leaves(&C, &A, 1, b_lo, b_hi);
+    out->s2t = pack(A.s2t);
+    out->s2e = pack(A.s2e);
+    out->n_trivial = A.nt;
+    out->n_easy = A.ne;
+    out->n_hard = A.nh;
+    uint64_t bmax = b_hi > 0 ? b_hi - 1 : 0;
+    if (bmax > C.a)
+        bmax = C.a;
+    out->bmax = bmax;
+    hard_direct_unplaced = 0;
+    i128 s2h = hard_direct(&C, &A.hard, 1u << 20, bmax, u_max, NULL, NULL, 0);
+    out->s2h = pack(s2h);
+    free(A.hard.v);
+    ctx_free(&C);
+    return hard_direct_unplaced ? 2 : 0;
 }

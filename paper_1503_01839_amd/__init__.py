@@ -18,6 +18,7 @@ PC_OK, PC_EINVAL, PC_ERANGE, PC_ENOMEM, PC_EDEVICE, PC_EINTERNAL = range(6)
 FLAG_TWO_PASS = 1
 FLAG_NO_BATCH_LARGE = 2
 FLAG_REBUILD_TABLES = 4
+FLAG_NO_SMALL_SEGMENTS = 8
 
 EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
            "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_wheel_c", "pc_status_str",
@@ -40,7 +41,8 @@ class I128(C.Structure):
 class Config(C.Structure):
     _fields_ = [("alpha", C.c_double), ("segment_kib", C.c_uint32), ("wg_size", C.c_uint32),
                 ("tile_leaves", C.c_uint32), ("flags", C.c_uint32),
-                ("carry_budget", C.c_uint64)]
+                ("carry_budget", C.c_uint64), ("small_span", C.c_uint32),
+                ("small_kib", C.c_uint32)]
 
 
 class _Result(C.Structure):
@@ -48,9 +50,10 @@ class _Result(C.Structure):
                [(n, I128) for n in ("s1", "s2_trivial", "s2_easy", "s2_hard", "p2", "phi")] + \
                [(n, C.c_uint64) for n in ("n_s1", "n_trivial", "n_easy", "n_hard", "n_p2",
                                           "segments", "tiles", "windows", "segment_bits",
-                                          "device_bytes")] + \
-               [(n, C.c_double) for n in ("ms_total", "ms_tables", "ms_s1", "ms_easy",
-                                          "ms_sieve", "ms_scan")]
+                                          "small_segments", "crossings", "device_bytes")] + \
+               [(n, C.c_uint32) for n in ("sieve_launches", "scan_launches")] + \
+               [(n, C.c_double) for n in ("ms_total", "ms_tables", "ms_leaves", "ms_sieve",
+                                          "ms_k_sieve", "ms_k_scan", "ms_k_easy", "ms_k_s1")]
 
 
 @dataclass
@@ -77,14 +80,19 @@ class Result:
     tiles: int
     windows: int
     segment_bits: int
+    small_segments: int
+    crossings: int
     device_bytes: int
+    sieve_launches: int
+    scan_launches: int
     ms_total: float
     ms_tables: float
-    ms_s1: float
-    ms_easy: float
+    ms_leaves: float
     ms_sieve: float
-    ms_scan: float
-
+    ms_k_sieve: float
+    ms_k_scan: float
+    ms_k_easy: float
+    ms_k_s1: float
 
 _lib = None
 
@@ -123,8 +131,10 @@ def _check(st: int):
         raise PicountError(st, f"{L.pc_status_str(st).decode()}: {L.pc_last_error().decode()}")
 
 
-def _config(alpha=0.0, segment_kib=0, wg_size=0, tile_leaves=0, flags=0, carry_budget=0):
-    return Config(float(alpha), segment_kib, wg_size, tile_leaves, flags, carry_budget)
+def _config(alpha=0.0, segment_kib=0, wg_size=0, tile_leaves=0, flags=0, carry_budget=0,
+            small_span=0, small_kib=0):
+    return Config(float(alpha), segment_kib, wg_size, tile_leaves, flags, carry_budget,
+                  small_span, small_kib)
 
 
 def _result(r: _Result) -> Result:

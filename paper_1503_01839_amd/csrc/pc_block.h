@@ -6,6 +6,33 @@
 
 __device__ __forceinline__ uint32_t pc_lane() { return __lane_id(); }
 
+// 32-bit wavefront sum and inclusive scan with DPP lane moves (gfx9 row
+// operations), no LDS traffic.  Every lane must be active.
+#define PC_DPP(v, ctrl, rm) ((uint32_t)__builtin_amdgcn_update_dpp(0, (int)(v), ctrl, rm, 0xF, false))
+
+// sum of v over the wavefront, returned (uniform) in every lane
+__device__ __forceinline__ uint32_t pc_wave_sum_u32(uint32_t v)
+{
+    v += PC_DPP(v, 0xB1, 0xF);  // quad_perm [1,0,3,2]
+    v += PC_DPP(v, 0x4E, 0xF);  // quad_perm [2,3,0,1]
+    v += PC_DPP(v, 0x141, 0xF); // row_half_mirror
+    v += PC_DPP(v, 0x140, 0xF); // row_mirror: every lane holds its row's sum
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+}
+
+// inclusive prefix sum across the wavefront
+__device__ __forceinline__ uint32_t pc_wave_incl_scan_u32(uint32_t v)
+{
+    v += PC_DPP(v, 0x111, 0xF); // row_shr:1
+    v += PC_DPP(v, 0x112, 0xF); // row_shr:2
+    v += PC_DPP(v, 0x114, 0xF); // row_shr:4
+    v += PC_DPP(v, 0x118, 0xF); // row_shr:8  -> inclusive within rows of 16
+    v += PC_DPP(v, 0x142, 0xA); // row_bcast:15 into rows 1 and 3
+    v += PC_DPP(v, 0x143, 0xC); // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Inclusive prefix sum across the 64 lanes of a wavefront.
 template <typename T> __device__ __forceinline__ T pc_wave_incl_scan(T v)
 {
@@ -50,7 +77,11 @@ __device__ __forceinline__ T pc_block_excl_scan(T v, T *scratch, T *total)
 {
     constexpr int NW = NT / 64;
     const int w = threadIdx.x >> 6;
-    T inc = pc_wave_incl_scan(v);
+    T inc;
+    if constexpr (sizeof(T) == 4)
+        inc = (T)pc_wave_incl_scan_u32((uint32_t)v);
+    else
+        inc = pc_wave_incl_scan(v);
     if (pc_lane() == 63)
         scratch[w] = inc;
     __syncthreads();
@@ -71,7 +102,10 @@ __device__ __forceinline__ T pc_block_excl_scan(T v, T *scratch, T *total)
 template <int NT, typename T> __device__ __forceinline__ T pc_block_sum(T v, T *scratch)
 {
     constexpr int NW = NT / 64;
-    v = pc_wave_sum(v);
+    if constexpr (sizeof(T) == 4)
+        v = (T)pc_wave_sum_u32((uint32_t)v);
+    else
+        v = pc_wave_sum(v);
     if (pc_lane() == 0)
         scratch[threadIdx.x >> 6] = v;
     __syncthreads();

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -45,9 +46,13 @@ struct DevBuf {
 
 size_t g_dev_bytes = 0, g_dev_peak = 0;
 
+hipStream_t g_stream = nullptr;
+
 void dfree(DevBuf &b)
 {
     if (b.p) {
+        if (g_stream) // kernels queued earlier may still read the buffer
+            (void)hipStreamSynchronize(g_stream);
         (void)hipFree(b.p);
         g_dev_bytes -= b.cap;
     }
@@ -97,13 +102,12 @@ struct Tables {
 Tables g_T;
 
 struct QueryBufs {
-    DevBuf Xb, e_start, e_count, e_off, e_tmp, e_total, part, sums, fin, ntriv;
+    DevBuf Ub, Xb, e_start, e_count, e_off, e_tmp, e_total, part, sums, fin, ntriv;
+    DevBuf work, hot, bounds, tiles_a, trace;
     DevBuf tiles, cnt, wgt, carry_rows, carry_a, carry_b, status, ticket, part_tile_h,
         part_tile_p, part_scan_h, part_scan_p, err;
 };
 QueryBufs g_Q;
-
-hipStream_t g_stream = nullptr;
 
 void init_stream()
 {
@@ -263,7 +267,7 @@ void drop_tables()
 void drop_query_bufs()
 {
     QueryBufs &B = g_Q;
-    DevBuf *all[] = {&B.Xb, &B.e_start, &B.e_count, &B.e_off, &B.e_tmp, &B.e_total, &B.part,
+    DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.e_start, &B.e_count, &B.e_off, &B.e_tmp, &B.e_total, &B.part,
                      &B.sums, &B.fin, &B.ntriv, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
                      &B.carry_a, &B.carry_b, &B.status, &B.ticket, &B.part_tile_h,
                      &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err};
@@ -313,6 +317,10 @@ struct Knobs {
     bool two_pass = false;
     bool batch = true;
     uint64_t carry_budget = 6ull << 30;
+    uint64_t tile_leaves = 0;    // hard-leaf items per tile; 0 = no column splitting
+    uint32_t hot_log2 = 15;      // small one-wavefront segments below hot_span * y
+    uint32_t hot_wg = 64;
+    uint64_t hot_span = 64;      // 0 = no small segments
 };
 
 Knobs knobs_from(const pc_config *cfg)
@@ -329,33 +337,161 @@ Knobs knobs_from(const pc_config *cfg)
     case 64:
         k.seg_log2 = 19;
         break;
-    case 128:
-        k.seg_log2 = 20;
-        break;
     default:
-        fail(PC_EINVAL, "segment_kib must be 32, 64 or 128");
+        fail(PC_EINVAL, "segment_kib must be 32 or 64");
     }
     switch (cfg->wg_size) {
     case 0:
         break;
+    case 256:
     case 512:
     case 1024:
         k.wg = cfg->wg_size;
         break;
     default:
-        fail(PC_EINVAL, "wg_size must be 512 or 1024");
+        fail(PC_EINVAL, "wg_size must be 256, 512 or 1024");
     }
+    // supported (segment, workgroup) shapes: each thread owns whole 512-bit blocks
+    // while crossing small primes, and the LDS image must fit in 160 KiB
+    const bool ok = (k.seg_log2 == 18 && (k.wg == 256 || k.wg == 512)) ||
+                    (k.seg_log2 == 19 && (k.wg == 512 || k.wg == 1024));
+    if (!ok)
+        fail(PC_EINVAL, "unsupported segment_kib / wg_size pair (32: 256|512, 64: 512|1024)");
     k.two_pass = (cfg->flags & PC_FLAG_TWO_PASS) != 0;
     k.batch = (cfg->flags & PC_FLAG_NO_BATCH_LARGE) == 0;
     if (cfg->carry_budget)
         k.carry_budget = cfg->carry_budget;
+    if (cfg->tile_leaves == 0xFFFFFFFFu)
+        k.tile_leaves = 0;
+    else if (cfg->tile_leaves)
+        k.tile_leaves = cfg->tile_leaves;
+    if (cfg->small_span)
+        k.hot_span = cfg->small_span;
+    switch (cfg->small_kib) {
+    case 0:
+        break;
+    case 4:
+        k.hot_log2 = 15;
+        k.hot_wg = 64;
+        break;
+    case 8:
+        k.hot_log2 = 16;
+        k.hot_wg = 64;
+        break;
+    default:
+        fail(PC_EINVAL, "small_kib must be 4 or 8");
+    }
+    if (cfg->flags & PC_FLAG_NO_SMALL_SEGMENTS)
+        k.hot_span = 0;
     return k;
+}
+
+// Kernel timing with HIP events recorded on the library stream.
+struct EvPair {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+std::vector<EvPair> g_ev;
+size_t g_ev_used = 0;
+
+EvPair &ev_next()
+{
+    if (g_ev_used == g_ev.size()) {
+        EvPair e;
+        hipck(hipEventCreate(&e.a), "hipEventCreate");
+        hipck(hipEventCreate(&e.b), "hipEventCreate");
+        g_ev.push_back(e);
+    }
+    return g_ev[g_ev_used++];
+}
+
+// time the launches made by f on the library stream; returns the event pair index
+template <typename F> size_t timed(F &&f)
+{
+    EvPair &e = ev_next();
+    hipck(hipEventRecord(e.a, g_stream), "hipEventRecord");
+    f();
+    hipck(hipEventRecord(e.b, g_stream), "hipEventRecord");
+    return g_ev_used - 1;
+}
+
+double ev_ms(size_t i)
+{
+    float ms = 0;
+    hipck(hipEventElapsedTime(&ms, g_ev[i].a, g_ev[i].b), "hipEventElapsedTime");
+    return ms;
 }
 
 using clk = std::chrono::steady_clock;
 double ms_since(clk::time_point t0)
 {
     return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+// Tiles of the window [s0, s0 + rows): segments below plan_end whose hard-leaf
+// work exceeds the target are cut into column ranges of about equal work
+// (these go first, heaviest first); every other segment is one tile.
+void plan_tiles(const pc_tables &T, const pc_query &Q, const Knobs &K, uint32_t log2s,
+                uint64_t lo_base, uint64_t seg_base, uint64_t s0, uint64_t rows, uint64_t plan_end,
+                std::vector<pc_tile> &tiles)
+{
+    QueryBufs &B = g_Q;
+    tiles.clear();
+    std::vector<uint8_t> split(rows, 0);
+    if (K.tile_leaves && plan_end > s0) {
+        const uint64_t np = plan_end - s0;
+        ensure(B.work, np * 8, "tile plan");
+        hipck(pc_launch_seg_work(T, Q, log2s, lo_base, seg_base, s0, (uint32_t)np,
+                                 ptr<uint64_t>(B.work), g_stream),
+              "tile plan");
+        std::vector<uint64_t> work(np);
+        hipck(hipMemcpyAsync(work.data(), B.work.p, np * 8, hipMemcpyDeviceToHost, g_stream),
+              "D2H");
+        hipck(hipStreamSynchronize(g_stream), "sync");
+        std::vector<uint4> hot;
+        uint32_t off = 0;
+        for (uint64_t i = 0; i < np; i++)
+            if (work[i] > K.tile_leaves) {
+                uint64_t k = (work[i] + K.tile_leaves - 1) / K.tile_leaves;
+                k = std::min<uint64_t>(k, std::min<uint64_t>(4096, Q.nb));
+                if (k < 2)
+                    continue;
+                hot.push_back(uint4{(uint32_t)(s0 + i), (uint32_t)k, off, 0});
+                off += (uint32_t)k + 1;
+            }
+        if (!hot.empty()) {
+            std::sort(hot.begin(), hot.end(), [&](const uint4 &a, const uint4 &b) {
+                return work[a.x - s0] > work[b.x - s0];
+            });
+            off = 0;
+            for (uint4 &h : hot) {
+                h.z = off;
+                off += h.y + 1;
+            }
+            ensure(B.hot, hot.size() * sizeof(uint4), "tile plan");
+            ensure(B.bounds, (size_t)off * 4, "tile plan");
+            hipck(hipMemcpyAsync(B.hot.p, hot.data(), hot.size() * sizeof(uint4),
+                                 hipMemcpyHostToDevice, g_stream),
+                  "H2D");
+            hipck(pc_launch_seg_split(T, Q, log2s, lo_base, seg_base, ptr<uint4>(B.hot),
+                                      (uint32_t)hot.size(), ptr<uint32_t>(B.bounds), g_stream),
+                  "tile split");
+            std::vector<uint32_t> bd(off);
+            hipck(hipMemcpyAsync(bd.data(), B.bounds.p, (size_t)off * 4, hipMemcpyDeviceToHost,
+                                 g_stream),
+                  "D2H");
+            hipck(hipStreamSynchronize(g_stream), "sync");
+            for (const uint4 &h : hot) {
+                const uint32_t *b = bd.data() + h.z;
+                for (uint32_t j = 0; j < h.y; j++)
+                    if (b[j] < b[j + 1])
+                        tiles.push_back(pc_tile{h.x, b[j], b[j + 1], 0});
+                split[h.x - s0] = 1;
+            }
+        }
+    }
+    for (uint64_t r = 0; r < rows; r++)
+        if (!split[r])
+            tiles.push_back(pc_tile{(uint32_t)(s0 + r), 0, Q.ncol, 0});
 }
 
 // Full decomposition for one (x, y); x >= 8, icbrt(x) <= y <= isqrt(x).
@@ -396,6 +532,21 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     Q.ncol = Q.nb + 1;
     Q.kx = (uint32_t)kx;
 
+    // Rows of the sieve: nA one-wavefront segments of 2*SA integers covering
+    // the leaf-dense low end up to about hot_span * y, then nB workgroup
+    // segments of 2*S integers, together covering [0, z].
+    const uint64_t S = 1ull << K.seg_log2, SA = 1ull << K.hot_log2;
+    uint64_t nA = 0;
+    if (K.hot_span) {
+        const uint64_t uA = std::min<uint64_t>(z + 1, K.hot_span * y);
+        nA = (uA + 2 * SA - 1) / (2 * SA);
+    }
+    const uint64_t baseB = nA * 2 * SA;
+    const uint64_t nB = baseB > z ? 0 : (z - baseB) / (2 * S) + 1;
+    const uint64_t nseg = nA + nB;
+    Q.sieve_end = baseB + nB * 2 * S;
+    g_ev_used = 0;
+
     // --- per-query tables and the leaves outside the sieve ---
     ensure(B.Xb, (a + 2) * 8, "X_b");
     Q.Xb = ptr<uint64_t>(B.Xb);
@@ -408,21 +559,26 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.sums), sizeof(pc_sums) / 8, 0, g_stream), "fill");
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.ntriv), 1, 0, g_stream), "fill");
     pc_sums *sums = ptr<pc_sums>(B.sums);
+    Q.sums = sums;
 
     const uint32_t s1_blocks = (uint32_t)std::min<uint64_t>(2048, y / 256 + 1);
     const uint32_t ls_blocks = (uint32_t)(a / 256 + 1);
     const uint32_t ez_blocks = 4096;
     ensure(B.part, (size_t)std::max<uint32_t>({s1_blocks, ls_blocks, ez_blocks}) * 16, "partials");
     auto t1 = clk::now();
-    hipck(pc_launch_s1(T, Q, ptr<pc_s128>(B.part), s1_blocks, g_stream), "S1");
+    const size_t ev_s1 = timed(
+        [&] { hipck(pc_launch_s1(T, Q, ptr<pc_s128>(B.part), s1_blocks, g_stream), "S1"); });
     hipck(pc_launch_sum128(ptr<pc_s128>(B.part), s1_blocks, &sums->s1, g_stream), "S1 sum");
 
     ensure(B.e_start, (a + 2) * 8, "easy ranges");
     ensure(B.e_count, (a + 2) * 8, "easy ranges");
     ensure(B.e_off, (a + 2) * 8, "easy offsets");
     ensure(B.e_tmp, ((a + 2) / 4096 + 2) * 8, "scan");
+    ensure(B.Ub, (a + 2) * 16, "hard-leaf u ranges");
+    Q.Ub = ptr<ulonglong2>(B.Ub);
     hipck(pc_launch_leaf_setup(T, Q, ptr<uint64_t>(B.e_start), ptr<uint64_t>(B.e_count),
-                               ptr<pc_s128>(B.part), ptr<uint64_t>(B.ntriv), ls_blocks, g_stream),
+                               ptr<pc_s128>(B.part), ptr<uint64_t>(B.ntriv),
+                               ptr<ulonglong2>(B.Ub), ls_blocks, g_stream),
           "leaf setup");
     hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ls_blocks, &sums->s2t, g_stream), "S2t sum");
     hipck(pc_launch_strip(ptr<uint64_t>(B.e_count), ptr<uint64_t>(B.e_off), a + 1, g_stream),
@@ -430,18 +586,19 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     hipck(pc_launch_scan_u64(ptr<uint64_t>(B.e_off), a + 1, ptr<uint64_t>(B.e_tmp),
                              ptr<uint64_t>(B.e_total), g_stream),
           "easy scan");
-    hipck(pc_launch_easy(T, Q, ptr<uint64_t>(B.e_start), ptr<uint64_t>(B.e_count),
-                         ptr<uint64_t>(B.e_off), ptr<uint64_t>(B.e_total), ptr<pc_s128>(B.part),
-                         ez_blocks, g_stream),
-          "easy");
+    const size_t ev_easy = timed([&] {
+        hipck(pc_launch_easy(T, Q, ptr<uint64_t>(B.e_start), ptr<uint64_t>(B.e_count),
+                             ptr<uint64_t>(B.e_off), ptr<uint64_t>(B.e_total),
+                             ptr<pc_s128>(B.part), ez_blocks, g_stream),
+              "easy");
+    });
     hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ez_blocks, &sums->s2e, g_stream), "S2e sum");
     hipck(hipStreamSynchronize(g_stream), "sync");
     const double ms_leaves = ms_since(t1);
 
     // --- the sieve of [1, z] in windows of segments ---
     auto t2 = clk::now();
-    const uint64_t S = 1ull << K.seg_log2;
-    const uint64_t nseg = z / (2 * S) + 1;
+    std::vector<size_t> ev_sieve, ev_scan;
     const uint64_t per_entry = K.two_pass ? 12 : 8;
     uint64_t rows_w = std::max<uint64_t>(1, K.carry_budget / (per_entry * Q.ncol));
     rows_w = std::min(rows_w, nseg);
@@ -450,7 +607,6 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     uint32_t R = (uint32_t)std::clamp<uint64_t>(rows_w / 64, 16, 1024);
     const uint64_t nchunk_max = (rows_w + R - 1) / R;
 
-    ensure(B.tiles, rows_w * sizeof(pc_tile), "tiles");
     ensure(B.cnt, rows_w * Q.ncol * 4, "counts");
     if (!K.two_pass)
         ensure(B.wgt, rows_w * Q.ncol * 4, "leaf weights");
@@ -460,42 +616,108 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     ensure(B.carry_b, (size_t)Q.ncol * 8, "carry");
     ensure(B.status, nchunk_max * Q.ncol * 8 + 8, "look-back status");
     ensure(B.ticket, 8, "ticket");
-    ensure(B.part_tile_h, rows_w * 16, "tile partials");
-    ensure(B.part_tile_p, rows_w * 16, "tile partials");
     ensure(B.part_scan_h, nchunk_max * ncb * 16, "scan partials");
     ensure(B.part_scan_p, nchunk_max * ncb * 16, "scan partials");
     ensure(B.err, 8, "error flag");
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.carry_a), Q.ncol, 0, g_stream), "fill");
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.err), 1, 0, g_stream), "fill");
 
-    std::vector<pc_tile> tiles(rows_w);
+    // PICOUNT_TILE_TRACE=<path>: append one line per sieve tile (profiling aid)
+    FILE *trace_file = nullptr;
+    if (const char *tp = std::getenv("PICOUNT_TILE_TRACE"))
+        trace_file = std::fopen(tp, "a");
+    std::vector<pc_tile> tiles_a, tiles_b;
+    uint64_t ntiles_total = 0;
     uint64_t *cin = ptr<uint64_t>(B.carry_a), *cout = ptr<uint64_t>(B.carry_b);
-    double ms_scan = 0;
+    const int bflag = K.batch ? 0 : 0x100;
     for (uint64_t w = 0; w < nwin; w++) {
-        const uint64_t s0 = w * rows_w;
-        const uint64_t rows = std::min(rows_w, nseg - s0);
-        for (uint64_t r = 0; r < rows; r++)
-            tiles[r] = pc_tile{(uint32_t)(s0 + r), 0, Q.ncol, 0};
-        hipck(hipMemcpyAsync(B.tiles.p, tiles.data(), rows * sizeof(pc_tile),
-                             hipMemcpyHostToDevice, g_stream),
-              "tiles");
-        pc_sieve_args A{};
-        A.T = T;
-        A.Q = Q;
-        A.tiles = ptr<pc_tile>(B.tiles);
-        A.ntiles = (uint32_t)rows;
-        A.seg0 = s0;
-        A.cnt = ptr<uint32_t>(B.cnt);
-        A.wgt = ptr<int32_t>(B.wgt);
-        A.carry = ptr<uint64_t>(B.carry_rows);
-        A.part_hard = ptr<pc_s128>(B.part_tile_h);
-        A.part_p2 = ptr<pc_s128>(B.part_tile_p);
-        A.err = ptr<int32_t>(B.err);
-        const int bflag = K.batch ? 0 : 0x100;
-        hipck(pc_launch_sieve(A, K.seg_log2, K.wg, (K.two_pass ? PC_MODE_COUNT : PC_MODE_TALLY) |
-                                                       bflag,
-                              g_stream),
-              "sieve");
+        const uint64_t r0 = w * rows_w;
+        const uint64_t rows = std::min(rows_w, nseg - r0), r1 = r0 + rows;
+        // rows [r0, min(r1, nA)) are small segments, the rest workgroup segments
+        tiles_a.clear();
+        for (uint64_t r = r0; r < std::min(r1, nA); r++)
+            tiles_a.push_back(pc_tile{(uint32_t)r, 0, Q.ncol, 0});
+        tiles_b.clear();
+        if (r1 > nA) {
+            const uint64_t b0 = std::max(r0, nA);
+            const uint64_t hot_end = std::max<uint64_t>(64 * y, z / 32);
+            const uint64_t plan_end =
+                hot_end <= baseB ? b0 : std::min(r1, nA + (hot_end - baseB) / (2 * S) + 1);
+            plan_tiles(T, Q, K, K.seg_log2, baseB, nA, b0, r1 - b0, std::max(b0, plan_end),
+                       tiles_b);
+        }
+        ntiles_total += tiles_a.size() + tiles_b.size();
+        ensure(B.tiles_a, tiles_a.size() * sizeof(pc_tile), "tiles");
+        ensure(B.tiles, tiles_b.size() * sizeof(pc_tile), "tiles");
+        const size_t npart = std::max(tiles_a.size(), tiles_b.size());
+        ensure(B.part_tile_h, npart * 16, "tile partials");
+        ensure(B.part_tile_p, npart * 16, "tile partials");
+        if (!tiles_a.empty())
+            hipck(hipMemcpyAsync(B.tiles_a.p, tiles_a.data(), tiles_a.size() * sizeof(pc_tile),
+                                 hipMemcpyHostToDevice, g_stream),
+                  "tiles");
+        if (!tiles_b.empty())
+            hipck(hipMemcpyAsync(B.tiles.p, tiles_b.data(), tiles_b.size() * sizeof(pc_tile),
+                                 hipMemcpyHostToDevice, g_stream),
+                  "tiles");
+        auto sieve_args = [&](bool small) {
+            pc_sieve_args A{};
+            A.T = T;
+            A.Q = Q;
+            A.tiles = ptr<pc_tile>(small ? B.tiles_a : B.tiles);
+            A.ntiles = (uint32_t)(small ? tiles_a.size() : tiles_b.size());
+            A.seg0 = r0;
+            A.lo_base = small ? 0 : baseB;
+            A.seg_base = small ? 0 : nA;
+            A.cnt = ptr<uint32_t>(B.cnt);
+            A.wgt = ptr<int32_t>(B.wgt);
+            A.carry = ptr<uint64_t>(B.carry_rows);
+            A.part_hard = ptr<pc_s128>(B.part_tile_h);
+            A.part_p2 = ptr<pc_s128>(B.part_tile_p);
+            A.err = ptr<int32_t>(B.err);
+            return A;
+        };
+        // one sieve launch per geometry; the tile partials are folded right after
+        auto sieve = [&](bool small, int mode) {
+            pc_sieve_args A = sieve_args(small);
+            if (A.ntiles == 0)
+                return;
+            if (trace_file) {
+                ensure(B.trace, (size_t)A.ntiles * 16, "tile trace");
+                hipck(pc_launch_fill_u64(ptr<uint64_t>(B.trace), (uint64_t)A.ntiles * 2, 0,
+                                         g_stream),
+                      "fill");
+                A.trace = ptr<uint4>(B.trace);
+            }
+            ev_sieve.push_back(timed([&] {
+                hipck(pc_launch_sieve(A, small ? K.hot_log2 : K.seg_log2, small ? K.hot_wg : K.wg,
+                                      mode | bflag, g_stream),
+                      "sieve");
+            }));
+            if (trace_file) { // per-tile profile: segment, columns, ticks (100 MHz), work
+                std::vector<uint4> tr(A.ntiles);
+                hipck(hipMemcpyAsync(tr.data(), B.trace.p, (size_t)A.ntiles * 16,
+                                     hipMemcpyDeviceToHost, g_stream),
+                      "D2H");
+                hipck(hipStreamSynchronize(g_stream), "sync");
+                const std::vector<pc_tile> &tl = small ? tiles_a : tiles_b;
+                for (uint32_t i = 0; i < A.ntiles; i++)
+                    std::fprintf(trace_file, "%u %u %u %u %u %u %u %u %d\n", (unsigned)w,
+                                 tl[i].seg, tl[i].col_lo, tl[i].col_hi, tr[i].x, tr[i].y, tr[i].z,
+                                 tr[i].w, small ? 1 : 0);
+            }
+            if (mode != PC_MODE_COUNT) {
+                hipck(pc_launch_sum128(ptr<pc_s128>(B.part_tile_h), A.ntiles, &sums->hard_local,
+                                       g_stream),
+                      "sum");
+                hipck(pc_launch_sum128(ptr<pc_s128>(B.part_tile_p), A.ntiles, &sums->p2_local,
+                                       g_stream),
+                      "sum");
+            }
+        };
+        const int first = K.two_pass ? PC_MODE_COUNT : PC_MODE_TALLY;
+        sieve(true, first);
+        sieve(false, first);
 
         pc_scan_args SA{};
         SA.cnt = ptr<uint32_t>(B.cnt);
@@ -518,10 +740,13 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
                                  g_stream),
               "fill");
         hipck(pc_launch_fill_u64(ptr<uint64_t>(B.ticket), 1, 0, g_stream), "fill");
-        hipck(pc_launch_scan(SA, K.two_pass ? PC_MODE_COUNT : PC_MODE_TALLY, g_stream), "scan");
+        ev_scan.push_back(timed([&] {
+            hipck(pc_launch_scan(SA, K.two_pass ? PC_MODE_COUNT : PC_MODE_TALLY, g_stream),
+                  "scan");
+        }));
         if (K.two_pass) {
-            hipck(pc_launch_sieve(A, K.seg_log2, K.wg, PC_MODE_LEAVES | bflag, g_stream),
-                  "leaf pass");
+            sieve(true, PC_MODE_LEAVES);
+            sieve(false, PC_MODE_LEAVES);
         } else {
             hipck(pc_launch_sum128(ptr<pc_s128>(B.part_scan_h), SA.nchunk * ncb,
                                    &sums->hard_dot, g_stream),
@@ -530,18 +755,16 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
                                    g_stream),
                   "sum");
         }
-        hipck(pc_launch_sum128(ptr<pc_s128>(B.part_tile_h), (uint32_t)rows, &sums->hard_local,
-                               g_stream),
-              "sum");
-        hipck(pc_launch_sum128(ptr<pc_s128>(B.part_tile_p), (uint32_t)rows, &sums->p2_local,
-                               g_stream),
-              "sum");
         std::swap(cin, cout);
     }
+    if (trace_file)
+        std::fclose(trace_file);
     hipck(pc_launch_combine(sums, Q, kx, ptr<pc_final>(B.fin), g_stream), "combine");
     pc_final fin{};
+    pc_sums hs{};
     int32_t err = 0;
     uint64_t ntriv = 0;
+    hipck(hipMemcpyAsync(&hs, B.sums.p, sizeof hs, hipMemcpyDeviceToHost, g_stream), "D2H");
     hipck(hipMemcpyAsync(&fin, B.fin.p, sizeof fin, hipMemcpyDeviceToHost, g_stream), "D2H");
     hipck(hipMemcpyAsync(&err, B.err.p, 4, hipMemcpyDeviceToHost, g_stream), "D2H");
     hipck(hipMemcpyAsync(&ntriv, B.ntriv.p, 8, hipMemcpyDeviceToHost, g_stream), "D2H");
@@ -571,17 +794,28 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         res->phi = to_abi(fin.phi);
         res->n_trivial = ntriv;
         res->n_p2 = kx > a ? kx - a : 0;
+        res->n_s1 = hs.n_s1;
+        res->n_easy = hs.n_easy;
+        res->n_hard = hs.n_hard;
+        res->crossings = hs.crossings;
         res->segments = nseg;
-        res->tiles = nseg;
+        res->tiles = ntiles_total;
         res->windows = nwin;
         res->segment_bits = S;
+        res->small_segments = nA;
         res->device_bytes = g_dev_peak;
         res->ms_total = ms_since(t0);
         res->ms_tables = ms_tables;
-        res->ms_s1 = ms_leaves;
-        res->ms_easy = ms_leaves;
+        res->ms_leaves = ms_leaves;
         res->ms_sieve = ms_sieve;
-        res->ms_scan = ms_scan;
+        res->ms_k_s1 = ev_ms(ev_s1);
+        res->ms_k_easy = ev_ms(ev_easy);
+        for (size_t i : ev_sieve)
+            res->ms_k_sieve += ev_ms(i);
+        for (size_t i : ev_scan)
+            res->ms_k_scan += ev_ms(i);
+        res->sieve_launches = (uint32_t)ev_sieve.size();
+        res->scan_launches = (uint32_t)ev_scan.size();
     }
 }
 

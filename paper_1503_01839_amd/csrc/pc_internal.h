@@ -32,6 +32,8 @@ struct pc_tables {
     uint32_t pad;
 };
 
+struct pc_sums;
+
 // Per-query scalars.
 struct pc_query {
     uint64_t x, y, z;
@@ -42,6 +44,9 @@ struct pc_query {
     uint32_t c, a, bmax, nb, ncol;
     uint32_t kx;            // pi(isqrt(x))
     const uint64_t *Xb;     // Xb[b] = floor(x / p_b), 1-based, b <= a
+    uint64_t sieve_end;     // the sieve covers [0, sieve_end): segments * 2S integers
+    const ulonglong2 *Ub;   // Ub[b] = [u_lo, u_hi]: u of every hard leaf of b (x > y: none)
+    pc_sums *sums;          // device accumulators of this query
 };
 
 enum { PC_MODE_TALLY = 0, PC_MODE_COUNT = 1, PC_MODE_LEAVES = 2 };
@@ -53,12 +58,15 @@ struct pc_sieve_args {
     uint32_t ntiles;
     uint32_t pad;
     uint64_t seg0;          // first segment of the window: row = seg - seg0
+    uint64_t lo_base;       // segment seg starts at lo_base + (seg - seg_base) * 2S
+    uint64_t seg_base;
     uint32_t *cnt;          // [row * ncol + col]
     int32_t *wgt;           // [row * ncol + col]
     const uint64_t *carry;  // PC_MODE_LEAVES: exclusive carries, same layout
     pc_s128 *part_hard;     // per tile
     pc_s128 *part_p2;       // per tile
     int32_t *err;
+    uint4 *trace;           // optional, per tile: ticks, leaves, candidates, leafy columns
 };
 
 // Launchers (each returns hipSuccess or the first HIP error).
@@ -88,7 +96,7 @@ hipError_t pc_launch_s1(const pc_tables &T, const pc_query &Q, pc_s128 *part, ui
                         hipStream_t s);
 hipError_t pc_launch_leaf_setup(const pc_tables &T, const pc_query &Q, uint64_t *e_start,
                                 uint64_t *e_count, pc_s128 *part_trivial, uint64_t *ntrivial,
-                                uint32_t nblocks, hipStream_t s);
+                                ulonglong2 *Ub, uint32_t nblocks, hipStream_t s);
 hipError_t pc_launch_strip(const uint64_t *e_count, uint64_t *e_off, uint64_t n, hipStream_t s);
 hipError_t pc_launch_scan_u64(uint64_t *data, uint64_t n, uint64_t *tmp, uint64_t *total,
                               hipStream_t s);
@@ -97,6 +105,14 @@ hipError_t pc_launch_easy(const pc_tables &T, const pc_query &Q, const uint64_t 
                           pc_s128 *part, uint32_t nblocks, hipStream_t s);
 hipError_t pc_launch_sum128(const pc_s128 *part, uint32_t n, pc_s128 *acc, hipStream_t s);
 hipError_t pc_launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+
+// Tile planning: hard-leaf items per segment, and column cuts for hot segments.
+hipError_t pc_launch_seg_work(const pc_tables &T, const pc_query &Q, uint32_t seg_log2,
+                              uint64_t lo_base, uint64_t seg_base, uint64_t seg0, uint32_t nseg,
+                              uint64_t *work, hipStream_t s);
+hipError_t pc_launch_seg_split(const pc_tables &T, const pc_query &Q, uint32_t seg_log2,
+                               uint64_t lo_base, uint64_t seg_base, const uint4 *hot,
+                               uint32_t nhot, uint32_t *bounds, hipStream_t s);
 
 // Sieve and carry scan.
 hipError_t pc_launch_sieve(const pc_sieve_args &A, uint32_t seg_log2, uint32_t wg, int mode,
@@ -122,7 +138,7 @@ hipError_t pc_launch_scan(const pc_scan_args &A, int mode, hipStream_t s);
 // Final combination of the partial sums into pi(x) and its parts.
 struct pc_sums {
     pc_s128 s1, s2t, s2e, hard_local, hard_dot, p2_local, p2_dot;
-    uint64_t n_trivial, pad;
+    unsigned long long n_s1, n_easy, n_hard, crossings;
 };
 struct pc_final {
     pc_s128 s1, s2t, s2e, s2h, p2, phi;

@@ -19,7 +19,9 @@ __global__ __launch_bounds__(LV_T) void k_s1(pc_tables T, pc_query Q, pc_s128 *p
 {
     __shared__ pc_s128 scr[LV_T / 64];
     const uint32_t pc_ = T.primes[Q.c];
+    __shared__ unsigned long long scr64[LV_T / 64];
     pc_s128 acc = 0;
+    unsigned long long terms = 0;
     const uint64_t stride = (uint64_t)gridDim.x * LV_T;
     for (uint64_t n = 1 + (uint64_t)blockIdx.x * LV_T + threadIdx.x; n <= Q.y; n += stride) {
         const int32_t v = T.mulpf[n];
@@ -30,10 +32,14 @@ __global__ __launch_bounds__(LV_T) void k_s1(pc_tables T, pc_query Q, pc_s128 *p
         const uint64_t qq = pc_div(u, Q.Qc, Q.recip_Qc);
         const uint64_t phi = qq * T.phiQ + T.phitab[u - qq * Q.Qc];
         acc += v > 0 ? (pc_s128)phi : -(pc_s128)phi;
+        terms++;
     }
     acc = pc_block_sum128<LV_T>(acc, scr);
-    if (threadIdx.x == 0)
+    terms = pc_block_sum<LV_T>(terms, scr64);
+    if (threadIdx.x == 0) {
         part[blockIdx.x] = acc;
+        atomicAdd(&Q.sums->n_s1, terms);
+    }
 }
 
 hipError_t pc_launch_s1(const pc_tables &T, const pc_query &Q, pc_s128 *part, uint32_t nblocks,
@@ -53,11 +59,33 @@ hipError_t pc_launch_s1(const pc_tables &T, const pc_query &Q, pc_s128 *part, ui
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(LV_T) void k_leaf_setup(pc_tables T, pc_query Q, uint64_t *e_start,
                                                      uint64_t *e_count, pc_s128 *part_t,
-                                                     uint64_t *ntriv)
+                                                     uint64_t *ntriv, ulonglong2 *Ub)
 {
     __shared__ uint64_t scr[LV_T / 64];
     const uint32_t b = blockIdx.x * LV_T + threadIdx.x;
-    uint64_t triv = 0;
+    uint64_t triv = 0, cross = 0;
+    if (b > Q.c && b <= Q.c + Q.nb) { // a sieving prime
+        const uint64_t p = T.primes[b], rp = T.recip[b], X = Q.Xb[b];
+        // odd multiples k p_b, k odd, below the sieve end
+        cross = (pc_div(Q.sieve_end - 1, p, rp) + 1) / 2;
+        // u range of the hard leaves of b: y/p < m <= y, m > p, m <= max(x/p^3, x/(p(y+1)))
+        uint64_t m1 = pc_div(Q.y, p, rp) + 1;
+        if (m1 < p + 1)
+            m1 = p + 1;
+        const uint64_t h1 = pc_div(pc_div(X, p, rp), p, rp);
+        const uint64_t h2 = pc_div(X, Q.y1, Q.recip_y1);
+        uint64_t m2 = h1 > h2 ? h1 : h2;
+        if (m2 > Q.y)
+            m2 = Q.y;
+        ulonglong2 ub;
+        ub.x = 1;
+        ub.y = 0;
+        if (m1 <= m2) {
+            ub.x = pc_div_small_q(X, (uint32_t)m2);
+            ub.y = pc_div_small_q(X, (uint32_t)m1);
+        }
+        Ub[b] = ub;
+    }
     if (b <= Q.a) {
         uint64_t st = 0, cn = 0;
         if (b > Q.c && b < Q.a) {
@@ -94,17 +122,19 @@ __global__ __launch_bounds__(LV_T) void k_leaf_setup(pc_tables T, pc_query Q, ui
         e_count[b] = cn;
     }
     const uint64_t s = pc_block_sum<LV_T>(triv, scr);
+    const uint64_t cs = pc_block_sum<LV_T>(cross, scr);
     if (threadIdx.x == 0) {
         part_t[blockIdx.x] = (pc_s128)s;
         atomicAdd((unsigned long long *)ntriv, (unsigned long long)s);
+        atomicAdd(&Q.sums->crossings, (unsigned long long)cs);
     }
 }
 
 hipError_t pc_launch_leaf_setup(const pc_tables &T, const pc_query &Q, uint64_t *e_start,
                                 uint64_t *e_count, pc_s128 *part_trivial, uint64_t *ntrivial,
-                                uint32_t nblocks, hipStream_t s)
+                                ulonglong2 *Ub, uint32_t nblocks, hipStream_t s)
 {
-    k_leaf_setup<<<nblocks, LV_T, 0, s>>>(T, Q, e_start, e_count, part_trivial, ntrivial);
+    k_leaf_setup<<<nblocks, LV_T, 0, s>>>(T, Q, e_start, e_count, part_trivial, ntrivial, Ub);
     return hipGetLastError();
 }
 
@@ -117,77 +147,86 @@ __global__ void k_strip_counts(const uint64_t *e_count, uint64_t *e_off, uint64_
 }
 
 // ---------------------------------------------------------------------------
-// Easy leaves: items laid end to end over b; each lane takes runs of EZ_RUN
-// consecutive items (consecutive m of one b share most of pi(u)'s cache lines).
+// Easy leaves: items laid end to end over b (e_off = exclusive prefix).  A
+// workgroup takes tiles of EZ_TILE consecutive items; one search finds the b
+// of the tile's first item, then lane t takes items i0 + t, i0 + t + EZ_T, ...
+// so neighbouring lanes read neighbouring primes m and neighbouring pi(u)
+// entries.  u = x/(m p_b) <= y < 2^50, so the fp64-estimate quotient is exact
+// after its remainder check.
 // ---------------------------------------------------------------------------
-#define EZ_RUN 16
+#define EZ_T 256
+#define EZ_PER 32
+#define EZ_TILE (EZ_T * EZ_PER)
 
-__global__ __launch_bounds__(LV_T) void k_easy(pc_tables T, pc_query Q, const uint64_t *e_start,
+__global__ __launch_bounds__(EZ_T) void k_easy(pc_tables T, pc_query Q, const uint64_t *e_start,
                                                const uint64_t *e_count, const uint64_t *e_off,
                                                const uint64_t *e_total, pc_s128 *part)
 {
-    __shared__ pc_s128 scr[LV_T / 64];
+    __shared__ pc_s128 scr[EZ_T / 64];
+    __shared__ unsigned long long scr64[EZ_T / 64];
+    __shared__ uint32_t s_b0;
+    unsigned long long nleaf = 0;
     const uint64_t E = *e_total;
-    const uint64_t nruns = (E + EZ_RUN - 1) / EZ_RUN;
-    const uint64_t stride = (uint64_t)gridDim.x * LV_T;
     int64_t acc = 0;
-    for (uint64_t r = (uint64_t)blockIdx.x * LV_T + threadIdx.x; r < nruns; r += stride) {
-        uint64_t i = r * EZ_RUN;
-        const uint64_t iend = i + EZ_RUN < E ? i + EZ_RUN : E;
-        // b with e_off[b] <= i < e_off[b] + count: binary search over b in [c+1, a-1]
-        uint32_t lo_b = Q.c + 1, hi_b = Q.a - 1;
-        while (lo_b < hi_b) {
-            const uint32_t mid = (lo_b + hi_b + 1) >> 1;
-            if (e_off[mid] <= i)
-                lo_b = mid;
-            else
-                hi_b = mid - 1;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * EZ_TILE; i0 < E; i0 += (uint64_t)gridDim.x * EZ_TILE) {
+        if (threadIdx.x == 0) { // b with e_off[b] <= i0 < e_off[b+1], b in [c+1, a-1]
+            uint32_t lo_b = Q.c + 1, hi_b = Q.a - 1;
+            while (lo_b < hi_b) {
+                const uint32_t mid = (lo_b + hi_b + 1) >> 1;
+                if (e_off[mid] <= i0)
+                    lo_b = mid;
+                else
+                    hi_b = mid - 1;
+            }
+            s_b0 = lo_b;
         }
-        uint32_t b = lo_b;
-        while (i < iend) {
-            uint64_t cn = e_count[b];
-            const bool cand = (cn & PC_MODEBIT) != 0;
-            cn &= ~PC_MODEBIT;
-            const uint64_t off = e_off[b];
-            if (i >= off + cn) {
+        __syncthreads();
+        uint32_t b = s_b0;
+        uint64_t off = e_off[b], cn = e_count[b], st = e_start[b], X = Q.Xb[b];
+        uint32_t p = T.primes[b];
+        const uint64_t iend = i0 + EZ_TILE < E ? i0 + EZ_TILE : E;
+        for (uint64_t i = i0 + threadIdx.x; i < iend; i += EZ_T) {
+            while (i >= off + (cn & ~PC_MODEBIT)) {
                 b++;
-                continue;
+                off = e_off[b];
+                cn = e_count[b];
+                st = e_start[b];
+                X = Q.Xb[b];
+                p = T.primes[b];
             }
-            const uint64_t st = e_start[b];
-            const uint32_t p = T.primes[b];
-            const uint64_t X = Q.Xb[b];
-            const uint64_t stop = off + cn < iend ? off + cn : iend;
-            for (; i < stop; i++) {
-                const uint64_t o = i - off;
-                uint64_t u;
-                int32_t w;
-                if (cand) {
-                    const uint32_t m = (uint32_t)(st + o);
-                    const int32_t v = T.mulpf[m];
-                    const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
-                    if (l <= p)
-                        continue;
-                    w = v > 0 ? -1 : 1;
-                    u = pc_div_small_q(X, m);
-                } else {
-                    const uint64_t k = st + o;
-                    u = pc_div(X, T.primes[k], T.recip[k]);
-                    w = 1;
-                }
-                acc += (int64_t)w * ((int64_t)pc_pi_lookup(T.pitab, u) - (int64_t)b + 2);
+            const uint64_t o = i - off;
+            uint32_t m;
+            int32_t w;
+            if (cn & PC_MODEBIT) {
+                m = (uint32_t)(st + o);
+                const int32_t v = T.mulpf[m];
+                const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
+                if (l <= p) // mu(m) = 0 or lpf(m) <= p_b
+                    continue;
+                w = v > 0 ? -1 : 1;
+            } else {
+                m = T.primes[st + o];
+                w = 1;
             }
+            const uint64_t u = pc_div_small_q(X, m);
+            acc += (int64_t)w * ((int64_t)pc_pi_lookup(T.pitab, u) - (int64_t)b + 2);
+            nleaf++;
         }
+        __syncthreads();
     }
-    const pc_s128 s = pc_block_sum128<LV_T>((pc_s128)acc, scr);
-    if (threadIdx.x == 0)
+    const pc_s128 s = pc_block_sum128<EZ_T>((pc_s128)acc, scr);
+    nleaf = pc_block_sum<EZ_T>(nleaf, scr64);
+    if (threadIdx.x == 0) {
         part[blockIdx.x] = s;
+        atomicAdd(&Q.sums->n_easy, nleaf);
+    }
 }
 
 hipError_t pc_launch_easy(const pc_tables &T, const pc_query &Q, const uint64_t *e_start,
                           const uint64_t *e_count, const uint64_t *e_off, const uint64_t *e_total,
                           pc_s128 *part, uint32_t nblocks, hipStream_t s)
 {
-    k_easy<<<nblocks, LV_T, 0, s>>>(T, Q, e_start, e_count, e_off, e_total, part);
+    k_easy<<<nblocks, EZ_T, 0, s>>>(T, Q, e_start, e_count, e_off, e_total, part);
     return hipGetLastError();
 }
 

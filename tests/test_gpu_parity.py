@@ -75,14 +75,14 @@ def test_golden_records(pc):
         assert r.n_trivial == rec["n_trivial"]
 
 
-@pytest.mark.parametrize("seg", [32, 64, 128])
-@pytest.mark.parametrize("wg", [512, 1024])
+@pytest.mark.parametrize("seg,wg", [(32, 256), (32, 512), (64, 512), (64, 1024)])
 def test_config_invariance(pc, seg, wg):
     # the sieve geometry never changes a value (the paper's own check, Section 5)
     for x, y in [(10**11, 4641), (10**12, 20000), (10**10 + 12345, 4000)]:
         say("case: invariance", x, y, seg, wg)
         o = O.decompose(x, y, 6, hard=O.HARD_SIEVE)
-        for flags in (0, pc.FLAG_NO_BATCH_LARGE, pc.FLAG_TWO_PASS):
+        for flags in (0, pc.FLAG_NO_BATCH_LARGE, pc.FLAG_TWO_PASS, pc.FLAG_NO_SMALL_SEGMENTS,
+                      pc.FLAG_TWO_PASS | pc.FLAG_NO_SMALL_SEGMENTS):
             r = pc.decompose(x, y, segment_kib=seg, wg_size=wg, flags=flags)
             assert (r.s2_hard, r.p2, r.pi) == (o.s2h, o.p2, o.pi), (x, y, seg, wg, flags)
 
@@ -91,7 +91,7 @@ def test_windows(pc):
     # a tiny carry budget forces many windows; carries must chain across them
     x, y = 10**12, 10**4
     o = O.decompose(x, y, 6, hard=O.HARD_SIEVE)
-    for budget in (1 << 16, 1 << 20, 3 << 20):
+    for budget in (1 << 16, 1 << 18, 1 << 20):
         say("case: windows", budget)
         r = pc.decompose(x, y, carry_budget=budget)
         assert r.windows > 1
@@ -125,6 +125,13 @@ def test_random_vs_oracle(pc):
         assert pc.pi_count(x) == O.pi_meissel(x), x
 
 
+def test_bad_shapes_rejected(pc):
+    with pytest.raises(pc.PicountError):
+        pc.decompose(10**11, 4641, segment_kib=32, wg_size=1024)
+    with pytest.raises(pc.PicountError):
+        pc.decompose(10**11, 4641, segment_kib=128)
+
+
 def test_p2_and_s2_hard_entry_points(pc):
     x, y = 10**11, 4641
     o = O.decompose(x, y, 6, hard=O.HARD_SIEVE)
@@ -134,3 +141,35 @@ def test_p2_and_s2_hard_entry_points(pc):
         pc.s2_hard(x, y, o.a + 1)
     with pytest.raises(pc.PicountError):
         pc.p2(x, 10)  # y below icbrt(x)
+
+
+@pytest.mark.parametrize("tile_leaves", [512, 4096, 49152, 0xFFFFFFFF])
+def test_tile_split_invariance(pc, tile_leaves, paper_pow10):
+    # cutting hot segments into column-range tiles never changes a value
+    recs = {(r["x"], r["y"]): r for r in golden()}
+    for (x, y) in [(10**12, 10**4), (10**13, 21544), (10**12, 80000)]:
+        say("case: split", x, y, tile_leaves)
+        rec = recs[(x, y)]
+        for flags in (0, pc.FLAG_NO_SMALL_SEGMENTS):
+            r = pc.decompose(x, y, tile_leaves=tile_leaves, flags=flags)
+            assert (r.s2_hard, r.p2, r.pi) == (rec["s2h"], rec["p2"], rec["pi"]), \
+                (x, y, tile_leaves, flags)
+            assert r.n_hard == rec["n_hard"]
+            if tile_leaves == 512 and flags:
+                assert r.tiles > r.segments
+    say("case: split 1e15", tile_leaves)
+    assert pc.pi_count_ex(10**15, tile_leaves=tile_leaves).pi == paper_pow10[15]
+
+
+@pytest.mark.parametrize("small_kib", [4, 8])
+@pytest.mark.parametrize("span", [1, 3, 64, 100000])
+def test_small_segment_invariance(pc, small_kib, span):
+    # the boundary between one-wavefront and workgroup segments moves nothing
+    recs = {(r["x"], r["y"]): r for r in golden()}
+    for (x, y) in [(10**12, 20000), (10**11, 4641), (10**13, 21544)]:
+        say("case: small segments", x, y, small_kib, span)
+        rec = recs[(x, y)]
+        r = pc.decompose(x, y, small_kib=small_kib, small_span=span)
+        assert (r.s2_hard, r.p2, r.pi) == (rec["s2h"], rec["p2"], rec["pi"]), (x, y)
+        assert r.n_hard == rec["n_hard"]
+        assert r.small_segments > 0
