@@ -683,11 +683,11 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
             if (A.ntiles == 0)
                 return;
             if (trace_file) {
-                ensure(B.trace, (size_t)A.ntiles * 16, "tile trace");
-                hipck(pc_launch_fill_u64(ptr<uint64_t>(B.trace), (uint64_t)A.ntiles * 2, 0,
-                                         g_stream),
+                ensure(B.trace, (size_t)A.ntiles * PC_TRACE_W * 4, "tile trace");
+                hipck(pc_launch_fill_u64(ptr<uint64_t>(B.trace),
+                                         (uint64_t)A.ntiles * PC_TRACE_W / 2, 0, g_stream),
                       "fill");
-                A.trace = ptr<uint4>(B.trace);
+                A.trace = ptr<uint32_t>(B.trace);
             }
             ev_sieve.push_back(timed([&] {
                 hipck(pc_launch_sieve(A, small ? K.hot_log2 : K.seg_log2, small ? K.hot_wg : K.wg,
@@ -695,16 +695,19 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
                       "sieve");
             }));
             if (trace_file) { // per-tile profile: segment, columns, ticks (100 MHz), work
-                std::vector<uint4> tr(A.ntiles);
-                hipck(hipMemcpyAsync(tr.data(), B.trace.p, (size_t)A.ntiles * 16,
+                std::vector<uint32_t> tr((size_t)A.ntiles * PC_TRACE_W);
+                hipck(hipMemcpyAsync(tr.data(), B.trace.p, tr.size() * 4,
                                      hipMemcpyDeviceToHost, g_stream),
                       "D2H");
                 hipck(hipStreamSynchronize(g_stream), "sync");
                 const std::vector<pc_tile> &tl = small ? tiles_a : tiles_b;
-                for (uint32_t i = 0; i < A.ntiles; i++)
-                    std::fprintf(trace_file, "%u %u %u %u %u %u %u %u %d\n", (unsigned)w,
-                                 tl[i].seg, tl[i].col_lo, tl[i].col_hi, tr[i].x, tr[i].y, tr[i].z,
-                                 tr[i].w, small ? 1 : 0);
+                for (uint32_t i = 0; i < A.ntiles; i++) {
+                    std::fprintf(trace_file, "%u %u %u %u %d", (unsigned)w, tl[i].seg,
+                                 tl[i].col_lo, tl[i].col_hi, small ? 1 : 0);
+                    for (uint32_t k = 0; k < PC_TRACE_W; k++)
+                        std::fprintf(trace_file, " %u", tr[(size_t)i * PC_TRACE_W + k]);
+                    std::fputc('\n', trace_file);
+                }
             }
             if (mode != PC_MODE_COUNT) {
                 hipck(pc_launch_sum128(ptr<pc_s128>(B.part_tile_h), A.ntiles, &sums->hard_local,

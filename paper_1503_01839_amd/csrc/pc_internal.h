@@ -51,6 +51,10 @@ struct pc_query {
 
 enum { PC_MODE_TALLY = 0, PC_MODE_COUNT = 1, PC_MODE_LEAVES = 2 };
 
+// per-tile trace record: 0 ticks (100 MHz), 1 hard leaves, 2 candidates read,
+// 3 leafy columns, 4 of them with p^3 < segment end, 5.. phase ticks
+#define PC_TRACE_W 16
+
 struct pc_sieve_args {
     pc_tables T;
     pc_query Q;
@@ -66,7 +70,7 @@ struct pc_sieve_args {
     pc_s128 *part_hard;     // per tile
     pc_s128 *part_p2;       // per tile
     int32_t *err;
-    uint4 *trace;           // optional, per tile: ticks, leaves, candidates, leafy columns
+    uint32_t *trace;        // optional, PC_TRACE_W words per tile (profiling aid)
 };
 
 // Launchers (each returns hipSuccess or the first HIP error).

@@ -33,6 +33,12 @@
 
 #define PC_CAND 0x80000000u
 
+// PC_PHASE_TRACE=1 adds per-phase tick counters to the tile trace (a
+// profiling build; the default build only records totals)
+#ifndef PC_PHASE_TRACE
+#define PC_PHASE_TRACE 0
+#endif
+
 // The hard leaves (b, m) whose u = floor(X_b/m) lies in [lo, hi): special
 // (y/p_b < m <= y, lpf(m) > p_b) and hard (m <= max(x/p^3, x/(p(y+1)))).
 // For p_b^2 > y every such m is prime and the range is returned as prime
@@ -74,43 +80,86 @@ __device__ __forceinline__ void pc_leaf_range(const pc_tables &TB, const pc_quer
     }
 }
 
+// Waves per SIMD that the LDS footprint of k_sieve<LOG2_S, T, CH> allows on a
+// CU (160 KiB of LDS, at most 8 waves per SIMD); the kernel asks the compiler
+// to fit its registers to that many, so a code change cannot silently cost a
+// resident workgroup.
+template <int LOG2_S, int T, int CH> constexpr uint32_t pc_sieve_gcap()
+{
+    return (1u << (LOG2_S - 9)) > 256u ? (1u << (LOG2_S - 9)) : 256u;
+}
+template <int LOG2_S, int T, int CH> constexpr int pc_sieve_waves_per_simd()
+{
+    constexpr long S = 1l << LOG2_S, NW = S / 32, NWP = NW + NW / 16, NBLK = S >> 9;
+    constexpr long NWV = T / 64;
+    constexpr long lds = 4 * (NWP + 16) + 4 * (NBLK + 1) + 4 * pc_sieve_gcap<LOG2_S, T, CH>() +
+                         24 * CH + 16 * (CH / 64) + 12 + 8 * NWV + 16 * NWV;
+    constexpr long wg = 163840 / lds;
+    constexpr long waves = wg * NWV < 32 ? wg * NWV : 32;
+    return waves / 4 < 1 ? 1 : (int)(waves / 4);
+}
+
 template <int LOG2_S, int T, int CH, int MODE, bool BATCH>
-__global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
+    pc_sieve_waves_per_simd<LOG2_S, T, CH>()))) void k_sieve(pc_sieve_args A)
 {
     static_assert(CH == T, "one lane per column of a chunk");
     static_assert(T % 64 == 0, "wavefront multiples");
-    constexpr uint32_t S = 1u << LOG2_S;  // odd integers (bits) per segment
-    constexpr uint32_t NW = S / 32;       // 32-bit words
+    constexpr uint32_t S = 1u << LOG2_S;   // odd integers (bits) per segment
+    constexpr uint32_t NW = S / 32;        // 32-bit words
     constexpr uint32_t NWP = NW + NW / 16; // padded: one spare word after every 16
-    constexpr uint32_t BL = 9;            // 512-bit counting blocks (16 words)
+    constexpr uint32_t BL = 9;             // 512-bit counting blocks (16 words)
     constexpr uint32_t NBLK = S >> BL;
     constexpr uint32_t NWV = T / 64;
-    constexpr uint32_t BPT = NBLK / T;    // blocks a thread owns while crossing small primes
-    static_assert(NBLK % T == 0 && BPT >= 1, "every thread owns whole counting blocks");
-    constexpr uint32_t OWN = BPT << BL;   // bits owned per thread
-    constexpr uint32_t LIGHT = 128;       // leaf items a single wavefront answers per column
-    constexpr uint32_t GAP = 4;           // leafless columns that end a single-wavefront run
+    constexpr uint32_t BPT = NBLK / T; // counting blocks per thread
+    static_assert(NBLK % T == 0 && BPT >= 1 && BPT <= 2, "every thread counts one or two blocks");
+    constexpr uint32_t RS = S / NWV;   // bits of the region a wavefront owns
+    constexpr uint32_t RSL = LOG2_S - (NWV == 1 ? 0 : NWV == 2 ? 1 : NWV == 4 ? 2 : NWV == 8 ? 3 : 4);
+    static_assert((1u << RSL) == RS && RS == 64 * BPT * 512, "a region is 64 threads' blocks");
+    constexpr uint32_t GCAP = pc_sieve_gcap<LOG2_S, T, CH>(); // gathered leaf items
+    constexpr uint32_t LIGHT = GCAP / 2; // more leaf items: the column is answered workgroup-wide
+    constexpr uint32_t GAPB = 8;         // leafless large-prime columns worth one batched crossing
+    constexpr uint32_t GATH = 0x40000000u; // c_lc: leaves gathered, (offset << 12) | count
 
     // Word w of the segment lives at bm[w + w/16]: the 16 words of a counting
     // block are contiguous and consecutive blocks start 17 words apart, so the
     // threads of a wavefront walking their own blocks hit distinct banks.
     __shared__ uint32_t bm[NWP + 16];  // 16 spare words: a query at q = S reads past the end
-    __shared__ uint32_t pre[NBLK + 1];   // prefix of the block counts (pre[NBLK] = total)
-    __shared__ uint32_t fen[NBLK + 1];   // Fenwick tree over the blocks, 1-based
-    __shared__ uint32_t c_p[CH];         // p_b
-    __shared__ uint32_t c_i0[CH];        // bit of the first multiple in the segment, S if none
-    __shared__ uint32_t c_ls[CH];        // first leaf item (m, or index of the prime m)
-    __shared__ uint32_t c_lc[CH];        // leaf items; PC_CAND: items are candidate m
-    __shared__ uint32_t c_new[CH];       // integers first removed by p_b in this segment
-    __shared__ int32_t c_w[CH];          // sum of -mu(m) over the leaves of the column
+    __shared__ uint32_t pre[NBLK + 1]; // prefix of the block counts; in a gather, slot offsets
+    __shared__ uint32_t gbuf[GCAP];    // gathered leaves: q << 2 | (mu(m) > 0) << 1 | 1
+    __shared__ uint32_t c_p[CH];       // p_b
+    __shared__ uint32_t c_i0[CH];      // bit of the first multiple in the segment, S if none
+    __shared__ uint32_t c_ls[CH];      // first leaf item (m, or index of the prime m)
+    __shared__ uint32_t c_lc[CH];      // leaf items; PC_CAND: items are candidate m; or GATH
+    __shared__ uint32_t c_new[CH];     // integers first removed by p_b in this segment
+    __shared__ int32_t c_w[CH];        // sum of -mu(m) over the leaves of the column
     __shared__ uint64_t c_leafy[CH / 64];
     __shared__ uint64_t c_heavy[CH / 64];
-    __shared__ uint32_t s_first_large;
+    __shared__ uint32_t s_first_large, s_gend, s_used;
+    __shared__ uint32_t reg_dec[NWV];  // integers a batched crossing removed, per region
     __shared__ uint32_t scr32[NWV];
     __shared__ pc_s128 scr128[NWV];
 
     const uint64_t t_start = A.trace ? __builtin_amdgcn_s_memrealtime() : 0;
-    uint32_t n_cand = 0, n_leafy = 0;
+    uint32_t n_cand = 0, n_leafy = 0, n_leafy_small = 0;
+#if PC_PHASE_TRACE
+    // 0 set-up, 1 per-column set-up, 2 gathers, 3 heavy columns, 4 wavefront
+    // columns, 5 batched crossings, 7 chunk results, 8 final column
+    uint32_t ph[9] = {};
+    uint64_t ph_last = t_start;
+#define PC_PH(k)                                                                        \
+    do {                                                                                \
+        if (A.trace) {                                                                  \
+            const uint64_t t_ = __builtin_amdgcn_s_memrealtime();                       \
+            ph[k] += (uint32_t)(t_ - ph_last);                                          \
+            ph_last = t_;                                                               \
+        }                                                                               \
+    } while (0)
+#else
+#define PC_PH(k) \
+    do {         \
+    } while (0)
+#endif
     const pc_tile tile = A.tiles[blockIdx.x];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
@@ -145,22 +194,30 @@ __global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
             BW(w) = v;
         }
     }
+    if (tid < NWV)
+        reg_dec[tid] = 0;
     __syncthreads();
 
-    // pre[] = exclusive prefix of the unsieved counts of the blocks, each thread
-    // counting the blocks it owns; returns the segment total.
-    auto build_pre = [&]() -> uint32_t {
-        uint32_t cnt[BPT], s = 0;
+    // unsieved integers in each of the blocks thread tid counts
+    auto block_counts = [&](uint32_t (&cnt)[BPT]) -> uint32_t {
+        uint32_t s = 0;
 #pragma unroll
         for (uint32_t k = 0; k < BPT; k++) {
             const uint32_t base = (tid * BPT + k) * 17;
             uint32_t c = 0;
 #pragma unroll
-            for (uint32_t j = 0; j < 16; j++)
-                c += (uint32_t)__builtin_popcount(bm[base + j]);
+            for (uint32_t i = 0; i < 16; i++)
+                c += (uint32_t)__builtin_popcount(bm[base + i]);
             cnt[k] = c;
             s += c;
         }
+        return s;
+    };
+    // pre[] = exclusive prefix of the unsieved counts of the blocks; returns
+    // the segment total.  Every thread must call it; it ends with a barrier.
+    auto build_pre = [&]() -> uint32_t {
+        uint32_t cnt[BPT];
+        const uint32_t s = block_counts(cnt);
         uint32_t tot;
         uint32_t ex = pc_block_excl_scan<T>(s, scr32, &tot);
 #pragma unroll
@@ -172,16 +229,6 @@ __global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
             pre[NBLK] = tot;
         __syncthreads();
         return tot;
-    };
-    // Fenwick tree from pre[]: fen[i] covers blocks [i - lowbit(i), i) (0-based)
-    auto build_fen = [&]() {
-        for (uint32_t i = tid + 1; i <= NBLK; i += T)
-            fen[i] = pre[i] - pre[i - (i & (0u - i))];
-        __syncthreads();
-    };
-    auto fen_dec = [&](uint32_t blk) {
-        for (uint32_t i = blk + 1; i <= NBLK; i += i & (0u - i))
-            __hip_atomic_fetch_sub(&fen[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     // unsieved integers among the bits of q's block below q: the block's 16
     // words are read unconditionally and masked, so the reads issue together
@@ -197,110 +244,50 @@ __global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
         }
         return s;
     };
-    // unsieved integers among bits [0, q), q <= S
+    // unsieved integers among bits [0, q), q <= S, against pre[]
     auto count_pre = [&](uint32_t q) -> uint32_t { return pre[q >> BL] + in_block(q); };
-    // Fenwick prefix over blocks [0, q/512): the node indices depend only on q,
-    // so the (at most log2(NBLK)+1) reads are unrolled and issue together
-    auto count_fen = [&](uint32_t q) -> uint32_t {
-        uint32_t i = q >> BL, s = 0;
-#pragma unroll
-        for (uint32_t l = 0; l <= LOG2_S - BL; l++) {
-            const uint32_t v = fen[i];
-            s += i ? v : 0u;
-            i &= i - 1;
-        }
-        return s + in_block(q);
-    };
 
     uint32_t total = build_pre();
-    bool fen_ok = false;               // uniform: the Fenwick tree mirrors the bitmap
+    PC_PH(0);
+    // Wavefront wv owns bits [R0, R1).  rc = its unsieved integers, kept exact
+    // through every crossing: a leaf whose u lies in a higher region counts
+    // all of them, one in this region counts a prefix of it.
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    const uint32_t R0 = wv * RS, R1 = R0 + RS;
+    uint32_t rc = (uint32_t)__builtin_amdgcn_readfirstlane((int)(pre[R1 >> BL] - pre[R0 >> BL]));
     unsigned long long nleaf = 0;      // hard leaves answered by this thread
     int64_t acc_local = 0;             // sum of -mu(m) * in-segment count (hard leaves)
     int64_t acc_p2 = 0;                // sum of in-segment counts (P2 terms)
-    pc_s128 acc_carry = 0;             // PC_MODE_LEAVES: carry * w, kept by thread 0
+    pc_s128 acc_carry = 0;             // PC_MODE_LEAVES: carry * w
 
-    // The leaves of column j (chunk base cb): items t0, t0 + stride, ... of the
-    // column; returns this thread's sum of -mu(m).
-    auto leaves = [&](uint32_t cb, uint32_t j, bool use_fen, uint32_t t0, uint32_t stride) -> int32_t {
-        constexpr uint32_t U = 4; // items in flight per lane
+    // one leaf item of column j (chunk base cb): sets *w = -mu(m) (0 if the
+    // candidate m is not a leaf) and returns q, the bit count below u
+    auto leaf_item = [&](uint32_t cb, uint32_t j, uint32_t it, int32_t *w) -> uint32_t {
         const uint32_t b = Q.c + 1 + cb + j;
         const uint32_t lc = c_lc[j], ls = c_ls[j], p = c_p[j];
-        const bool cand = (lc & PC_CAND) != 0;
-        const uint32_t n = lc & ~PC_CAND;
-        const uint64_t X = Q.Xb[b];
-        int32_t wsum = 0;
-        int64_t lsum = 0;
-        for (uint32_t t2 = t0; t2 < n; t2 += U * stride) {
-            uint32_t mm[U];
-            int32_t ww[U];
-#pragma unroll
-            for (uint32_t k = 0; k < U; k++) { // issue the loads of U items together
-                const uint32_t it = t2 + k * stride;
-                mm[k] = 0;
-                ww[k] = 0;
-                if (it < n) {
-                    if (cand) {
-                        const int32_t v = TB.mulpf[ls + it];
-                        const uint32_t av = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
-                        if (av > p) { // squarefree with lpf(m) > p_b
-                            mm[k] = ls + it;
-                            ww[k] = v > 0 ? -1 : 1;
-                        }
-                    } else {
-                        mm[k] = TB.primes[ls + it];
-                        ww[k] = 1;
-                    }
-                }
+        uint64_t m = 0;
+        *w = 0;
+        if (lc & PC_CAND) {
+            const int32_t v = TB.mulpf[ls + it];
+            const uint32_t av = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
+            n_cand++;
+            if (av > p) { // squarefree with lpf(m) > p_b
+                m = ls + it;
+                *w = v > 0 ? -1 : 1;
             }
-            if (cand)
-#pragma unroll
-                for (uint32_t k = 0; k < U; k++)
-                    n_cand += t2 + k * stride < n;
-            uint32_t qq[U];
-#pragma unroll
-            for (uint32_t k = 0; k < U; k++) {
-                qq[k] = 0;
-                if (ww[k]) {
-                    const uint64_t u = pc_div_small_q(X, mm[k]);
-                    if (u < lo || u >= hi) { // cannot happen if the m range is right
-                        atomicOr(A.err, 2);
-                        ww[k] = 0;
-                    } else {
-                        qq[k] = (uint32_t)((u - lo + 1) >> 1);
-                    }
-                }
-            }
-#pragma unroll
-            for (uint32_t k = 0; k < U; k++)
-                if (ww[k]) {
-                    lsum += (int64_t)ww[k] * (int64_t)(use_fen ? count_fen(qq[k]) : count_pre(qq[k]));
-                    wsum += ww[k];
-                    nleaf++;
-                }
+        } else {
+            m = TB.primes[ls + it];
+            *w = 1;
         }
-        acc_local += lsum;
-        return wsum;
-    };
-    // cross p_b of column j, items t0, t0 + stride, ... of its multiples, on
-    // the exact current state; returns the integers this thread removed
-    auto cross_exact = [&](uint32_t j, uint32_t t0, uint32_t stride) -> uint32_t {
-        const uint32_t i0 = c_i0[j];
-        uint32_t mine = 0;
-        if (i0 < S) {
-            const uint32_t p = c_p[j];
-            const uint32_t n = (S - 1 - i0) / p + 1;
-            for (uint32_t t2 = t0; t2 < n; t2 += stride) {
-                const uint32_t bit = i0 + t2 * p;
-                const uint32_t w = bit >> 5, mask = 1u << (bit & 31);
-                if (BW(w) & mask) { // only this lane touches this bit
-                    mine++;
-                    fen_dec(bit >> BL);
-                    __hip_atomic_fetch_and(&BW(w), ~mask, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            }
+        if (*w == 0)
+            return 0;
+        const uint64_t u = pc_div_small_q(Q.Xb[b], m);
+        if (u < lo || u >= hi) { // cannot happen if the m range is right
+            atomicOr(A.err, 2);
+            *w = 0;
+            return 0;
         }
-        return mine;
+        return (uint32_t)((u - lo + 1) >> 1);
     };
 
     const uint32_t col_lo = tile.col_lo, col_hi = tile.col_hi;
@@ -310,7 +297,7 @@ __global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
         if (tid == 0)
             s_first_large = jend;
         __syncthreads();
-        // --- phase A: one lane per column: first multiple, leaf range ---
+        // --- one lane per column: first multiple, leaf range ---
         bool leafy = false, heavy = false, large = false;
         if (tid < jend) {
             const uint32_t j = tid, col = cb + j, b = Q.c + 1 + col;
@@ -353,165 +340,297 @@ __global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
             }
         }
         __syncthreads();
+        PC_PH(1);
         const uint32_t first_large = BATCH ? s_first_large : jend;
-        uint32_t j = 0;
 
-        // --- small primes (p^3 < hi): each thread crosses the words of the
-        // blocks it owns, in prime order; no atomics and no barriers ---
-        const uint32_t own0 = tid * OWN;
-        for (; j < min(first_large, jend); j++) {
-            const bool lf = (c_leafy[j >> 6] >> (j & 63)) & 1;
-            if (lf) {
+        // For 64 columns from cg0 on (one column per lane): p, the first
+        // multiple of p at or above R0 and the number of its multiples in
+        // [R0, R1), computed together; v_rem collects each column's removals
+        // in its lane and goes to c_new once per 64 columns.
+        uint32_t cg0 = 0x80000000u, v_f = 0, v_p = 1, v_nm = 0, v_rem = 0; // j - cg0 >= 64: reload
+        auto flush_removed = [&]() {
+            if (v_rem)
+                atomicAdd(&c_new[cg0 + lane], v_rem);
+            v_rem = 0;
+        };
+        // cross p_b of column j in this wave's region, one lane per multiple
+        auto cross_region = [&](uint32_t j) {
+            if (j - cg0 >= 64) {
+                flush_removed();
+                cg0 = j;
+                v_p = 1;
+                v_nm = 0;
+                v_f = 0;
+                if (j + lane < jend) {
+                    const uint32_t i0 = c_i0[j + lane], p = c_p[j + lane];
+                    // floor(e / p) for e < 2^20: the fp32 reciprocal puts the
+                    // estimate within one of the quotient, one step corrects it
+                    const float rp = __builtin_amdgcn_rcpf((float)p);
+                    auto quot = [&](uint32_t e) -> uint32_t {
+                        uint32_t q = (uint32_t)((float)e * rp);
+                        const int32_t r = (int32_t)(e - q * p);
+                        if (r < 0)
+                            q--;
+                        else if (r >= (int32_t)p)
+                            q++;
+                        return q;
+                    };
+                    uint32_t f = i0;
+                    if (i0 < R0) {
+                        const uint32_t d = R0 - i0, r = d - quot(d) * p;
+                        f = R0 + (r ? p - r : 0);
+                    }
+                    v_p = p;
+                    v_f = f;
+                    v_nm = f < R1 ? quot(R1 - 1 - f) + 1 : 0;
+                }
+            }
+            const int32_t k = (int32_t)(j - cg0);
+            const uint32_t nm = (uint32_t)__builtin_amdgcn_readlane((int)v_nm, k);
+            if (nm == 0)
+                return;
+            const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)v_f, k);
+            const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)v_p, k);
+            uint32_t removed = 0;
+            uint32_t bit = f + lane * p;
+            for (uint32_t t0 = 0; t0 < nm; t0 += 64, bit += 64 * p) {
+                bool hit = false;
+                if (t0 + lane < nm) {
+                    const uint32_t mask = 1u << (bit & 31);
+                    const uint32_t old = __hip_atomic_fetch_and(
+                        &BW(bit >> 5), ~mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    hit = (old & mask) != 0;
+                }
+                removed += (uint32_t)__builtin_popcountll(__ballot(hit));
+            }
+            rc -= removed;
+            if (lane == (uint32_t)k)
+                v_rem = removed;
+        };
+
+        // Gather the leaves of the light leafy columns of [j0, jend) that fit
+        // in gbuf (whole columns, in order), one item per thread: c_lc of a
+        // gathered column becomes GATH | offset << 12 | count.
+        auto gather = [&](uint32_t j0) {
+            PC_PH(4);
+            __syncthreads(); // earlier readers of gbuf and pre are done
+            const uint32_t jt = tid;
+            uint32_t v = 0;
+            if (jt >= j0 && jt < jend) {
+                const uint32_t lc = c_lc[jt];
+                if (lc != 0 && !(lc & GATH) && (lc & ~PC_CAND) <= LIGHT)
+                    v = lc & ~PC_CAND;
+            }
+            if (tid == 0) {
+                s_gend = jend;
+                s_used = 0;
+            }
+            uint32_t tot;
+            const uint32_t off = pc_block_excl_scan<T>(v, scr32, &tot); // two barriers
+            const bool fit = off + v <= GCAP;
+            if (jt >= j0 && jt < jend)
+                pre[jt] = fit ? off : GCAP;
+            if (v && !fit)
+                atomicMin(&s_gend, jt);
+            if (v && fit)
+                atomicMax(&s_used, off + v);
+            __syncthreads();
+            const uint32_t used = s_used, gend = s_gend;
+            for (uint32_t s = tid; s < used; s += T) {
+                uint32_t a = j0, z = gend; // the column: largest jc in [j0, gend) with pre[jc] <= s
+                while (z - a > 1) {
+                    const uint32_t mid = (a + z) >> 1;
+                    if (pre[mid] <= s)
+                        a = mid;
+                    else
+                        z = mid;
+                }
+                int32_t w;
+                const uint32_t q = leaf_item(cb, a, s - pre[a], &w);
+                uint32_t e = 0;
+                if (w) {
+                    e = (q << 2) | (w < 0 ? 2u : 0u) | 1u;
+                    atomicAdd(&c_w[a], w);
+                    nleaf++;
+                }
+                gbuf[s] = e;
+            }
+            __syncthreads(); // every reader of c_lc, c_ls and pre is done
+            if (v && fit) {
+                c_lc[jt] = GATH | (off << 12) | v;
                 n_leafy++;
-                __syncthreads(); // every thread has crossed the columns before j
-                build_pre();
-                const uint32_t ws = pc_wave_sum_u32((uint32_t)leaves(cb, j, false, tid, T));
-                if (lane == 0 && ws != 0)
-                    atomicAdd(&c_w[j], (int32_t)ws);
-                __syncthreads();
-                if (MODE == PC_MODE_LEAVES && tid == 0)
-                    acc_carry += (pc_s128)c_w[j] * (pc_s128)A.carry[row * ncol + cb + j];
+                if (jt < first_large)
+                    n_leafy_small++;
             }
-            const uint32_t i0 = c_i0[j];
-            uint32_t mine = 0;
-            if (i0 < S) {
-                const uint32_t p = c_p[j];
-                uint32_t f;
-                if (i0 >= own0) {
-                    f = i0;
-                } else { // first multiple at or above own0: (own0 - i0) mod p by fp32 reciprocal
-                    const uint32_t d = own0 - i0;
-                    uint32_t q = (uint32_t)((float)d * __builtin_amdgcn_rcpf((float)p));
-                    int32_t r = (int32_t)(d - q * p);
-                    if (r < 0)
-                        r += (int32_t)p;
-                    else if (r >= (int32_t)p)
-                        r -= (int32_t)p;
-                    f = own0 + (r ? p - (uint32_t)r : 0);
-                }
-                for (uint32_t bit = f; bit < own0 + OWN; bit += p) {
-                    const uint32_t w = bit >> 5, mask = 1u << (bit & 31);
-                    const uint32_t v = BW(w);
-                    if (v & mask) {
-                        BW(w) = v & ~mask;
-                        mine++;
+            __syncthreads();
+            PC_PH(2);
+        };
+        // this wave's part of the leaves of gathered column j: all of rc for a
+        // leaf above the region, a prefix of the region for one inside it
+        auto answer = [&](uint32_t j) {
+            const uint32_t g = c_lc[j];
+            const uint32_t s0 = (g >> 12) & 0x3FFFFu, s1 = s0 + (g & 0xFFFu);
+            bool have = false;
+            uint32_t pe = 0, pc0 = 0; // lane prefix of the region's block counts; first block
+            int32_t above = 0;
+            for (uint32_t s = s0; s < s1; s += 64) {
+                const uint32_t e = s + lane < s1 ? gbuf[s + lane] : 0u;
+                const bool valid = e & 1, neg = (e >> 1) & 1;
+                const uint32_t q = e >> 2, r = q >> RSL;
+                above += (int32_t)__builtin_popcountll(__ballot(valid && r > wv && !neg)) -
+                         (int32_t)__builtin_popcountll(__ballot(valid && r > wv && neg));
+                const bool in = valid && r == wv;
+                if (__ballot(in)) {
+                    if (!have) {
+                        uint32_t cnt[BPT];
+                        const uint32_t sum = block_counts(cnt);
+                        pe = pc_wave_incl_scan_u32(sum) - sum;
+                        pc0 = cnt[0];
+                        have = true;
+                    }
+                    const uint32_t bl = in ? (q >> BL) - (R0 >> BL) : 0u;
+                    const uint32_t src = bl / BPT;
+                    uint32_t c = (uint32_t)__shfl((int)pe, (int)src, 64);
+                    if (BPT > 1) {
+                        const uint32_t c0 = (uint32_t)__shfl((int)pc0, (int)src, 64);
+                        c += (bl % BPT) ? c0 : 0u;
+                    }
+                    if (in) {
+                        c += in_block(q);
+                        acc_local += neg ? -(int64_t)c : (int64_t)c;
                     }
                 }
             }
-            mine = pc_wave_sum_u32(mine);
-            if (lane == 0 && mine)
-                atomicAdd(&c_new[j], mine);
-        }
+            if (lane == 0)
+                acc_local += (int64_t)rc * above;
+        };
+        // many leaves: the whole workgroup answers them against pre[]
+        auto heavy_col = [&](uint32_t j) {
+            PC_PH(4);
+            __syncthreads(); // every wave has crossed the columns before j
+            build_pre();
+            const uint32_t n = c_lc[j] & ~PC_CAND;
+            int32_t wsum = 0;
+            int64_t lsum = 0;
+            for (uint32_t t0 = 0; t0 < n; t0 += 2 * T) {
+                int32_t w0, w1 = 0;
+                const uint32_t it0 = t0 + tid, it1 = it0 + T;
+                uint32_t q0 = 0, q1 = 0;
+                if (it0 < n)
+                    q0 = leaf_item(cb, j, it0, &w0);
+                else
+                    w0 = 0;
+                if (it1 < n)
+                    q1 = leaf_item(cb, j, it1, &w1);
+                if (w0) {
+                    lsum += (int64_t)w0 * (int64_t)count_pre(q0);
+                    wsum += w0;
+                    nleaf++;
+                }
+                if (w1) {
+                    lsum += (int64_t)w1 * (int64_t)count_pre(q1);
+                    wsum += w1;
+                    nleaf++;
+                }
+            }
+            acc_local += lsum;
+            const uint32_t ws = pc_wave_sum_u32((uint32_t)wsum);
+            if (lane == 0 && ws != 0)
+                atomicAdd(&c_w[j], (int32_t)ws);
+            if (tid == 0) {
+                n_leafy++;
+                if (j < first_large)
+                    n_leafy_small++;
+            }
+            __syncthreads(); // every read of the column's state precedes its crossing
+            PC_PH(3);
+        };
+        // Leafless columns [j, jb) of primes with p^3 >= hi, one lane per
+        // prime: an integer n = p k unsieved at the start of the run is first
+        // removed by p exactly when k = 1 or k >= p.
+        auto batch = [&](uint32_t j, uint32_t jb) {
+            PC_PH(4);
+            __syncthreads(); // every wave has crossed the columns before j
+            const uint32_t jj = j + tid;
+            const bool mine_col = jj < jb;
+            uint32_t i0 = S, p = 0;
+            if (mine_col) {
+                i0 = c_i0[jj];
+                p = c_p[jj];
+                uint32_t credit = 0;
+                // n = lo + 2 bit + 1 >= p^2  <=>  bit >= tb;  n = p  <=>  bit = ip
+                const uint64_t p2 = (uint64_t)p * p;
+                const uint32_t tb = p2 <= lo ? 0u : (uint32_t)min<uint64_t>(S, (p2 - lo - 1) >> 1);
+                const uint32_t ip = lo <= p ? i0 : S;
+                auto credit_bit = [&](uint32_t bit, uint32_t v) {
+                    if (((v >> (bit & 31)) & 1) && (bit >= tb || bit == ip)) {
+                        credit++;
+                        atomicAdd(&reg_dec[bit >> RSL], 1u);
+                    }
+                };
+                for (uint32_t bit = i0; bit < S; bit += 2 * p) {
+                    const uint32_t b1 = bit + p;
+                    const uint32_t v0 = BW(bit >> 5);
+                    const uint32_t v1 = b1 < S ? BW(b1 >> 5) : 0u;
+                    credit_bit(bit, v0);
+                    if (b1 < S)
+                        credit_bit(b1, v1);
+                }
+                c_new[jj] = credit;
+            }
+            __syncthreads(); // every read of the run precedes every clear
+            if (mine_col)
+                for (uint32_t bit = i0; bit < S; bit += p)
+                    __hip_atomic_fetch_and(&BW(bit >> 5), ~(1u << (bit & 31)), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            __syncthreads(); // clears and region counts complete
+            rc -= (uint32_t)__builtin_amdgcn_readfirstlane((int)reg_dec[wv]);
+            if (lane == 0)
+                reg_dec[wv] = 0; // next written after the next run's first barrier
+            PC_PH(5);
+        };
 
-        // --- large primes (p^3 >= hi), with the Fenwick tree ---
-        if (j < jend) {
-            if (!fen_ok) {
-                __syncthreads(); // every thread has finished its small primes
-                build_pre();
-                build_fen();
-                fen_ok = true;
+        // Columns in order.  Each wave crosses its own region, so between the
+        // workgroup-wide steps (gather, heavy column, batched run) the waves
+        // move through the columns independently.
+        uint32_t j = 0, jb_next = 0; // jb_next: the next leafy column, once known
+        uint32_t lw_at = ~0u;        // c_leafy word cached for columns [64 lw_at, 64 lw_at + 64)
+        uint64_t lw = 0;
+        while (j < jend) {
+            if ((j >> 6) != lw_at) {
+                lw_at = j >> 6;
+                lw = c_leafy[lw_at];
             }
-            while (j < jend) {
-                const bool lf = (c_leafy[j >> 6] >> (j & 63)) & 1;
+            const bool lf = (lw >> (j & 63)) & 1;
+            if (lf) {
                 const bool hv = (c_heavy[j >> 6] >> (j & 63)) & 1;
-                if (lf && hv) {
-                    // many leaves: the whole workgroup answers them, then crosses p_b
-                    n_leafy++;
-                    const uint32_t ws = pc_wave_sum_u32((uint32_t)leaves(cb, j, true, tid, T));
-                    if (lane == 0 && ws != 0)
-                        atomicAdd(&c_w[j], (int32_t)ws);
-                    __syncthreads(); // leaf reads done before the column is crossed
-                    if (MODE == PC_MODE_LEAVES && tid == 0)
-                        acc_carry += (pc_s128)c_w[j] * (pc_s128)A.carry[row * ncol + cb + j];
-                    const uint32_t mine = pc_wave_sum_u32(cross_exact(j, tid, T));
-                    if (lane == 0 && mine)
-                        atomicAdd(&c_new[j], mine);
-                    __syncthreads();
-                    j++;
-                } else if (lf) {
-                    // a run of light columns: wavefront 0 answers each column's
-                    // leaves and crosses its prime in order, with no workgroup
-                    // barrier; the run ends at a heavy column, at GAP leafless
-                    // columns in a row, or at the chunk end
-                    uint32_t jr = jend;
-                    {
-                        const uint32_t nwd = (jend + 63) / 64;
-                        for (uint32_t wv = j >> 6; wv < nwd; wv++) {
-                            const uint64_t keep = wv == (j >> 6) ? (~0ull << (j & 63)) : ~0ull;
-                            const uint64_t z = ~c_leafy[wv];
-                            uint64_t gap = z;
-#pragma unroll
-                            for (uint32_t g = 1; g < GAP; g++)
-                                gap &= z >> g;
-                            const uint64_t stop = (c_heavy[wv] | gap) & keep;
-                            if (stop) {
-                                jr = min(jend, wv * 64 + (uint32_t)__builtin_ctzll(stop));
-                                break;
-                            }
-                        }
-                    }
-                    if (tid < 64) {
-                        for (uint32_t jj = j; jj < jr; jj++) {
-                            if ((c_leafy[jj >> 6] >> (jj & 63)) & 1) {
-                                n_leafy++;
-                                const uint32_t ws = pc_wave_sum_u32((uint32_t)leaves(cb, jj, true, lane, 64));
-                                if (lane == 0) {
-                                    c_w[jj] = (int32_t)ws;
-                                    if (MODE == PC_MODE_LEAVES)
-                                        acc_carry += (pc_s128)(int32_t)ws *
-                                                     (pc_s128)A.carry[row * ncol + cb + jj];
-                                }
-                            }
-                            const uint32_t mine = pc_wave_sum_u32(cross_exact(jj, lane, 64));
-                            if (lane == 0)
-                                c_new[jj] = mine;
-                        }
-                    }
-                    __syncthreads();
-                    j = jr;
+                if (hv) {
+                    heavy_col(j);
                 } else {
-                    // run of leafless columns [j, jb), one lane per prime: an
-                    // integer n = p k unsieved at the start of the run is first
-                    // removed by p exactly when k = 1 or k >= p
-                    uint32_t jb = jend;
-                    {
-                        uint32_t wv = j >> 6;
-                        uint64_t msk = c_leafy[wv] & (~0ull << (j & 63));
-                        while (!msk && ++wv < (jend + 63) / 64)
-                            msk = c_leafy[wv];
-                        if (msk)
-                            jb = min(jend, wv * 64 + (uint32_t)__builtin_ctzll(msk));
-                    }
-                    const uint32_t jj = j + tid;
-                    const bool mine_col = jj < jb;
-                    uint32_t i0 = S, p = 0;
-                    if (mine_col) {
-                        i0 = c_i0[jj];
-                        p = c_p[jj];
-                        uint32_t credit = 0;
-                        const uint64_t p2 = (uint64_t)p * p;
-                        for (uint32_t bit = i0; bit < S; bit += p)
-                            if ((BW(bit >> 5) >> (bit & 31)) & 1) {
-                                const uint64_t nn = lo + 2ull * bit + 1;
-                                if (nn == p || nn >= p2) {
-                                    credit++;
-                                    fen_dec(bit >> BL);
-                                }
-                            }
-                        c_new[jj] = credit;
-                    }
-                    __syncthreads(); // every read of the run precedes every clear
-                    if (mine_col)
-                        for (uint32_t bit = i0; bit < S; bit += p)
-                            __hip_atomic_fetch_and(&BW(bit >> 5), ~(1u << (bit & 31)),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __syncthreads();
-                    j = jb;
+                    if (!(c_lc[j] & GATH))
+                        gather(j);
+                    answer(j);
+                }
+            } else if (BATCH && j >= first_large) {
+                if (jb_next <= j) { // the next leafy column at or after j
+                    uint32_t wd = j >> 6;
+                    uint64_t msk = c_leafy[wd] & (~0ull << (j & 63));
+                    while (!msk && ++wd < (jend + 63) / 64)
+                        msk = c_leafy[wd];
+                    jb_next = msk ? min(jend, wd * 64 + (uint32_t)__builtin_ctzll(msk)) : jend;
+                }
+                if (jb_next - j >= GAPB) {
+                    batch(j, jb_next);
+                    j = jb_next;
+                    continue;
                 }
             }
-        } else {
-            __syncthreads(); // c_new complete
+            cross_region(j);
+            j++;
         }
+        flush_removed();
+        PC_PH(4);
+        __syncthreads(); // c_new complete
         // --- chunk results: cnt before each crossing, and w ---
         {
             const uint32_t v = tid < jend ? c_new[tid] : 0;
@@ -525,19 +644,20 @@ __global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
                         A.cnt[idx] = total - ex;
                     if (MODE == PC_MODE_TALLY)
                         A.wgt[idx] = c_w[tid];
+                    if (MODE == PC_MODE_LEAVES && c_w[tid] != 0)
+                        acc_carry += (pc_s128)c_w[tid] * (pc_s128)A.carry[idx];
                 }
             }
             total -= tot;
         }
+        PC_PH(7);
     }
 
     // --- final column: P2 lookups pi(x/p) = phi(x/p, bmax) + bmax - 1 ---
     pc_s128 extra_p2 = 0; // PC_MODE_LEAVES: carry * (lookups), kept by thread 0
     if (col_hi == ncol) {
-        if (!fen_ok) {
-            __syncthreads();
-            build_pre();
-        }
+        __syncthreads();
+        build_pre();
         uint32_t k1 = 1, k2 = 0;
         {
             const uint64_t tA = pc_div(Q.x, hi, rhi);              // x/p < hi  <=> p > x/hi
@@ -556,8 +676,7 @@ __global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
                     atomicOr(A.err, 4);
                     continue;
                 }
-                const uint32_t q = (uint32_t)((v - lo + 1) >> 1);
-                acc_p2 += fen_ok ? count_fen(q) : count_pre(q);
+                acc_p2 += count_pre((uint32_t)((v - lo + 1) >> 1));
             }
         if (tid == 0) {
             const uint64_t idx = row * ncol + Q.nb;
@@ -578,15 +697,24 @@ __global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
         if (lane == 0 && nleaf)
             atomicAdd(&Q.sums->n_hard, nleaf);
         if (A.trace) {
+            uint32_t *tr = A.trace + (size_t)blockIdx.x * PC_TRACE_W;
             const uint32_t nc = pc_wave_sum_u32(n_cand);
+            const uint32_t nl = pc_wave_sum_u32(n_leafy);
+            const uint32_t ns = pc_wave_sum_u32(n_leafy_small);
             if (lane == 0) {
-                atomicAdd(&A.trace[blockIdx.x].y, (uint32_t)nleaf);
-                atomicAdd(&A.trace[blockIdx.x].z, nc);
+                atomicAdd(&tr[1], (uint32_t)nleaf);
+                atomicAdd(&tr[2], nc);
+                atomicAdd(&tr[3], nl);
+                atomicAdd(&tr[4], ns);
             }
             __syncthreads();
+            PC_PH(8);
             if (tid == 0) {
-                A.trace[blockIdx.x].w = n_leafy;
-                A.trace[blockIdx.x].x = (uint32_t)(__builtin_amdgcn_s_memrealtime() - t_start);
+                tr[0] = (uint32_t)(__builtin_amdgcn_s_memrealtime() - t_start);
+#if PC_PHASE_TRACE
+                for (int k = 0; k < 9; k++)
+                    tr[5 + k] = ph[k];
+#endif
             }
         }
         if (tid == 0) {
@@ -595,6 +723,7 @@ __global__ __launch_bounds__(T) void k_sieve(pc_sieve_args A)
         }
     }
 }
+#undef PC_PH
 
 // ---------------------------------------------------------------------------
 // Look-back scan over the segments of a window, independently per column:
