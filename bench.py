@@ -25,13 +25,38 @@ METRIC = "S2 special leaves/s + π(x) wall time at x=1e18; batched queries/s, p5
 X = 10**18
 PI_1E18 = 24739954287740860  # Table 1 of the paper
 
-# MI355X: 256 CUs at 2.4 GHz; LDS 64 banks x 4 bytes per CU per clock.
-CUS, CLOCK_HZ, LDS_DWORDS_PER_CLK = 256, 2.4e9, 64
-LDS_PEAK_OPS = CUS * CLOCK_HZ * LDS_DWORDS_PER_CLK  # 32-bit LDS read-modify-writes per second
+# MI355X: 256 CUs of 64 lanes at 2.4 GHz: one 32-bit integer operation per lane
+# per clock (the sieve is integer work; no matrix cores, no packed math).
+CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
+INT_PEAK = CUS * LANES * CLOCK_HZ  # 32-bit integer lane operations per second
 
-# Bounded oracle sample of the same workload (alpha = 8): the special leaves
-# with 1000 <= b < 2500, hard ones with u <= 1e7.
-CPU_SAMPLE = dict(y=8000000, c=6, b_lo=1000, b_hi=2500, u_max=10**7)
+# Algorithmic integer operations of the sieve kernel, per unit of work:
+#   crossing an odd multiple of p_b: address, mask, one LDS read-modify-write
+#   placing prime p_b in a segment: first multiple by multiply-high reciprocal
+#   a hard leaf or a P2 lookup: 64/32 division by reciprocal (about 12), a
+#   prefix-table read with a masked popcount (4), the signed add (2)
+OPS_CROSSING, OPS_VISIT, OPS_LEAF = 3, 8, 18
+
+# Bounded oracle sample of the same workload (alpha = 16, the library's choice
+# at 1e18): the special leaves with 1000 <= b < 1250, hard ones with u <= 5e7.
+CPU_SAMPLE = dict(y=16000000, c=6, b_lo=1000, b_hi=1250, u_max=5 * 10**7)
+
+# HBM traffic of the sieve kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# scaled by the same counters on a plain copy of known size; reported only while
+# the kernel source is the one the counters were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sieve_traffic_1e18.txt")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1503_01839_amd", "csrc", f)
+              for f in ("pc_sieve.hip", "pc_leafrange.h", "pc_block.h", "pc_device.h",
+                        "pc_internal.h")]
+
+
+def kernel_sha256():
+    """Hash of the sources the sieve kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def sync():
@@ -43,6 +68,32 @@ def sync():
         pass
 
 
+def traffic_bytes(launches):
+    """HBM bytes per sieve launch from the committed counter summary, or None
+    when there is none or the kernel source has changed since."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line)
+    except OSError:
+        return None
+    if kv.get("kernel_sha256", "").strip() != kernel_sha256():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes):
+    """One plain device-to-device copy of nbytes (for scaling HBM counters)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}), flush=True)
+
+
 def cpu_baseline():
     import oracle
     s = CPU_SAMPLE
@@ -51,7 +102,7 @@ def cpu_baseline():
     dt = time.perf_counter() - t0
     leaves = d.n_trivial + d.n_easy + d.n_hard
     return {"value": leaves / dt, "unit": "special leaves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"pi(1e18), alpha=8 (y={s['y']}): special leaves with "
+            "sample": (f"pi(1e18), alpha=16 (y={s['y']}): special leaves with "
                        f"{s['b_lo']} <= b < {s['b_hi']}, hard leaves only for u <= {s['u_max']} "
                        f"({d.n_easy} easy + {d.n_hard} hard + {d.n_trivial} trivial) "
                        f"in {dt:.2f} s, single-threaded C oracle")}
@@ -68,7 +119,12 @@ def main():
     ap.add_argument("--keep-tables", action="store_true",
                     help="reuse device tables across steps (default: rebuild every step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(pi(x) shards by segment range, see DESIGN.md); rerun with --gpus 1",
@@ -98,17 +154,22 @@ def main():
     leaves = r.n_trivial + r.n_easy + r.n_hard
     value = leaves / (ms_step / 1e3)
 
-    # roofline of the dominant kernel (the sieve): LDS bit-crossings
+    # roofline of the dominant kernel (the sieve): algorithmic integer operations
     k_ms = sum(q.ms_k_sieve for q in results) / len(results)
     launches = r.sieve_launches
     avg_launch_ms = k_ms / max(launches, 1)
-    crossings_per_launch = r.crossings / max(launches, 1)
-    achieved = crossings_per_launch / (avg_launch_ms / 1e3)
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": LDS_PEAK_OPS / 1e12,
-            "unit": "T LDS-RMW/s", "frac": achieved / LDS_PEAK_OPS, "traffic": None,
+    visits = r.segments * (r.bmax - r.c)
+    ops = (OPS_CROSSING * r.crossings + OPS_VISIT * visits + OPS_LEAF * (r.n_hard + r.n_p2))
+    ops_per_launch = ops / max(launches, 1)
+    achieved = ops_per_launch / (avg_launch_ms / 1e3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK / 1e12,
+            "unit": "T int-ops/s", "frac": achieved / INT_PEAK, "traffic": traffic_bytes(launches),
             "kernel": "k_sieve", "launches": launches, "avg_launch_ms": avg_launch_ms,
-            "work_per_launch": crossings_per_launch,
-            "work": "odd multiples of p_{c+1}..p_bmax crossed in LDS (one 32-bit RMW each)"}
+            "ops_per_launch": ops_per_launch,
+            "work": {"crossings": r.crossings, "prime_visits": visits, "hard_leaves": r.n_hard,
+                     "p2_lookups": r.n_p2,
+                     "ops_per_unit": {"crossing": OPS_CROSSING, "visit": OPS_VISIT,
+                                      "leaf": OPS_LEAF}}}
 
     out = {
         "metric": METRIC, "value": value, "unit": "special leaves/s", "n_gpus": 1,

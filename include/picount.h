@@ -60,17 +60,17 @@ typedef struct {
     double alpha;          /* y = alpha * icbrt(x), clamped to [icbrt x, isqrt x]; 0 = tuned */
     uint32_t segment_kib;  /* LDS bitmap per sieve segment: 32 or 64                       */
     uint32_t wg_size;      /* sieve workgroup: 256|512 (32 KiB segments), 512|1024 (64)   */
-    uint32_t tile_leaves;  /* hard-leaf budget per sieve tile (hot-segment splitting); 0 = auto, 0xFFFFFFFF = off */
+    uint32_t tile_leaves;  /* leaf items per sieve tile (hot segments split by columns); 0 = 2^21, 0xFFFFFFFF = off */
     uint32_t flags;        /* PC_FLAG_* below */
     uint64_t carry_budget; /* bytes for per-(segment, prime) counts per window; 0 = auto  */
-    uint32_t small_span;   /* one-wavefront segments cover [0, small_span * y); 0 = auto   */
+    uint32_t small_span;   /* one-wavefront segments cover [0, small_span * y); 0 = none    */
     uint32_t small_kib;    /* size of those segments: 4 or 8 KiB; 0 = auto                  */
 } pc_config;
 
 #define PC_FLAG_TWO_PASS 1u      /* count pass, carry scan, then leaf pass (else one tally pass) */
 #define PC_FLAG_NO_BATCH_LARGE 2u /* cross large primes one at a time (no batched crossing)     */
 #define PC_FLAG_REBUILD_TABLES 4u /* drop cached tables and rebuild them inside this call       */
-#define PC_FLAG_NO_SMALL_SEGMENTS 8u /* sieve the leaf-dense low end with workgroup segments too  */
+#define PC_FLAG_NO_SMALL_SEGMENTS 8u /* no one-wavefront segments even if small_span is set        */
 
 /* Everything one pi(x) evaluation produced, for tests and measurement. */
 typedef struct {
@@ -84,7 +84,11 @@ typedef struct {
     uint64_t crossings;             /* odd multiples of p_{c+1}..p_bmax below the sieve end */
     uint64_t device_bytes;          /* peak device bytes held by the library        */
     uint32_t sieve_launches, scan_launches;
-    double ms_total, ms_tables, ms_leaves, ms_sieve;   /* host wall clock per phase   */
+    /* ms_total, ms_tables, ms_sieve: host wall clock of the call, of the table
+     * build and from the sieve's start to the result.  ms_leaves: GPU time from
+     * the start of S1 to the end of the easy leaves, which run on a second
+     * stream concurrently with the sieve. */
+    double ms_total, ms_tables, ms_leaves, ms_sieve;
     double ms_k_sieve, ms_k_scan, ms_k_easy, ms_k_s1;  /* kernel time, HIP events     */
 } pc_result;
 

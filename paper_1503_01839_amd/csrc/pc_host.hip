@@ -46,12 +46,15 @@ struct DevBuf {
 
 size_t g_dev_bytes = 0, g_dev_peak = 0;
 
-hipStream_t g_stream = nullptr;
+hipStream_t g_stream = nullptr;  // the library stream
+hipStream_t g_stream2 = nullptr; // easy leaves, concurrent with the sieve (same priority)
 
 void dfree(DevBuf &b)
 {
     if (b.p) {
-        if (g_stream) // kernels queued earlier may still read the buffer
+        if (g_stream2) // kernels queued earlier may still read the buffer
+            (void)hipStreamSynchronize(g_stream2);
+        if (g_stream)
             (void)hipStreamSynchronize(g_stream);
         (void)hipFree(b.p);
         g_dev_bytes -= b.cap;
@@ -109,10 +112,18 @@ struct QueryBufs {
 };
 QueryBufs g_Q;
 
+hipEvent_t g_fork = nullptr, g_join = nullptr;
+
 void init_stream()
 {
     if (!g_stream)
         hipck(hipStreamCreateWithFlags(&g_stream, hipStreamNonBlocking), "hipStreamCreate");
+    if (!g_stream2)
+        hipck(hipStreamCreateWithFlags(&g_stream2, hipStreamNonBlocking), "hipStreamCreate");
+    if (!g_fork)
+        hipck(hipEventCreateWithFlags(&g_fork, hipEventDisableTiming), "hipEventCreate");
+    if (!g_join)
+        hipck(hipEventCreateWithFlags(&g_join, hipEventDisableTiming), "hipEventCreate");
 }
 
 // pi at a few points, read back to the host (planning only).
@@ -317,10 +328,10 @@ struct Knobs {
     bool two_pass = false;
     bool batch = true;
     uint64_t carry_budget = 6ull << 30;
-    uint64_t tile_leaves = 0;    // hard-leaf items per tile; 0 = no column splitting
-    uint32_t hot_log2 = 15;      // small one-wavefront segments below hot_span * y
+    uint64_t tile_leaves = 1u << 21; // hard-leaf items per tile; 0 = no column splitting
+    uint32_t hot_log2 = 15;          // small one-wavefront segments below hot_span * y
     uint32_t hot_wg = 64;
-    uint64_t hot_span = 64;      // 0 = no small segments
+    uint64_t hot_span = 0;           // 0 = no small segments (the measured best at every size)
 };
 
 Knobs knobs_from(const pc_config *cfg)
@@ -351,8 +362,8 @@ Knobs knobs_from(const pc_config *cfg)
     default:
         fail(PC_EINVAL, "wg_size must be 256, 512 or 1024");
     }
-    // supported (segment, workgroup) shapes: each thread owns whole 512-bit blocks
-    // while crossing small primes, and the LDS image must fit in 160 KiB
+    // supported (segment, workgroup) shapes: each thread counts one or two whole
+    // 512-bit blocks, and the LDS image must fit in 160 KiB
     const bool ok = (k.seg_log2 == 18 && (k.wg == 256 || k.wg == 512)) ||
                     (k.seg_log2 == 19 && (k.wg == 512 || k.wg == 1024));
     if (!ok)
@@ -404,13 +415,15 @@ EvPair &ev_next()
     return g_ev[g_ev_used++];
 }
 
-// time the launches made by f on the library stream; returns the event pair index
-template <typename F> size_t timed(F &&f)
+// time the launches made by f on stream st; returns the event pair index
+template <typename F> size_t timed(F &&f, hipStream_t st = nullptr)
 {
+    if (!st)
+        st = g_stream;
     EvPair &e = ev_next();
-    hipck(hipEventRecord(e.a, g_stream), "hipEventRecord");
+    hipck(hipEventRecord(e.a, st), "hipEventRecord");
     f();
-    hipck(hipEventRecord(e.b, g_stream), "hipEventRecord");
+    hipck(hipEventRecord(e.b, st), "hipEventRecord");
     return g_ev_used - 1;
 }
 
@@ -586,15 +599,30 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     hipck(pc_launch_scan_u64(ptr<uint64_t>(B.e_off), a + 1, ptr<uint64_t>(B.e_tmp),
                              ptr<uint64_t>(B.e_total), g_stream),
           "easy scan");
-    const size_t ev_easy = timed([&] {
-        hipck(pc_launch_easy(T, Q, ptr<uint64_t>(B.e_start), ptr<uint64_t>(B.e_count),
-                             ptr<uint64_t>(B.e_off), ptr<uint64_t>(B.e_total),
-                             ptr<pc_s128>(B.part), ez_blocks, g_stream),
-              "easy");
-    });
-    hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ez_blocks, &sums->s2e, g_stream), "S2e sum");
-    hipck(hipStreamSynchronize(g_stream), "sync");
-    const double ms_leaves = ms_since(t1);
+    // The easy leaves touch nothing the sieve writes: they run on the second
+    // stream, launched once the first sieve window is queued (the tile plan
+    // before it needs the GPU to itself), and rejoin before the combination.
+    size_t ev_easy = 0;
+    bool forked = false;
+    auto fork_easy = [&]() {
+        if (forked)
+            return;
+        forked = true;
+        hipck(hipEventRecord(g_fork, g_stream), "hipEventRecord");
+        hipck(hipStreamWaitEvent(g_stream2, g_fork, 0), "hipStreamWaitEvent");
+        ev_easy = timed(
+            [&] {
+                hipck(pc_launch_easy(T, Q, ptr<uint64_t>(B.e_start), ptr<uint64_t>(B.e_count),
+                                     ptr<uint64_t>(B.e_off), ptr<uint64_t>(B.e_total),
+                                     ptr<pc_s128>(B.part), ez_blocks, g_stream2),
+                      "easy");
+            },
+            g_stream2);
+        hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ez_blocks, &sums->s2e, g_stream2),
+              "S2e sum");
+        hipck(hipEventRecord(g_join, g_stream2), "hipEventRecord");
+    };
+    (void)t1;
 
     // --- the sieve of [1, z] in windows of segments ---
     auto t2 = clk::now();
@@ -721,6 +749,7 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         const int first = K.two_pass ? PC_MODE_COUNT : PC_MODE_TALLY;
         sieve(true, first);
         sieve(false, first);
+        fork_easy();
 
         pc_scan_args SA{};
         SA.cnt = ptr<uint32_t>(B.cnt);
@@ -762,6 +791,8 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     }
     if (trace_file)
         std::fclose(trace_file);
+    fork_easy();
+    hipck(hipStreamWaitEvent(g_stream, g_join, 0), "hipStreamWaitEvent");
     hipck(pc_launch_combine(sums, Q, kx, ptr<pc_final>(B.fin), g_stream), "combine");
     pc_final fin{};
     pc_sums hs{};
@@ -809,7 +840,9 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         res->device_bytes = g_dev_peak;
         res->ms_total = ms_since(t0);
         res->ms_tables = ms_tables;
-        res->ms_leaves = ms_leaves;
+        float ms_lv = 0; // S1 start to the end of the easy leaves (GPU clock)
+        hipck(hipEventElapsedTime(&ms_lv, g_ev[ev_s1].a, g_ev[ev_easy].b), "hipEventElapsedTime");
+        res->ms_leaves = ms_lv;
         res->ms_sieve = ms_sieve;
         res->ms_k_s1 = ev_ms(ev_s1);
         res->ms_k_easy = ev_ms(ev_easy);
@@ -1013,10 +1046,20 @@ void pc_shutdown(void)
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     drop_tables();
     drop_query_bufs();
+    if (g_stream2) {
+        (void)hipStreamSynchronize(g_stream2);
+        (void)hipStreamDestroy(g_stream2);
+        g_stream2 = nullptr;
+    }
     if (g_stream) {
         (void)hipStreamDestroy(g_stream);
         g_stream = nullptr;
     }
+    for (hipEvent_t *e : {&g_fork, &g_join})
+        if (*e) {
+            (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
     g_dev_peak = g_dev_bytes;
 }
 

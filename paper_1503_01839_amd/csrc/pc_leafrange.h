@@ -1,0 +1,62 @@
+// pc_leafrange.h -- the hard special leaves of one sieving prime that land in
+// one segment (Sections 2.3 and 3 of the paper): shared by the sieve kernel and
+// the tile planner.
+#pragma once
+
+#include "pc_device.h"
+#include "pc_internal.h"
+
+#define PC_CAND 0x80000000u
+
+// The hard leaves (b, m) whose u = floor(X_b/m) lies in [lo, hi): special
+// (y/p_b < m <= y, lpf(m) > p_b) and hard (m <= max(x/p^3, x/(p(y+1)))).
+// For p_b^2 > y every such m is prime and the range is returned as prime
+// indices [ls, ls + lc); otherwise as candidate m values, lc | PC_CAND.
+__device__ __forceinline__ void pc_leaf_mrange(const pc_query &Q, uint32_t b, uint64_t p,
+                                               uint64_t rp, uint64_t lo, uint64_t hi,
+                                               uint64_t rhi, uint64_t rlo, uint64_t *m1o,
+                                               uint64_t *m2o)
+{
+    const uint64_t X = Q.Xb[b];
+    const uint64_t mA = pc_div(X, hi, rhi) + 1;            // u < hi   <=> m > X/hi
+    const uint64_t mB = lo ? pc_div(X, lo, rlo) : X;        // u >= lo  <=> m <= X/lo
+    uint64_t m1 = pc_div(Q.y, p, rp) + 1;
+    if (m1 < mA)
+        m1 = mA;
+    if (m1 < p + 1)
+        m1 = p + 1;
+    const uint64_t h1 = pc_div(pc_div(X, p, rp), p, rp);
+    const uint64_t h2 = pc_div(X, Q.y1, Q.recip_y1);
+    uint64_t m2 = h1 > h2 ? h1 : h2;
+    if (m2 > Q.y)
+        m2 = Q.y;
+    if (m2 > mB)
+        m2 = mB;
+    *m1o = m1;
+    *m2o = m2;
+}
+
+__device__ __forceinline__ void pc_leaf_range(const pc_tables &TB, const pc_query &Q, uint32_t b,
+                                              uint64_t p, uint64_t rp, uint64_t lo, uint64_t hi,
+                                              uint64_t rhi, uint64_t rlo, uint32_t *ls,
+                                              uint32_t *lc)
+{
+    uint64_t m1, m2;
+    pc_leaf_mrange(Q, b, p, rp, lo, hi, rhi, rlo, &m1, &m2);
+    *ls = 0;
+    *lc = 0;
+    if (m1 <= m2) {
+        if (p > Q.sqrty) {
+            const uint32_t k1 = pc_pi_lookup(TB.pitab, m1 - 1) + 1;
+            const uint32_t k2 = pc_pi_lookup(TB.pitab, m2);
+            if (k1 <= k2) {
+                *ls = k1;
+                *lc = k2 - k1 + 1;
+            }
+        } else {
+            *ls = (uint32_t)m1;
+            *lc = (uint32_t)(m2 - m1 + 1) | PC_CAND;
+        }
+    }
+}
+

@@ -30,55 +30,13 @@
 // without ordering the lanes.
 #include "pc_block.h"
 #include "pc_internal.h"
-
-#define PC_CAND 0x80000000u
+#include "pc_leafrange.h"
 
 // PC_PHASE_TRACE=1 adds per-phase tick counters to the tile trace (a
 // profiling build; the default build only records totals)
 #ifndef PC_PHASE_TRACE
 #define PC_PHASE_TRACE 0
 #endif
-
-// The hard leaves (b, m) whose u = floor(X_b/m) lies in [lo, hi): special
-// (y/p_b < m <= y, lpf(m) > p_b) and hard (m <= max(x/p^3, x/(p(y+1)))).
-// For p_b^2 > y every such m is prime and the range is returned as prime
-// indices [ls, ls + lc); otherwise as candidate m values, lc | PC_CAND.
-__device__ __forceinline__ void pc_leaf_range(const pc_tables &TB, const pc_query &Q, uint32_t b,
-                                              uint64_t p, uint64_t rp, uint64_t lo, uint64_t hi,
-                                              uint64_t rhi, uint64_t rlo, uint32_t *ls,
-                                              uint32_t *lc)
-{
-    const uint64_t X = Q.Xb[b];
-    const uint64_t mA = pc_div(X, hi, rhi) + 1;            // u < hi   <=> m > X/hi
-    const uint64_t mB = lo ? pc_div(X, lo, rlo) : X;        // u >= lo  <=> m <= X/lo
-    uint64_t m1 = pc_div(Q.y, p, rp) + 1;
-    if (m1 < mA)
-        m1 = mA;
-    if (m1 < p + 1)
-        m1 = p + 1;
-    const uint64_t h1 = pc_div(pc_div(X, p, rp), p, rp);
-    const uint64_t h2 = pc_div(X, Q.y1, Q.recip_y1);
-    uint64_t m2 = h1 > h2 ? h1 : h2;
-    if (m2 > Q.y)
-        m2 = Q.y;
-    if (m2 > mB)
-        m2 = mB;
-    *ls = 0;
-    *lc = 0;
-    if (m1 <= m2) {
-        if (p > Q.sqrty) {
-            const uint32_t k1 = pc_pi_lookup(TB.pitab, m1 - 1) + 1;
-            const uint32_t k2 = pc_pi_lookup(TB.pitab, m2);
-            if (k1 <= k2) {
-                *ls = k1;
-                *lc = k2 - k1 + 1;
-            }
-        } else {
-            *ls = (uint32_t)m1;
-            *lc = (uint32_t)(m2 - m1 + 1) | PC_CAND;
-        }
-    }
-}
 
 // Waves per SIMD that the LDS footprint of k_sieve<LOG2_S, T, CH> allows on a
 // CU (160 KiB of LDS, at most 8 waves per SIMD); the kernel asks the compiler
@@ -813,117 +771,6 @@ template <int MODE> __global__ __launch_bounds__(SCAN_T) void k_scan(pc_scan_arg
             A.part_p2[tk] = dp;
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// Tile planning.  k_seg_work: hard-leaf items (primes m, or candidate m) that
-// segment seg0 + blockIdx.x will answer, summed over every column.
-// k_seg_split: for segment hot[i].x cut into hot[i].y tiles of about equal
-// leaf work, the column boundaries (hot[i].y + 1 of them) at bounds[off_i].
-// ---------------------------------------------------------------------------
-#define PL_T 256
-
-template <int LOG2_S>
-__device__ __forceinline__ uint32_t pc_col_items(const pc_tables &TB, const pc_query &Q,
-                                                 uint32_t col, uint64_t lo, uint64_t hi,
-                                                 uint64_t rhi, uint64_t rlo)
-{
-    const uint32_t b = Q.c + 1 + col;
-    const uint64_t p = TB.primes[b];
-    uint32_t ls, lc;
-    pc_leaf_range(TB, Q, b, p, TB.recip[b], lo, hi, rhi, rlo, &ls, &lc);
-    return lc & ~PC_CAND;
-}
-
-template <int LOG2_S>
-__global__ __launch_bounds__(PL_T) void k_seg_work(pc_tables TB, pc_query Q, uint64_t seg0,
-                                                   uint64_t lo_base, uint64_t seg_base,
-                                                   uint64_t *work)
-{
-    __shared__ uint64_t scr[PL_T / 64];
-    const uint64_t seg = seg0 + blockIdx.x;
-    const uint64_t lo = lo_base + ((seg - seg_base) << (LOG2_S + 1)), hi = lo + (2ull << LOG2_S);
-    const uint64_t rhi = pc_recip(hi), rlo = lo ? pc_recip(lo) : 0;
-    uint64_t s = 0;
-    for (uint32_t col = threadIdx.x; col < Q.nb; col += PL_T)
-        s += pc_col_items<LOG2_S>(TB, Q, col, lo, hi, rhi, rlo);
-    s = pc_block_sum<PL_T>(s, scr);
-    if (threadIdx.x == 0)
-        work[blockIdx.x] = s;
-}
-
-template <int LOG2_S>
-__global__ __launch_bounds__(PL_T) void k_seg_split(pc_tables TB, pc_query Q, const uint4 *hot,
-                                                    uint64_t lo_base, uint64_t seg_base,
-                                                    uint32_t *bounds)
-{
-    __shared__ uint64_t scr[PL_T / 64];
-    const uint4 h = hot[blockIdx.x]; // x = segment, y = tiles K, z = offset, w = unused
-    const uint64_t seg = h.x;
-    const uint64_t lo = lo_base + ((seg - seg_base) << (LOG2_S + 1)), hi = lo + (2ull << LOG2_S);
-    const uint64_t rhi = pc_recip(hi), rlo = lo ? pc_recip(lo) : 0;
-    // total, then boundaries where the running work crosses j * total / K
-    uint64_t tot = 0;
-    for (uint32_t col = threadIdx.x; col < Q.nb; col += PL_T)
-        tot += pc_col_items<LOG2_S>(TB, Q, col, lo, hi, rhi, rlo);
-    tot = pc_block_sum<PL_T>(tot, scr);
-    const uint64_t K = h.y;
-    uint32_t *bd = bounds + h.z;
-    if (threadIdx.x == 0) {
-        bd[0] = 0;
-        bd[K] = Q.ncol;
-    }
-    uint64_t run = 0;
-    for (uint32_t c0 = 0; c0 < Q.nb; c0 += PL_T) {
-        const uint32_t col = c0 + threadIdx.x;
-        const uint64_t v = col < Q.nb ? pc_col_items<LOG2_S>(TB, Q, col, lo, hi, rhi, rlo) : 0;
-        uint64_t chunk;
-        const uint64_t e = run + pc_block_excl_scan<PL_T>(v, scr, &chunk);
-        // tile j >= 1 starts at the first column whose exclusive prefix reaches j*tot/K
-        if (col < Q.nb && tot > 0) {
-            const uint64_t i = e + v;
-            uint64_t j0 = (e * K) / tot + 1;     // smallest j with j*tot > e*K ... candidates
-            for (uint64_t j = j0; j < K && j * tot <= i * K; j++)
-                bd[j] = col + 1;
-        }
-        run += chunk;
-    }
-}
-
-hipError_t pc_launch_seg_work(const pc_tables &T, const pc_query &Q, uint32_t seg_log2,
-                              uint64_t lo_base, uint64_t seg_base, uint64_t seg0, uint32_t nseg,
-                              uint64_t *work, hipStream_t s)
-{
-    if (nseg == 0)
-        return hipSuccess;
-    switch (seg_log2) {
-    case 15: k_seg_work<15><<<nseg, PL_T, 0, s>>>(T, Q, seg0, lo_base, seg_base, work); break;
-    case 16: k_seg_work<16><<<nseg, PL_T, 0, s>>>(T, Q, seg0, lo_base, seg_base, work); break;
-    case 17: k_seg_work<17><<<nseg, PL_T, 0, s>>>(T, Q, seg0, lo_base, seg_base, work); break;
-    case 18: k_seg_work<18><<<nseg, PL_T, 0, s>>>(T, Q, seg0, lo_base, seg_base, work); break;
-    case 19: k_seg_work<19><<<nseg, PL_T, 0, s>>>(T, Q, seg0, lo_base, seg_base, work); break;
-    case 20: k_seg_work<20><<<nseg, PL_T, 0, s>>>(T, Q, seg0, lo_base, seg_base, work); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t pc_launch_seg_split(const pc_tables &T, const pc_query &Q, uint32_t seg_log2,
-                               uint64_t lo_base, uint64_t seg_base, const uint4 *hot,
-                               uint32_t nhot, uint32_t *bounds, hipStream_t s)
-{
-    if (nhot == 0)
-        return hipSuccess;
-    switch (seg_log2) {
-    case 15: k_seg_split<15><<<nhot, PL_T, 0, s>>>(T, Q, hot, lo_base, seg_base, bounds); break;
-    case 16: k_seg_split<16><<<nhot, PL_T, 0, s>>>(T, Q, hot, lo_base, seg_base, bounds); break;
-    case 17: k_seg_split<17><<<nhot, PL_T, 0, s>>>(T, Q, hot, lo_base, seg_base, bounds); break;
-    case 18: k_seg_split<18><<<nhot, PL_T, 0, s>>>(T, Q, hot, lo_base, seg_base, bounds); break;
-    case 19: k_seg_split<19><<<nhot, PL_T, 0, s>>>(T, Q, hot, lo_base, seg_base, bounds); break;
-    case 20: k_seg_split<20><<<nhot, PL_T, 0, s>>>(T, Q, hot, lo_base, seg_base, bounds); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
 }
 
 hipError_t pc_launch_scan(const pc_scan_args &A, int mode, hipStream_t s)

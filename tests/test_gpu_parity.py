@@ -81,10 +81,11 @@ def test_config_invariance(pc, seg, wg):
     for x, y in [(10**11, 4641), (10**12, 20000), (10**10 + 12345, 4000)]:
         say("case: invariance", x, y, seg, wg)
         o = O.decompose(x, y, 6, hard=O.HARD_SIEVE)
-        for flags in (0, pc.FLAG_NO_BATCH_LARGE, pc.FLAG_TWO_PASS, pc.FLAG_NO_SMALL_SEGMENTS,
-                      pc.FLAG_TWO_PASS | pc.FLAG_NO_SMALL_SEGMENTS):
-            r = pc.decompose(x, y, segment_kib=seg, wg_size=wg, flags=flags)
-            assert (r.s2_hard, r.p2, r.pi) == (o.s2h, o.p2, o.pi), (x, y, seg, wg, flags)
+        for kw in (dict(flags=0), dict(flags=pc.FLAG_NO_BATCH_LARGE), dict(flags=pc.FLAG_TWO_PASS),
+                   dict(small_span=64), dict(flags=pc.FLAG_TWO_PASS, small_span=64),
+                   dict(tile_leaves=0xFFFFFFFF), dict(tile_leaves=2048)):
+            r = pc.decompose(x, y, segment_kib=seg, wg_size=wg, **kw)
+            assert (r.s2_hard, r.p2, r.pi) == (o.s2h, o.p2, o.pi), (x, y, seg, wg, kw)
 
 
 def test_windows(pc):
@@ -150,12 +151,12 @@ def test_tile_split_invariance(pc, tile_leaves, paper_pow10):
     for (x, y) in [(10**12, 10**4), (10**13, 21544), (10**12, 80000)]:
         say("case: split", x, y, tile_leaves)
         rec = recs[(x, y)]
-        for flags in (0, pc.FLAG_NO_SMALL_SEGMENTS):
-            r = pc.decompose(x, y, tile_leaves=tile_leaves, flags=flags)
+        for span in (0, 64):
+            r = pc.decompose(x, y, tile_leaves=tile_leaves, small_span=span)
             assert (r.s2_hard, r.p2, r.pi) == (rec["s2h"], rec["p2"], rec["pi"]), \
-                (x, y, tile_leaves, flags)
+                (x, y, tile_leaves, span)
             assert r.n_hard == rec["n_hard"]
-            if tile_leaves == 512 and flags:
+            if tile_leaves == 512 and not span:
                 assert r.tiles > r.segments
     say("case: split 1e15", tile_leaves)
     assert pc.pi_count_ex(10**15, tile_leaves=tile_leaves).pi == paper_pow10[15]
