@@ -50,8 +50,10 @@ template <int LOG2_S, int T, int CH> constexpr int pc_sieve_waves_per_simd()
 {
     constexpr long S = 1l << LOG2_S, NW = S / 32, NWP = NW + NW / 16, NBLK = S >> 9;
     constexpr long NWV = T / 64;
+    constexpr long KMAX = 64; // gathered columns per round (g_rc, g_rm)
     constexpr long lds = 4 * (NWP + 16) + 4 * (NBLK + 1) + 4 * pc_sieve_gcap<LOG2_S, T, CH>() +
-                         24 * CH + 16 * (CH / 64) + 12 + 8 * NWV + 16 * NWV;
+                         2 * KMAX * NWV + 4 * KMAX + 24 * CH + 16 * (CH / 64) + 16 + 8 * NWV +
+                         16 * NWV;
     constexpr long wg = 163840 / lds;
     constexpr long waves = wg * NWV < 32 ? wg * NWV : 32;
     return waves / 4 < 1 ? 1 : (int)(waves / 4);
@@ -77,14 +79,20 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     constexpr uint32_t GCAP = pc_sieve_gcap<LOG2_S, T, CH>(); // gathered leaf items
     constexpr uint32_t LIGHT = GCAP / 2; // more leaf items: the column is answered workgroup-wide
     constexpr uint32_t GAPB = 8;         // leafless large-prime columns worth one batched crossing
-    constexpr uint32_t GATH = 0x40000000u; // c_lc: leaves gathered, (offset << 12) | count
+    constexpr uint32_t KMAX = 64;         // columns per gather round (as in pc_sieve_waves_per_simd)
+    // c_lc of a gathered column: GATH | ordinal k << 22 | slot offset << 11 | count
+    // (GATH is not PC_CAND: a column not yet gathered keeps its PC_CAND bit)
+    constexpr uint32_t GATH = 0x40000000u;
+    static_assert(GCAP < 2048 && LIGHT < 2048 && KMAX <= 128, "gathered-column fields");
 
     // Word w of the segment lives at bm[w + w/16]: the 16 words of a counting
     // block are contiguous and consecutive blocks start 17 words apart, so the
     // threads of a wavefront walking their own blocks hit distinct banks.
     __shared__ uint32_t bm[NWP + 16];  // 16 spare words: a query at q = S reads past the end
     __shared__ uint32_t pre[NBLK + 1]; // prefix of the block counts; in a gather, slot offsets
-    __shared__ uint32_t gbuf[GCAP];    // gathered leaves: q << 2 | (mu(m) > 0) << 1 | 1
+    __shared__ uint32_t gbuf[GCAP];    // gathered leaves: k << 22 | q << 2 | (mu(m) > 0) << 1 | 1
+    __shared__ uint16_t g_rc[KMAX * NWV]; // each wave's region count at gathered column k
+    __shared__ uint32_t g_rm[KMAX];       // regions that hold a leaf of gathered column k
     __shared__ uint32_t c_p[CH];       // p_b
     __shared__ uint32_t c_i0[CH];      // bit of the first multiple in the segment, S if none
     __shared__ uint32_t c_ls[CH];      // first leaf item (m, or index of the prime m)
@@ -93,7 +101,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     __shared__ int32_t c_w[CH];        // sum of -mu(m) over the leaves of the column
     __shared__ uint64_t c_leafy[CH / 64];
     __shared__ uint64_t c_heavy[CH / 64];
-    __shared__ uint32_t s_first_large, s_gend, s_used;
+    __shared__ uint32_t s_first_large, s_gend, s_used, s_hn;
     __shared__ uint32_t reg_dec[NWV];  // integers a batched crossing removed, per region
     __shared__ uint32_t scr32[NWV];
     __shared__ pc_s128 scr128[NWV];
@@ -218,33 +226,28 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     int64_t acc_p2 = 0;                // sum of in-segment counts (P2 terms)
     pc_s128 acc_carry = 0;             // PC_MODE_LEAVES: carry * w
 
-    // one leaf item of column j (chunk base cb): sets *w = -mu(m) (0 if the
-    // candidate m is not a leaf) and returns q, the bit count below u
-    auto leaf_item = [&](uint32_t cb, uint32_t j, uint32_t it, int32_t *w) -> uint32_t {
-        const uint32_t b = Q.c + 1 + cb + j;
-        const uint32_t lc = c_lc[j], ls = c_ls[j], p = c_p[j];
-        uint64_t m = 0;
-        *w = 0;
+    // Leaf item it of column j: *m and *w = -mu(m), false if the candidate m
+    // is not squarefree with lpf(m) > p_b.
+    auto leaf_filter = [&](uint32_t j, uint32_t it, uint64_t *m, int32_t *w) -> bool {
+        const uint32_t lc = c_lc[j], ls = c_ls[j];
         if (lc & PC_CAND) {
             const int32_t v = TB.mulpf[ls + it];
             const uint32_t av = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
             n_cand++;
-            if (av > p) { // squarefree with lpf(m) > p_b
-                m = ls + it;
-                *w = v > 0 ? -1 : 1;
-            }
-        } else {
-            m = TB.primes[ls + it];
-            *w = 1;
+            *m = ls + it;
+            *w = v > 0 ? -1 : 1;
+            return av > c_p[j];
         }
-        if (*w == 0)
-            return 0;
-        const uint64_t u = pc_div_small_q(Q.Xb[b], m);
-        if (u < lo || u >= hi) { // cannot happen if the m range is right
+        *m = TB.primes[ls + it];
+        *w = 1;
+        return true;
+    };
+    // q = bits of the segment below u = floor(X_b / m), u in [lo, hi)
+    auto leaf_q = [&](uint32_t cb, uint32_t j, uint64_t m, bool *ok) -> uint32_t {
+        const uint64_t u = pc_div_small_q(Q.Xb[Q.c + 1 + cb + j], m);
+        *ok = u >= lo && u < hi;
+        if (!*ok) // cannot happen if the m range is right
             atomicOr(A.err, 2);
-            *w = 0;
-            return 0;
-        }
         return (uint32_t)((u - lo + 1) >> 1);
     };
 
@@ -366,28 +369,60 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 v_rem = removed;
         };
 
-        // Gather the leaves of the light leafy columns of [j0, jend) that fit
-        // in gbuf (whole columns, in order), one item per thread: c_lc of a
-        // gathered column becomes GATH | offset << 12 | count.
+        // Gather rounds.  The leaves of up to KMAX light leafy columns (whole
+        // columns, in order, stopping at the next heavy column) go to gbuf,
+        // one candidate per slot.  Each wave answers only the leaves whose u
+        // lies in its own region, and records its region count per column in
+        // g_rc; when the round is over (every wave past its columns), settle()
+        // adds, for every leaf, the counts of the regions below its own.
+        uint32_t g_used = 0; // slots of the open round (uniform); 0 = none open
+        auto settle = [&]() { // after a barrier that every wave reached past the round
+            for (uint32_t s = tid; s < g_used; s += T) {
+                const uint32_t e = gbuf[s];
+                if (!(e & 1))
+                    continue;
+                const uint32_t k = e >> 22, r = min(((e >> 2) & 0xFFFFFu) >> RSL, NWV);
+                uint32_t below = 0;
+                for (uint32_t w = 0; w < r; w++)
+                    below += g_rc[k * NWV + w];
+                acc_local += (e & 2) ? -(int64_t)below : (int64_t)below;
+            }
+            g_used = 0;
+        };
         auto gather = [&](uint32_t j0) {
             PC_PH(4);
-            __syncthreads(); // earlier readers of gbuf and pre are done
+            __syncthreads(); // every wave is past the open round's columns
+            settle();
+            // the next heavy column at or after j0 ends the round
+            uint32_t hvn = jend;
+            {
+                uint32_t wd = j0 >> 6;
+                uint64_t msk = c_heavy[wd] & (~0ull << (j0 & 63));
+                while (!msk && ++wd < (jend + 63) / 64)
+                    msk = c_heavy[wd];
+                if (msk)
+                    hvn = min(jend, wd * 64 + (uint32_t)__builtin_ctzll(msk));
+            }
             const uint32_t jt = tid;
             uint32_t v = 0;
-            if (jt >= j0 && jt < jend) {
+            if (jt >= j0 && jt < hvn) {
                 const uint32_t lc = c_lc[jt];
-                if (lc != 0 && !(lc & GATH) && (lc & ~PC_CAND) <= LIGHT)
-                    v = lc & ~PC_CAND;
+                if (lc != 0 && !(lc & GATH))
+                    v = lc & ~PC_CAND; // light: heavy columns lie at or past hvn
             }
             if (tid == 0) {
                 s_gend = jend;
                 s_used = 0;
             }
+            if (tid < KMAX)
+                g_rm[tid] = 0;
             uint32_t tot;
-            const uint32_t off = pc_block_excl_scan<T>(v, scr32, &tot); // two barriers
-            const bool fit = off + v <= GCAP;
+            // items (high bits) and columns (low 10 bits) before this column
+            const uint32_t ex = pc_block_excl_scan<T>((v << 10) | (v ? 1u : 0u), scr32, &tot);
+            const uint32_t off = ex >> 10, k = ex & 1023u;
+            const bool fit = off + v <= GCAP && k < KMAX;
             if (jt >= j0 && jt < jend)
-                pre[jt] = fit ? off : GCAP;
+                pre[jt] = fit ? (off << 10) | k : GCAP << 10; // slot offset, ordinal
             if (v && !fit)
                 atomicMin(&s_gend, jt);
             if (v && fit)
@@ -395,49 +430,59 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             __syncthreads();
             const uint32_t used = s_used, gend = s_gend;
             for (uint32_t s = tid; s < used; s += T) {
-                uint32_t a = j0, z = gend; // the column: largest jc in [j0, gend) with pre[jc] <= s
+                uint32_t a = j0, z = gend; // the column: largest in [j0, gend) starting at or below s
                 while (z - a > 1) {
                     const uint32_t mid = (a + z) >> 1;
-                    if (pre[mid] <= s)
+                    if ((pre[mid] >> 10) <= s)
                         a = mid;
                     else
                         z = mid;
                 }
+                const uint32_t pa = pre[a], kk = pa & 1023u;
+                uint64_t m;
                 int32_t w;
-                const uint32_t q = leaf_item(cb, a, s - pre[a], &w);
                 uint32_t e = 0;
-                if (w) {
-                    e = (q << 2) | (w < 0 ? 2u : 0u) | 1u;
-                    atomicAdd(&c_w[a], w);
-                    nleaf++;
+                if (leaf_filter(a, s - (pa >> 10), &m, &w)) {
+                    bool ok;
+                    const uint32_t q = leaf_q(cb, a, m, &ok);
+                    if (ok) {
+                        const uint32_t r = q >> RSL;
+                        e = (kk << 22) | (q << 2) | (w < 0 ? 2u : 0u) | 1u;
+                        atomicAdd(&c_w[a], w);
+                        if (r < NWV)
+                            atomicOr(&g_rm[kk], 1u << r);
+                        nleaf++;
+                    }
                 }
                 gbuf[s] = e;
             }
             __syncthreads(); // every reader of c_lc, c_ls and pre is done
             if (v && fit) {
-                c_lc[jt] = GATH | (off << 12) | v;
+                c_lc[jt] = GATH | (k << 22) | (off << 11) | v;
                 n_leafy++;
                 if (jt < first_large)
                     n_leafy_small++;
             }
+            g_used = used;
             __syncthreads();
             PC_PH(2);
         };
-        // this wave's part of the leaves of gathered column j: all of rc for a
-        // leaf above the region, a prefix of the region for one inside it
+        // this wave's part of the leaves of gathered column j: it records its
+        // region count, and counts a prefix of its region for each leaf in it
         auto answer = [&](uint32_t j) {
             const uint32_t g = c_lc[j];
-            const uint32_t s0 = (g >> 12) & 0x3FFFFu, s1 = s0 + (g & 0xFFFu);
+            const uint32_t k = (g >> 22) & 0x7Fu;
+            if (lane == 0)
+                g_rc[k * NWV + wv] = (uint16_t)rc;
+            if (!((g_rm[k] >> wv) & 1u))
+                return;
+            const uint32_t s0 = (g >> 11) & 0x7FFu, s1 = s0 + (g & 0x7FFu);
             bool have = false;
             uint32_t pe = 0, pc0 = 0; // lane prefix of the region's block counts; first block
-            int32_t above = 0;
             for (uint32_t s = s0; s < s1; s += 64) {
                 const uint32_t e = s + lane < s1 ? gbuf[s + lane] : 0u;
-                const bool valid = e & 1, neg = (e >> 1) & 1;
-                const uint32_t q = e >> 2, r = q >> RSL;
-                above += (int32_t)__builtin_popcountll(__ballot(valid && r > wv && !neg)) -
-                         (int32_t)__builtin_popcountll(__ballot(valid && r > wv && neg));
-                const bool in = valid && r == wv;
+                const uint32_t q = (e >> 2) & 0xFFFFFu;
+                const bool in = (e & 1) && (q >> RSL) == wv;
                 if (__ballot(in)) {
                     if (!have) {
                         uint32_t cnt[BPT];
@@ -455,40 +500,64 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                     }
                     if (in) {
                         c += in_block(q);
-                        acc_local += neg ? -(int64_t)c : (int64_t)c;
+                        acc_local += (e & 2) ? -(int64_t)c : (int64_t)c;
                     }
                 }
             }
-            if (lane == 0)
-                acc_local += (int64_t)rc * above;
         };
-        // many leaves: the whole workgroup answers them against pre[]
+        // Many leaves: the whole workgroup answers them against pre[].  Prime
+        // items are all leaves; candidates are first filtered into gbuf, so
+        // the divisions and counts run on full wavefronts.
         auto heavy_col = [&](uint32_t j) {
             PC_PH(4);
             __syncthreads(); // every wave has crossed the columns before j
-            build_pre();
-            const uint32_t n = c_lc[j] & ~PC_CAND;
+            settle();
+            build_pre();     // (its barriers also end settle's reads of gbuf)
+            const uint32_t lc = c_lc[j], n = lc & ~PC_CAND, ls = c_ls[j];
             int32_t wsum = 0;
             int64_t lsum = 0;
-            for (uint32_t t0 = 0; t0 < n; t0 += 2 * T) {
-                int32_t w0, w1 = 0;
-                const uint32_t it0 = t0 + tid, it1 = it0 + T;
-                uint32_t q0 = 0, q1 = 0;
-                if (it0 < n)
-                    q0 = leaf_item(cb, j, it0, &w0);
-                else
-                    w0 = 0;
-                if (it1 < n)
-                    q1 = leaf_item(cb, j, it1, &w1);
-                if (w0) {
-                    lsum += (int64_t)w0 * (int64_t)count_pre(q0);
-                    wsum += w0;
+            auto one = [&](uint64_t m, int32_t w) {
+                bool ok;
+                const uint32_t q = leaf_q(cb, j, m, &ok);
+                if (ok) {
+                    lsum += (int64_t)w * (int64_t)count_pre(q);
+                    wsum += w;
                     nleaf++;
                 }
-                if (w1) {
-                    lsum += (int64_t)w1 * (int64_t)count_pre(q1);
-                    wsum += w1;
-                    nleaf++;
+            };
+            if (!(lc & PC_CAND)) {
+                for (uint32_t it = tid; it < n; it += T)
+                    one(TB.primes[ls + it], 1);
+            } else {
+                for (uint32_t base = 0; base < n; base += GCAP) {
+                    if (tid == 0)
+                        s_hn = 0;
+                    __syncthreads();
+                    const uint32_t nb = min(GCAP, n - base);
+                    for (uint32_t t0 = 0; t0 < nb; t0 += T) {
+                        const uint32_t it = t0 + tid;
+                        bool keep = false;
+                        int32_t w = 0;
+                        if (it < nb) {
+                            uint64_t m;
+                            keep = leaf_filter(j, base + it, &m, &w);
+                        }
+                        const uint64_t bal = __ballot(keep);
+                        uint32_t at = 0;
+                        if (lane == 0 && bal)
+                            at = atomicAdd(&s_hn, (uint32_t)__builtin_popcountll(bal));
+                        at = (uint32_t)__shfl((int)at, 0, 64) +
+                             (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1));
+                        if (keep)
+                            gbuf[at] = it | (w < 0 ? 0x80000000u : 0u);
+                    }
+                    __syncthreads();
+                    const uint32_t nk = s_hn;
+                    for (uint32_t s = tid; s < nk; s += T) {
+                        const uint32_t e = gbuf[s];
+                        one(ls + base + (e & 0x7FFFFFFFu), (e >> 31) ? -1 : 1);
+                    }
+                    __syncthreads(); // gbuf and s_hn are reused
                 }
             }
             acc_local += lsum;
@@ -588,7 +657,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         }
         flush_removed();
         PC_PH(4);
-        __syncthreads(); // c_new complete
+        __syncthreads(); // c_new complete; every wave is past the open round
+        settle();
         // --- chunk results: cnt before each crossing, and w ---
         {
             const uint32_t v = tid < jend ? c_new[tid] : 0;
