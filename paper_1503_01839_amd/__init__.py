@@ -19,6 +19,8 @@ FLAG_TWO_PASS = 1
 FLAG_NO_BATCH_LARGE = 2
 FLAG_REBUILD_TABLES = 4
 FLAG_NO_SMALL_SEGMENTS = 8
+FLAG_NO_GRAPH = 16
+FLAG_BATCH_SEQUENTIAL = 32
 
 EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
            "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_wheel_c", "pc_status_str",

@@ -1,0 +1,182 @@
+// pc_batch.hip -- many pi(x) queries in one pass: the same per-item work as
+// the one-query kernels (pc_leafwork.h) on flat grids whose blocks are dealt
+// out to the queries by host-built tables, with every query's sums
+// accumulated in place (pc_atomic_add128).  The sieve itself is the one-query
+// kernel: its tiles name their query.
+#include "pc_leafwork.h"
+
+#define BT 256
+#define BEZ_PER 32
+
+// block -> (query, block of the query, blocks of the query)
+struct pc_blk {
+    const uint32_t *q;     // query of each block
+    const uint32_t *first; // first block of each query; first[nq] = total
+};
+
+__device__ __forceinline__ void pc_blk_of(const pc_blk &B, uint32_t *q, uint32_t *lb,
+                                          uint32_t *nlb)
+{
+    *q = B.q[blockIdx.x];
+    const uint32_t f = B.first[*q];
+    *lb = blockIdx.x - f;
+    *nlb = B.first[*q + 1] - f;
+}
+
+__global__ __launch_bounds__(BT) void k_xb_b(pc_tables T, const pc_query *Qs, pc_blk B)
+{
+    uint32_t q, lb, nlb;
+    pc_blk_of(B, &q, &lb, &nlb);
+    const pc_query &Q = Qs[q];
+    for (uint32_t b = lb * BT + threadIdx.x; b <= Q.a; b += nlb * BT)
+        pc_xb_item(T, Q, b);
+}
+
+__global__ __launch_bounds__(BT) void k_s1_b(pc_tables T, const pc_query *Qs, pc_blk B)
+{
+    __shared__ pc_s128 scr[BT / 64];
+    __shared__ unsigned long long scr64[BT / 64];
+    uint32_t q, lb, nlb;
+    pc_blk_of(B, &q, &lb, &nlb);
+    const pc_query &Q = Qs[q];
+    const uint32_t pcc = T.primes[Q.c];
+    pc_s128 acc = 0;
+    unsigned long long terms = 0;
+    for (uint64_t n = 1 + (uint64_t)lb * BT + threadIdx.x; n <= Q.y; n += (uint64_t)nlb * BT)
+        terms += pc_s1_item(T, Q, pcc, n, &acc);
+    acc = pc_block_sum128<BT>(acc, scr);
+    terms = pc_block_sum<BT>(terms, scr64);
+    if (threadIdx.x == 0) {
+        pc_atomic_add128(&Q.sums->s1, acc);
+        atomicAdd(&Q.sums->n_s1, terms);
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_leaf_setup_b(pc_tables T, const pc_query *Qs, pc_blk B)
+{
+    __shared__ uint64_t scr[BT / 64];
+    uint32_t q, lb, nlb;
+    pc_blk_of(B, &q, &lb, &nlb);
+    const pc_query &Q = Qs[q];
+    uint64_t triv = 0, cross = 0;
+    for (uint32_t b = lb * BT + threadIdx.x; b <= max(Q.a, Q.c + Q.nb); b += nlb * BT) {
+        uint64_t t, c;
+        pc_leaf_setup_item(T, Q, b, &t, &c);
+        triv += t;
+        cross += c;
+    }
+    const uint64_t s = pc_block_sum<BT>(triv, scr);
+    const uint64_t cs = pc_block_sum<BT>(cross, scr);
+    if (threadIdx.x == 0) {
+        pc_atomic_add128(&Q.sums->s2t, (pc_s128)s);
+        atomicAdd(&Q.sums->n_trivial, (unsigned long long)s);
+        atomicAdd(&Q.sums->crossings, (unsigned long long)cs);
+    }
+}
+
+// e_off = exclusive prefix of the easy item counts of b = 0..a, one workgroup
+// per query, in chunks of BT entries.
+__global__ __launch_bounds__(BT) void k_escan_b(const pc_query *Qs)
+{
+    __shared__ uint64_t scr[BT / 64];
+    const pc_query &Q = Qs[blockIdx.x];
+    uint64_t run = 0;
+    for (uint32_t b0 = 0; b0 <= Q.a; b0 += BT) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint64_t v = b <= Q.a ? Q.e_count[b] & ~PC_MODEBIT : 0;
+        uint64_t tot;
+        const uint64_t ex = pc_block_excl_scan<BT>(v, scr, &tot);
+        if (b <= Q.a)
+            Q.e_off[b] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0)
+        *Q.e_total = run;
+}
+
+__global__ __launch_bounds__(BT) void k_easy_b(pc_tables T, const pc_query *Qs, pc_blk B)
+{
+    __shared__ pc_s128 scr[BT / 64];
+    __shared__ unsigned long long scr64[BT / 64];
+    __shared__ uint32_t s_b0;
+    uint32_t q, lb, nlb;
+    pc_blk_of(B, &q, &lb, &nlb);
+    const pc_query &Q = Qs[q];
+    unsigned long long nleaf = 0;
+    int64_t acc = 0;
+    pc_easy_tiles<BT, BEZ_PER>(T, Q, lb, nlb, &s_b0, &acc, &nleaf);
+    const pc_s128 s = pc_block_sum128<BT>((pc_s128)acc, scr);
+    nleaf = pc_block_sum<BT>(nleaf, scr64);
+    if (threadIdx.x == 0) {
+        pc_atomic_add128(&Q.sums->s2e, s);
+        atomicAdd(&Q.sums->n_easy, nleaf);
+    }
+}
+
+// Carries of whole queries (every row of a query in one pass): block i scans
+// the columns [256 cb, 256 cb + 256) of query q down the rows in order,
+// carry = sum of the counts above, and adds sum w * carry to the query.
+__global__ __launch_bounds__(BT) void k_scan_rows_b(const pc_query *Qs, pc_blk B)
+{
+    __shared__ pc_s128 scr[BT / 64];
+    uint32_t q, cb, ncb;
+    pc_blk_of(B, &q, &cb, &ncb);
+    const pc_query &Q = Qs[q];
+    const uint32_t col = cb * BT + threadIdx.x;
+    pc_s128 dh = 0, dp = 0;
+    if (col < Q.ncol) {
+        uint64_t carry = 0;
+        const uint64_t nrows = Q.nseg, ncol = Q.ncol;
+        for (uint64_t r = 0; r < nrows; r++) {
+            const uint64_t idx = r * ncol + col;
+            const int32_t w = Q.wgt[idx];
+            if (w) {
+                if (col == Q.nb)
+                    dp += (pc_s128)w * (pc_s128)carry;
+                else
+                    dh += (pc_s128)w * (pc_s128)carry;
+            }
+            carry += Q.cnt[idx];
+        }
+    }
+    dh = pc_block_sum128<BT>(dh, scr);
+    dp = pc_block_sum128<BT>(dp, scr);
+    if (threadIdx.x == 0) {
+        pc_atomic_add128(&Q.sums->hard_dot, dh);
+        pc_atomic_add128(&Q.sums->p2_dot, dp);
+    }
+}
+
+__global__ void k_combine_b(const pc_query *Qs, uint32_t nq, pc_final *out)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq)
+        pc_combine_one(*Qs[q].sums, Qs[q], Qs[q].kx, &out[q]);
+}
+
+hipError_t pc_launch_batch_setup(const pc_tables &T, const pc_query *Qs, const uint32_t *bq_xb,
+                                 const uint32_t *bf_xb, uint32_t nb_xb, const uint32_t *bq_s1,
+                                 const uint32_t *bf_s1, uint32_t nb_s1, uint32_t nq,
+                                 hipStream_t s)
+{
+    k_xb_b<<<nb_xb, BT, 0, s>>>(T, Qs, pc_blk{bq_xb, bf_xb});
+    k_s1_b<<<nb_s1, BT, 0, s>>>(T, Qs, pc_blk{bq_s1, bf_s1});
+    k_leaf_setup_b<<<nb_xb, BT, 0, s>>>(T, Qs, pc_blk{bq_xb, bf_xb});
+    k_escan_b<<<nq, BT, 0, s>>>(Qs);
+    return hipGetLastError();
+}
+
+hipError_t pc_launch_batch_easy(const pc_tables &T, const pc_query *Qs, const uint32_t *bq,
+                                const uint32_t *bf, uint32_t nblocks, hipStream_t s)
+{
+    k_easy_b<<<nblocks, BT, 0, s>>>(T, Qs, pc_blk{bq, bf});
+    return hipGetLastError();
+}
+
+hipError_t pc_launch_batch_finish(const pc_query *Qs, const uint32_t *bq, const uint32_t *bf,
+                                  uint32_t nblocks, uint32_t nq, pc_final *out, hipStream_t s)
+{
+    k_scan_rows_b<<<nblocks, BT, 0, s>>>(Qs, pc_blk{bq, bf});
+    k_combine_b<<<(nq + 63) / 64, 64, 0, s>>>(Qs, nq, out);
+    return hipGetLastError();
+}

@@ -131,3 +131,17 @@ template <int NT> __device__ __forceinline__ pc_s128 pc_block_sum128(pc_s128 v, 
     __syncthreads();
     return all;
 }
+
+// *dst += v for a signed 128-bit accumulator in device memory, from any number
+// of threads: the low words are added atomically, and each adder carries its
+// own overflow into the high word, so the total is exact in any order.
+__device__ __forceinline__ void pc_atomic_add128(pc_s128 *dst, pc_s128 v)
+{
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(dst);
+    const unsigned long long lo = (unsigned long long)(uint64_t)v;
+    const unsigned long long hi = (unsigned long long)(uint64_t)(v >> 64);
+    const unsigned long long old = atomicAdd(&w[0], lo);
+    const unsigned long long carry = old + lo < old ? 1ull : 0ull;
+    if (hi + carry)
+        atomicAdd(&w[1], hi + carry);
+}

@@ -105,7 +105,7 @@ struct Tables {
 Tables g_T;
 
 struct QueryBufs {
-    DevBuf Ub, Xb, e_start, e_count, e_off, e_tmp, e_total, part, sums, fin, ntriv;
+    DevBuf Ub, Xb, e_start, e_count, e_off, e_tmp, e_total, part, sums, fin, qdev;
     DevBuf work, hot, bounds, tiles_a, trace;
     DevBuf tiles, cnt, wgt, carry_rows, carry_a, carry_b, status, ticket, part_tile_h,
         part_tile_p, part_scan_h, part_scan_p, err;
@@ -279,9 +279,9 @@ void drop_query_bufs()
 {
     QueryBufs &B = g_Q;
     DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.e_start, &B.e_count, &B.e_off, &B.e_tmp, &B.e_total, &B.part,
-                     &B.sums, &B.fin, &B.ntriv, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
+                     &B.sums, &B.fin, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
                      &B.carry_a, &B.carry_b, &B.status, &B.ticket, &B.part_tile_h,
-                     &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err};
+                     &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err, &B.qdev};
     for (DevBuf *b : all)
         dfree(*b);
 }
@@ -558,19 +558,18 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     const uint64_t nB = baseB > z ? 0 : (z - baseB) / (2 * S) + 1;
     const uint64_t nseg = nA + nB;
     Q.sieve_end = baseB + nB * 2 * S;
+    Q.nseg = nseg;
     g_ev_used = 0;
 
     // --- per-query tables and the leaves outside the sieve ---
     ensure(B.Xb, (a + 2) * 8, "X_b");
-    Q.Xb = ptr<uint64_t>(B.Xb);
+    Q.Xb = Q.Xb_w = ptr<uint64_t>(B.Xb);
     hipck(pc_launch_xb(T, x, (uint32_t)a, ptr<uint64_t>(B.Xb), g_stream), "X_b");
 
     ensure(B.sums, sizeof(pc_sums), "sums");
     ensure(B.fin, sizeof(pc_final), "final");
-    ensure(B.ntriv, 8, "counts");
     ensure(B.e_total, 16, "easy total");
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.sums), sizeof(pc_sums) / 8, 0, g_stream), "fill");
-    hipck(pc_launch_fill_u64(ptr<uint64_t>(B.ntriv), 1, 0, g_stream), "fill");
     pc_sums *sums = ptr<pc_sums>(B.sums);
     Q.sums = sums;
 
@@ -588,11 +587,12 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     ensure(B.e_off, (a + 2) * 8, "easy offsets");
     ensure(B.e_tmp, ((a + 2) / 4096 + 2) * 8, "scan");
     ensure(B.Ub, (a + 2) * 16, "hard-leaf u ranges");
-    Q.Ub = ptr<ulonglong2>(B.Ub);
-    hipck(pc_launch_leaf_setup(T, Q, ptr<uint64_t>(B.e_start), ptr<uint64_t>(B.e_count),
-                               ptr<pc_s128>(B.part), ptr<uint64_t>(B.ntriv),
-                               ptr<ulonglong2>(B.Ub), ls_blocks, g_stream),
-          "leaf setup");
+    Q.Ub = Q.Ub_w = ptr<ulonglong2>(B.Ub);
+    Q.e_start = ptr<uint64_t>(B.e_start);
+    Q.e_count = ptr<uint64_t>(B.e_count);
+    Q.e_off = ptr<uint64_t>(B.e_off);
+    Q.e_total = ptr<uint64_t>(B.e_total);
+    hipck(pc_launch_leaf_setup(T, Q, ptr<pc_s128>(B.part), ls_blocks, g_stream), "leaf setup");
     hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ls_blocks, &sums->s2t, g_stream), "S2t sum");
     hipck(pc_launch_strip(ptr<uint64_t>(B.e_count), ptr<uint64_t>(B.e_off), a + 1, g_stream),
           "strip");
@@ -612,10 +612,7 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         hipck(hipStreamWaitEvent(g_stream2, g_fork, 0), "hipStreamWaitEvent");
         ev_easy = timed(
             [&] {
-                hipck(pc_launch_easy(T, Q, ptr<uint64_t>(B.e_start), ptr<uint64_t>(B.e_count),
-                                     ptr<uint64_t>(B.e_off), ptr<uint64_t>(B.e_total),
-                                     ptr<pc_s128>(B.part), ez_blocks, g_stream2),
-                      "easy");
+                hipck(pc_launch_easy(T, Q, ptr<pc_s128>(B.part), ez_blocks, g_stream2), "easy");
             },
             g_stream2);
         hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ez_blocks, &sums->s2e, g_stream2),
@@ -648,6 +645,12 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     ensure(B.part_scan_p, nchunk_max * ncb * 16, "scan partials");
     ensure(B.err, 8, "error flag");
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.carry_a), Q.ncol, 0, g_stream), "fill");
+    // the query as the sieve reads it: one entry of a device array
+    Q.cnt = ptr<uint32_t>(B.cnt);
+    Q.wgt = ptr<int32_t>(B.wgt);
+    Q.carry = ptr<uint64_t>(B.carry_rows);
+    ensure(B.qdev, sizeof(pc_query), "query");
+    hipck(hipMemcpyAsync(B.qdev.p, &Q, sizeof Q, hipMemcpyHostToDevice, g_stream), "H2D");
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.err), 1, 0, g_stream), "fill");
 
     // PICOUNT_TILE_TRACE=<path>: append one line per sieve tile (profiling aid)
@@ -691,15 +694,12 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         auto sieve_args = [&](bool small) {
             pc_sieve_args A{};
             A.T = T;
-            A.Q = Q;
+            A.Qs = ptr<pc_query>(B.qdev);
             A.tiles = ptr<pc_tile>(small ? B.tiles_a : B.tiles);
             A.ntiles = (uint32_t)(small ? tiles_a.size() : tiles_b.size());
             A.seg0 = r0;
             A.lo_base = small ? 0 : baseB;
             A.seg_base = small ? 0 : nA;
-            A.cnt = ptr<uint32_t>(B.cnt);
-            A.wgt = ptr<int32_t>(B.wgt);
-            A.carry = ptr<uint64_t>(B.carry_rows);
             A.part_hard = ptr<pc_s128>(B.part_tile_h);
             A.part_p2 = ptr<pc_s128>(B.part_tile_p);
             A.err = ptr<int32_t>(B.err);
@@ -797,11 +797,9 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     pc_final fin{};
     pc_sums hs{};
     int32_t err = 0;
-    uint64_t ntriv = 0;
     hipck(hipMemcpyAsync(&hs, B.sums.p, sizeof hs, hipMemcpyDeviceToHost, g_stream), "D2H");
     hipck(hipMemcpyAsync(&fin, B.fin.p, sizeof fin, hipMemcpyDeviceToHost, g_stream), "D2H");
     hipck(hipMemcpyAsync(&err, B.err.p, 4, hipMemcpyDeviceToHost, g_stream), "D2H");
-    hipck(hipMemcpyAsync(&ntriv, B.ntriv.p, 8, hipMemcpyDeviceToHost, g_stream), "D2H");
     hipck(hipStreamSynchronize(g_stream), "sync");
     const double ms_sieve = ms_since(t2);
     if (err & 1)
@@ -826,7 +824,7 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         res->s2_hard = to_abi(fin.s2h);
         res->p2 = to_abi(fin.p2);
         res->phi = to_abi(fin.phi);
-        res->n_trivial = ntriv;
+        res->n_trivial = hs.n_trivial;
         res->n_p2 = kx > a ? kx - a : 0;
         res->n_s1 = hs.n_s1;
         res->n_easy = hs.n_easy;
@@ -911,6 +909,281 @@ void pi_one(uint64_t x, const Knobs &K, double alpha, pc_result *res, uint64_t *
     *pi = r.pi;
     if (res)
         *res = r;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batches.  Queries x >= kSmallX go through rounds: each round holds as many
+// queries (in order) as fit the carry budget with every row of their sieve
+// counts resident, and runs them together: one set-up pass, one easy-leaf
+// pass, one sieve launch whose tiles name their query, one carry pass and one
+// combination, captured as a HIP graph (PC_FLAG_NO_GRAPH: launched directly).
+// A query whose counts alone exceed the budget runs by itself, windowed.
+// ---------------------------------------------------------------------------
+struct BatchQuery {
+    uint64_t x, y, a, kx, bmax, z, nseg;
+    uint32_t c, nb, ncol;
+    size_t idx; // position in the caller's array
+    uint64_t bytes() const { return nseg * ncol * 8; }
+};
+
+struct BatchBufs {
+    DevBuf arena, qs, tiles, blk;
+};
+BatchBufs g_Bt;
+
+constexpr uint32_t kBatchLog2S = 18; // 32 KiB segments
+constexpr uint32_t kBatchWG = 512;
+
+void run_batch_round(const std::vector<BatchQuery> &R, const Knobs &K, bool use_graph,
+                     uint64_t *out)
+{
+    const uint32_t nq = (uint32_t)R.size();
+    const uint64_t S = 1ull << kBatchLog2S;
+    QueryBufs &QB = g_Q;
+    const pc_tables T = tables_view(kWheelC);
+
+    // arena: sums, easy totals, results, then each query's arrays
+    size_t tot = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = tot;
+        tot += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t o_sums = take(nq * sizeof(pc_sums)), o_et = take(nq * 8),
+                 o_fin = take(nq * sizeof(pc_final));
+    std::vector<size_t> o_xb(nq), o_ub(nq), o_es(nq), o_ec(nq), o_eo(nq), o_cnt(nq), o_wgt(nq);
+    for (uint32_t i = 0; i < nq; i++) {
+        const uint64_t na = R[i].a + 2;
+        o_xb[i] = take(na * 8);
+        o_ub[i] = take(na * 16);
+        o_es[i] = take(na * 8);
+        o_ec[i] = take(na * 8);
+        o_eo[i] = take(na * 8);
+        o_cnt[i] = take(R[i].nseg * R[i].ncol * 4);
+        o_wgt[i] = take(R[i].nseg * R[i].ncol * 4);
+    }
+    ensure(g_Bt.arena, tot, "batch arena");
+    char *base = static_cast<char *>(g_Bt.arena.p);
+    pc_sums *sums = reinterpret_cast<pc_sums *>(base + o_sums);
+    pc_final *fin = reinterpret_cast<pc_final *>(base + o_fin);
+
+    std::vector<pc_query> Qv(nq);
+    for (uint32_t i = 0; i < nq; i++) {
+        const BatchQuery &b = R[i];
+        pc_query &Q = Qv[i];
+        Q.x = b.x;
+        Q.y = b.y;
+        Q.z = b.z;
+        Q.y1 = b.y + 1;
+        Q.recip_y1 = pc_recip(b.y + 1);
+        Q.sqrtx = pc_isqrt(b.x);
+        Q.sqrty = pc_isqrt(b.y);
+        Q.Qc = T.Qc;
+        Q.recip_Qc = pc_recip(T.Qc);
+        Q.c = b.c;
+        Q.a = (uint32_t)b.a;
+        Q.bmax = (uint32_t)b.bmax;
+        Q.nb = b.nb;
+        Q.ncol = b.ncol;
+        Q.kx = (uint32_t)b.kx;
+        Q.Xb = Q.Xb_w = reinterpret_cast<uint64_t *>(base + o_xb[i]);
+        Q.Ub = Q.Ub_w = reinterpret_cast<ulonglong2 *>(base + o_ub[i]);
+        Q.e_start = reinterpret_cast<uint64_t *>(base + o_es[i]);
+        Q.e_count = reinterpret_cast<uint64_t *>(base + o_ec[i]);
+        Q.e_off = reinterpret_cast<uint64_t *>(base + o_eo[i]);
+        Q.e_total = reinterpret_cast<uint64_t *>(base + o_et) + i;
+        Q.sums = sums + i;
+        Q.cnt = reinterpret_cast<uint32_t *>(base + o_cnt[i]);
+        Q.wgt = reinterpret_cast<int32_t *>(base + o_wgt[i]);
+        Q.carry = nullptr;
+        Q.nseg = b.nseg;
+        Q.sieve_end = b.nseg * 2 * S;
+    }
+
+    // block tables: the query of each block and each query's first block
+    std::vector<uint32_t> blk;
+    auto table = [&](auto nblocks_of, uint32_t *nblocks) {
+        const size_t at = blk.size();
+        std::vector<uint32_t> first(nq + 1);
+        uint32_t nbk = 0;
+        for (uint32_t i = 0; i < nq; i++) {
+            first[i] = nbk;
+            nbk += std::max<uint32_t>(1, nblocks_of(R[i]));
+        }
+        first[nq] = nbk;
+        for (uint32_t i = 0; i < nq; i++)
+            for (uint32_t k = first[i]; k < first[i + 1]; k++)
+                blk.push_back(i);
+        blk.insert(blk.end(), first.begin(), first.end());
+        *nblocks = nbk;
+        return at; // q at [at, at + nbk), first at [at + nbk, at + nbk + nq + 1)
+    };
+    uint32_t nb_xb, nb_s1, nb_ez, nb_sc;
+    const size_t t_xb = table([](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, (b.a + 2 + 255) / 256); }, &nb_xb);
+    const size_t t_s1 = table([](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, b.y / 4096 + 1); }, &nb_s1);
+    const size_t t_ez = table([](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(1024, b.y / 4096 + 1); }, &nb_ez);
+    const size_t t_sc = table([](const BatchQuery &b) { return (b.ncol + 255) / 256; }, &nb_sc);
+
+    // sieve tiles, largest queries first, each query's low (leaf-dense) segments first
+    std::vector<uint32_t> order(nq);
+    for (uint32_t i = 0; i < nq; i++)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t u, uint32_t v) { return R[u].bytes() > R[v].bytes(); });
+    std::vector<pc_tile> tiles;
+    for (uint32_t i : order)
+        for (uint64_t sg = 0; sg < R[i].nseg; sg++)
+            tiles.push_back(pc_tile{(uint32_t)sg, 0, R[i].ncol, i});
+
+    ensure(g_Bt.qs, nq * sizeof(pc_query), "batch queries");
+    ensure(g_Bt.tiles, tiles.size() * sizeof(pc_tile), "batch tiles");
+    ensure(g_Bt.blk, blk.size() * 4, "batch blocks");
+    ensure(QB.err, 8, "error flag");
+    hipck(hipMemcpyAsync(g_Bt.qs.p, Qv.data(), nq * sizeof(pc_query), hipMemcpyHostToDevice, g_stream), "H2D");
+    hipck(hipMemcpyAsync(g_Bt.tiles.p, tiles.data(), tiles.size() * sizeof(pc_tile), hipMemcpyHostToDevice, g_stream), "H2D");
+    hipck(hipMemcpyAsync(g_Bt.blk.p, blk.data(), blk.size() * 4, hipMemcpyHostToDevice, g_stream), "H2D");
+    hipck(pc_launch_fill_u64(ptr<uint64_t>(QB.err), 1, 0, g_stream), "fill");
+    const pc_query *qs = ptr<pc_query>(g_Bt.qs);
+    const uint32_t *bk = ptr<uint32_t>(g_Bt.blk);
+
+    auto launches = [&]() {
+        hipck(pc_launch_fill_u64(reinterpret_cast<uint64_t *>(sums), nq * sizeof(pc_sums) / 8, 0, g_stream), "fill");
+        hipck(pc_launch_batch_setup(T, qs, bk + t_xb, bk + t_xb + nb_xb, nb_xb, bk + t_s1,
+                                    bk + t_s1 + nb_s1, nb_s1, nq, g_stream),
+              "batch set-up");
+        hipck(pc_launch_batch_easy(T, qs, bk + t_ez, bk + t_ez + nb_ez, nb_ez, g_stream), "batch easy");
+        pc_sieve_args A{};
+        A.T = T;
+        A.Qs = qs;
+        A.tiles = ptr<pc_tile>(g_Bt.tiles);
+        A.ntiles = (uint32_t)tiles.size();
+        A.err = ptr<int32_t>(QB.err);
+        hipck(pc_launch_sieve(A, kBatchLog2S, kBatchWG, PC_MODE_TALLY | (K.batch ? 0 : 0x100), g_stream),
+              "batch sieve");
+        hipck(pc_launch_batch_finish(qs, bk + t_sc, bk + t_sc + nb_sc, nb_sc, nq, fin, g_stream),
+              "batch finish");
+    };
+    if (use_graph) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipck(hipStreamBeginCapture(g_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+            launches();
+        } catch (...) {
+            (void)hipStreamEndCapture(g_stream, &graph);
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            throw;
+        }
+        hipck(hipStreamEndCapture(g_stream, &graph), "hipStreamEndCapture");
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e == hipSuccess)
+            e = hipGraphLaunch(exec, g_stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(g_stream);
+        if (exec)
+            (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        hipck(e, "batch graph");
+    } else {
+        launches();
+    }
+    std::vector<pc_final> f(nq);
+    int32_t err = 0;
+    hipck(hipMemcpyAsync(f.data(), fin, nq * sizeof(pc_final), hipMemcpyDeviceToHost, g_stream), "D2H");
+    hipck(hipMemcpyAsync(&err, QB.err.p, 4, hipMemcpyDeviceToHost, g_stream), "D2H");
+    hipck(hipStreamSynchronize(g_stream), "sync");
+    if (err)
+        fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment (batch)");
+    for (uint32_t i = 0; i < nq; i++) {
+        if (!f[i].ok)
+            fail(PC_EINTERNAL, "pi(x) outside [0, 2^64) (batch)");
+        out[R[i].idx] = f[i].pi;
+    }
+}
+
+void run_batch(const uint64_t *xs, size_t n, const Knobs &K, double alpha, bool use_graph,
+               uint64_t *out)
+{
+    if (std::isnan(alpha) || alpha < 0)
+        fail(PC_EINVAL, "alpha must be >= 0 (0 = tuned)");
+    init_stream();
+    // parameters of every query, and the tables they need
+    std::vector<uint64_t> ys(n, 0);
+    uint64_t need = kSmallX, ymax = 0;
+    for (size_t i = 0; i < n; i++) {
+        if (xs[i] < kSmallX)
+            continue;
+        ys[i] = choose_y(xs[i], alpha > 0 ? alpha : default_alpha(xs[i]));
+        need = std::max<uint64_t>({need, pc_isqrt(xs[i]), ys[i]});
+        ymax = std::max(ymax, ys[i]);
+    }
+    ensure_pi(std::max<uint64_t>(need, 1024) + 1);
+    std::vector<uint64_t> pts;
+    pts.reserve(3 * n);
+    for (size_t i = 0; i < n; i++) {
+        if (xs[i] < kSmallX) {
+            pts.push_back(xs[i]);
+            pts.push_back(0);
+            pts.push_back(0);
+        } else {
+            pts.push_back(ys[i]);
+            pts.push_back(pc_isqrt(xs[i]));
+            pts.push_back(pc_isqrt(xs[i] / ys[i]));
+        }
+    }
+    const std::vector<uint64_t> lk = lookup(pts);
+    uint64_t amax = 0;
+    std::vector<BatchQuery> big;
+    for (size_t i = 0; i < n; i++) {
+        if (xs[i] < kSmallX) {
+            out[i] = lk[3 * i];
+            continue;
+        }
+        BatchQuery b{};
+        b.x = xs[i];
+        b.y = ys[i];
+        b.a = lk[3 * i];
+        b.kx = lk[3 * i + 1];
+        b.bmax = lk[3 * i + 2];
+        b.z = xs[i] / ys[i];
+        b.c = (uint32_t)std::min<uint64_t>(kWheelC, b.a);
+        b.nb = b.bmax > b.c ? (uint32_t)(b.bmax - b.c) : 0;
+        b.ncol = b.nb + 1;
+        b.nseg = b.z / (2ull << kBatchLog2S) + 1;
+        b.idx = i;
+        amax = std::max(amax, b.a);
+        big.push_back(b);
+    }
+    if (big.empty())
+        return;
+    ensure_mulpf(ymax);
+    ensure_recip(amax + 1);
+    ensure_wheel(kWheelC);
+    // rounds in input order, each within the carry budget
+    std::vector<BatchQuery> round;
+    uint64_t bytes = 0;
+    auto flush = [&]() {
+        if (!round.empty())
+            run_batch_round(round, K, use_graph, out);
+        round.clear();
+        bytes = 0;
+    };
+    for (const BatchQuery &b : big) {
+        if (b.bytes() > K.carry_budget) { // alone, windowed
+            flush();
+            pc_result r;
+            run_query(b.x, b.y, K, &r);
+            out[b.idx] = r.pi;
+            continue;
+        }
+        if (bytes + b.bytes() > K.carry_budget || round.size() >= 65536)
+            flush();
+        round.push_back(b);
+        bytes += b.bytes();
+    }
+    flush();
 }
 
 } // namespace
@@ -1002,11 +1275,18 @@ pc_status pc_pi_count_batch_ex(const uint64_t *xs, size_t n, const pc_config *cf
     std::vector<uint64_t> out(n);
     pc_status st = guarded([&] {
         Knobs K = knobs_from(cfg);
-        double alpha = cfg ? cfg->alpha : 0.0;
-        if (std::isnan(alpha) || alpha < 0)
-            fail(PC_EINVAL, "alpha must be >= 0 (0 = tuned)");
-        for (size_t i = 0; i < n; i++)
-            pi_one(xs[i], K, alpha, nullptr, &out[i]);
+        const double alpha = cfg ? cfg->alpha : 0.0;
+        const uint32_t flags = cfg ? cfg->flags : 0u;
+        if (flags & PC_FLAG_REBUILD_TABLES)
+            drop_tables();
+        if (flags & PC_FLAG_BATCH_SEQUENTIAL) {
+            if (std::isnan(alpha) || alpha < 0)
+                fail(PC_EINVAL, "alpha must be >= 0 (0 = tuned)");
+            for (size_t i = 0; i < n; i++)
+                pi_one(xs[i], K, alpha, nullptr, &out[i]);
+        } else {
+            run_batch(xs, n, K, alpha, (flags & PC_FLAG_NO_GRAPH) == 0, out.data());
+        }
     });
     if (st == PC_OK)
         memcpy(pi_out, out.data(), n * 8);

@@ -15,7 +15,7 @@ struct pc_tile {
     uint32_t seg;
     uint32_t col_lo;
     uint32_t col_hi;
-    uint32_t pad;
+    uint32_t q;             // query (index into the launch's query array)
 };
 
 // Shared device tables (read-only during a query).
@@ -45,8 +45,18 @@ struct pc_query {
     uint32_t kx;            // pi(isqrt(x))
     const uint64_t *Xb;     // Xb[b] = floor(x / p_b), 1-based, b <= a
     uint64_t sieve_end;     // the sieve covers [0, sieve_end): segments * 2S integers
+    uint64_t nseg;          // segments (rows of cnt and wgt when the query has one window)
     const ulonglong2 *Ub;   // Ub[b] = [u_lo, u_hi]: u of every hard leaf of b (x > y: none)
     pc_sums *sums;          // device accumulators of this query
+    uint32_t *cnt;          // sieve counts [row * ncol + col], row = seg - seg0
+    int32_t *wgt;           // leaf weights, same layout
+    const uint64_t *carry;  // PC_MODE_LEAVES: exclusive carries, same layout
+    uint64_t *e_start;      // easy leaves per b: first item, count (bit 63: candidate m),
+    uint64_t *e_count;      //   exclusive prefix of the counts and their total
+    uint64_t *e_off;
+    uint64_t *e_total;
+    ulonglong2 *Ub_w;       // writable view of Ub (set-up kernels)
+    uint64_t *Xb_w;         // writable view of Xb (set-up kernels)
 };
 
 enum { PC_MODE_TALLY = 0, PC_MODE_COUNT = 1, PC_MODE_LEAVES = 2 };
@@ -57,18 +67,15 @@ enum { PC_MODE_TALLY = 0, PC_MODE_COUNT = 1, PC_MODE_LEAVES = 2 };
 
 struct pc_sieve_args {
     pc_tables T;
-    pc_query Q;
+    const pc_query *Qs;     // device array; tile.q indexes it
     const pc_tile *tiles;
     uint32_t ntiles;
     uint32_t pad;
     uint64_t seg0;          // first segment of the window: row = seg - seg0
     uint64_t lo_base;       // segment seg starts at lo_base + (seg - seg_base) * 2S
     uint64_t seg_base;
-    uint32_t *cnt;          // [row * ncol + col]
-    int32_t *wgt;           // [row * ncol + col]
-    const uint64_t *carry;  // PC_MODE_LEAVES: exclusive carries, same layout
-    pc_s128 *part_hard;     // per tile
-    pc_s128 *part_p2;       // per tile
+    pc_s128 *part_hard;     // per tile; null: added to the tile's query sums instead
+    pc_s128 *part_p2;       // per tile (null as part_hard)
     int32_t *err;
     uint32_t *trace;        // optional, PC_TRACE_W words per tile (profiling aid)
 };
@@ -87,26 +94,17 @@ hipError_t pc_launch_lookup(const uint2 *pitab, const uint64_t *in, uint32_t n, 
                             hipStream_t s);
 hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint32_t a, uint64_t *Xb, hipStream_t s);
 
-// Leaves outside the sieve: S1, trivial and easy special leaves.
-struct pc_leaf_bufs {
-    uint64_t *e_start;   // per b: first easy item (m or prime index)
-    uint64_t *e_count;   // per b: easy items; bit 63 set: candidate (m) mode
-    uint64_t *e_off;     // exclusive prefix of the easy item counts
-    pc_s128 *part;       // partial sums
-    uint64_t *scan_tmp;
-    uint32_t nparts;
-};
+// Leaves outside the sieve: S1, trivial and easy special leaves.  The set-up
+// and easy kernels use the per-query arrays named in pc_query.
 hipError_t pc_launch_s1(const pc_tables &T, const pc_query &Q, pc_s128 *part, uint32_t nblocks,
                         hipStream_t s);
-hipError_t pc_launch_leaf_setup(const pc_tables &T, const pc_query &Q, uint64_t *e_start,
-                                uint64_t *e_count, pc_s128 *part_trivial, uint64_t *ntrivial,
-                                ulonglong2 *Ub, uint32_t nblocks, hipStream_t s);
+hipError_t pc_launch_leaf_setup(const pc_tables &T, const pc_query &Q, pc_s128 *part_trivial,
+                                uint32_t nblocks, hipStream_t s);
 hipError_t pc_launch_strip(const uint64_t *e_count, uint64_t *e_off, uint64_t n, hipStream_t s);
 hipError_t pc_launch_scan_u64(uint64_t *data, uint64_t n, uint64_t *tmp, uint64_t *total,
                               hipStream_t s);
-hipError_t pc_launch_easy(const pc_tables &T, const pc_query &Q, const uint64_t *e_start,
-                          const uint64_t *e_count, const uint64_t *e_off, const uint64_t *e_total,
-                          pc_s128 *part, uint32_t nblocks, hipStream_t s);
+hipError_t pc_launch_easy(const pc_tables &T, const pc_query &Q, pc_s128 *part, uint32_t nblocks,
+                          hipStream_t s);
 hipError_t pc_launch_sum128(const pc_s128 *part, uint32_t n, pc_s128 *acc, hipStream_t s);
 hipError_t pc_launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 
@@ -142,12 +140,25 @@ hipError_t pc_launch_scan(const pc_scan_args &A, int mode, hipStream_t s);
 // Final combination of the partial sums into pi(x) and its parts.
 struct pc_sums {
     pc_s128 s1, s2t, s2e, hard_local, hard_dot, p2_local, p2_dot;
-    unsigned long long n_s1, n_easy, n_hard, crossings;
+    unsigned long long n_s1, n_easy, n_hard, crossings, n_trivial, pad;
 };
 struct pc_final {
     pc_s128 s1, s2t, s2e, s2h, p2, phi;
     uint64_t pi;
     uint64_t ok;
 };
+// Batches: the queries' set-up (X_b, S1, per-b leaf set-up, easy offsets),
+// their easy leaves, and their carries and combination, each over all queries
+// of the batch.  bq / bf: the query of each block, the first block of each
+// query (bf[nq] = blocks).
+hipError_t pc_launch_batch_setup(const pc_tables &T, const pc_query *Qs, const uint32_t *bq_xb,
+                                 const uint32_t *bf_xb, uint32_t nb_xb, const uint32_t *bq_s1,
+                                 const uint32_t *bf_s1, uint32_t nb_s1, uint32_t nq,
+                                 hipStream_t s);
+hipError_t pc_launch_batch_easy(const pc_tables &T, const pc_query *Qs, const uint32_t *bq,
+                                const uint32_t *bf, uint32_t nblocks, hipStream_t s);
+hipError_t pc_launch_batch_finish(const pc_query *Qs, const uint32_t *bq, const uint32_t *bf,
+                                  uint32_t nblocks, uint32_t nq, pc_final *out, hipStream_t s);
+
 hipError_t pc_launch_combine(const pc_sums *sums, const pc_query &Q, uint64_t kp2,
                              pc_final *out, hipStream_t s);

@@ -1,0 +1,201 @@
+// pc_leafwork.h -- the per-item work of the parts of phi(x, a) = S1 + S2 that
+// need no sieve, shared by the one-query kernels (pc_leaves.hip) and the
+// batched kernels (pc_batch.hip):
+//   S1  ordinary leaves  sum_{n <= y, mu(n) != 0, lpf(n) > p_c} mu(n) phi(x/n, c),
+//       phi(u, c) from the wheel (Section 4: phi(m, c) in O(1));
+//   S2t trivial special leaves (u = x/(m p_b) < p_b, phi = 1; m is then prime);
+//   S2e easy special leaves (p_b <= u < p_b^2, u <= y), Legendre's formula
+//       phi(u, b-1) = pi(u) - b + 2 (Section 4), independent of each other
+//       (Section 3);
+// and the final combination pi(x) = phi(x, a) + a - 1 - P2.
+#pragma once
+
+#include "pc_block.h"
+#include "pc_internal.h"
+
+#define PC_MODEBIT (1ull << 63)
+
+// X_b = floor(x / p_b) for 1 <= b <= a (X_0 = x).
+__device__ __forceinline__ void pc_xb_item(const pc_tables &T, const pc_query &Q, uint32_t b)
+{
+    if (b == 0)
+        Q.Xb_w[0] = Q.x;
+    else if (b <= Q.a)
+        Q.Xb_w[b] = pc_div(Q.x, T.primes[b], T.recip[b]);
+}
+
+// The S1 term of n (pcc = p_c): adds mu(n) phi(x/n, c) to *acc when n <= y is
+// squarefree with lpf(n) > p_c, and returns whether it did.
+__device__ __forceinline__ bool pc_s1_item(const pc_tables &T, const pc_query &Q, uint32_t pcc,
+                                           uint64_t n, pc_s128 *acc)
+{
+    const int32_t v = T.mulpf[n];
+    const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
+    if (v == 0 || l <= pcc) // mu(n) = 0, or n has a prime factor <= p_c
+        return false;
+    const uint64_t u = pc_div_any(Q.x, (uint32_t)n);
+    const uint64_t qq = pc_div(u, Q.Qc, Q.recip_Qc);
+    const uint64_t phi = qq * T.phiQ + T.phitab[u - qq * Q.Qc];
+    *acc += v > 0 ? (pc_s128)phi : -(pc_s128)phi;
+    return true;
+}
+
+// Per-b set-up of the special leaves outside the sieve, c < b < a:
+//   trivial leaves: primes m with max(p_b, x/p_b^2) < m <= y  (counted);
+//   easy range:     max(y/p_b, H_b, p_b) < m <= min(y, x/p_b^2),
+//                   H_b = max(x/p_b^3, x/(p_b (y+1)));
+// for p_b^2 > y every m in the range is prime, so the range is stored as
+// prime indices; otherwise as candidate m (bit 63 of the count).  For a
+// sieving prime it also records the u range of its hard leaves (Ub) and the
+// odd multiples below the sieve end (*cross).
+__device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_query &Q,
+                                                   uint32_t b, uint64_t *triv, uint64_t *cross)
+{
+    *triv = 0;
+    *cross = 0;
+    if (b > Q.c && b <= Q.c + Q.nb) { // a sieving prime
+        const uint64_t p = T.primes[b], rp = T.recip[b], X = Q.Xb[b];
+        // odd multiples k p_b, k odd, below the sieve end
+        *cross = (pc_div(Q.sieve_end - 1, p, rp) + 1) / 2;
+        // u range of the hard leaves of b: y/p < m <= y, m > p, m <= max(x/p^3, x/(p(y+1)))
+        uint64_t m1 = pc_div(Q.y, p, rp) + 1;
+        if (m1 < p + 1)
+            m1 = p + 1;
+        const uint64_t h1 = pc_div(pc_div(X, p, rp), p, rp);
+        const uint64_t h2 = pc_div(X, Q.y1, Q.recip_y1);
+        uint64_t m2 = h1 > h2 ? h1 : h2;
+        if (m2 > Q.y)
+            m2 = Q.y;
+        ulonglong2 ub;
+        ub.x = 1;
+        ub.y = 0;
+        if (m1 <= m2) {
+            ub.x = pc_div_small_q(X, (uint32_t)m2);
+            ub.y = pc_div_small_q(X, (uint32_t)m1);
+        }
+        Q.Ub_w[b] = ub;
+    }
+    if (b <= Q.a) {
+        uint64_t st = 0, cn = 0;
+        if (b > Q.c && b < Q.a) {
+            const uint64_t p = T.primes[b], rp = T.recip[b];
+            const uint64_t X = Q.Xb[b];
+            const uint64_t tp = pc_div(X, p, rp); // floor(x / p^2): u >= p  <=>  m <= tp
+            uint64_t m1 = pc_div(Q.y, p, rp) + 1;
+            if (m1 < p + 1)
+                m1 = p + 1;
+            const uint64_t h1 = pc_div(tp, p, rp);
+            const uint64_t h2 = pc_div(X, Q.y1, Q.recip_y1);
+            const uint64_t H = h1 > h2 ? h1 : h2;
+            uint64_t e1 = H + 1 > m1 ? H + 1 : m1;
+            uint64_t e2 = tp < Q.y ? tp : Q.y;
+            if (p > Q.sqrty) {
+                if (e1 <= e2) {
+                    const uint64_t k1 = pc_pi_lookup(T.pitab, e1 - 1) + 1;
+                    const uint64_t k2 = pc_pi_lookup(T.pitab, e2);
+                    if (k1 <= k2) {
+                        st = k1;
+                        cn = k2 - k1 + 1;
+                    }
+                }
+                // trivial: m prime, m > max(m1 - 1, tp), m <= y
+                uint64_t t0 = tp > m1 - 1 ? tp : m1 - 1;
+                if (t0 < Q.y)
+                    *triv = Q.a - pc_pi_lookup(T.pitab, t0);
+            } else if (e1 <= e2) {
+                st = e1;
+                cn = (e2 - e1 + 1) | PC_MODEBIT;
+            }
+        }
+        Q.e_start[b] = st;
+        Q.e_count[b] = cn;
+    }
+}
+
+// Easy leaves, items laid end to end over b (e_off = exclusive prefix of the
+// counts, e_total their sum).  The calling workgroup (NT threads; every thread
+// calls) takes tiles lb, lb + nlb, ... of NT * PER consecutive items; one
+// search finds the b of a tile's first item, then thread t takes items
+// i0 + t, i0 + t + NT, ... so neighbouring lanes read neighbouring primes m
+// and neighbouring pi(u) entries.  u = x/(m p_b) <= y < 2^50, so the fp64
+// estimate quotient is exact after its remainder check.
+template <int NT, int PER>
+__device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query &Q, uint64_t lb,
+                                              uint64_t nlb, uint32_t *s_b0, int64_t *acc,
+                                              unsigned long long *nleaf)
+{
+    constexpr uint64_t TILE = (uint64_t)NT * PER;
+    const uint64_t E = *Q.e_total;
+    const uint64_t *e_off = Q.e_off, *e_count = Q.e_count, *e_start = Q.e_start;
+    for (uint64_t i0 = lb * TILE; i0 < E; i0 += nlb * TILE) {
+        if (threadIdx.x == 0) { // b with e_off[b] <= i0 < e_off[b+1], b in [c+1, a-1]
+            uint32_t lo_b = Q.c + 1, hi_b = Q.a - 1;
+            while (lo_b < hi_b) {
+                const uint32_t mid = (lo_b + hi_b + 1) >> 1;
+                if (e_off[mid] <= i0)
+                    lo_b = mid;
+                else
+                    hi_b = mid - 1;
+            }
+            *s_b0 = lo_b;
+        }
+        __syncthreads();
+        uint32_t b = *s_b0;
+        uint64_t off = e_off[b], cn = e_count[b], st = e_start[b], X = Q.Xb[b];
+        uint32_t p = T.primes[b];
+        const uint64_t iend = i0 + TILE < E ? i0 + TILE : E;
+        for (uint64_t i = i0 + threadIdx.x; i < iend; i += NT) {
+            while (i >= off + (cn & ~PC_MODEBIT)) {
+                b++;
+                off = e_off[b];
+                cn = e_count[b];
+                st = e_start[b];
+                X = Q.Xb[b];
+                p = T.primes[b];
+            }
+            const uint64_t o = i - off;
+            uint32_t m;
+            int32_t w;
+            if (cn & PC_MODEBIT) {
+                m = (uint32_t)(st + o);
+                const int32_t v = T.mulpf[m];
+                const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
+                if (l <= p) // mu(m) = 0 or lpf(m) <= p_b
+                    continue;
+                w = v > 0 ? -1 : 1;
+            } else {
+                m = T.primes[st + o];
+                w = 1;
+            }
+            const uint64_t u = pc_div_small_q(X, m);
+            *acc += (int64_t)w * ((int64_t)pc_pi_lookup(T.pitab, u) - (int64_t)b + 2);
+            (*nleaf)++;
+        }
+        __syncthreads();
+    }
+}
+
+// pi(x) = S1 + S2t + S2e + S2h + a - 1 - P2, with
+//   S2h = in-segment sums + sum w * carry, and
+//   P2  = sum_{k=a+1}^{kx} (phi(x/p_k, B) + B - 1) - sum_{k=a+1}^{kx} (k - 1),
+//   B = c + nb = max(c, bmax) primes crossed by the sieve.
+__device__ __forceinline__ void pc_combine_one(const pc_sums &S, const pc_query &Q, uint64_t kp2,
+                                               pc_final *out)
+{
+    const pc_s128 s2h = S.hard_local + S.hard_dot;
+    const pc_s128 B = (pc_s128)(Q.c + Q.nb);
+    const pc_s128 a = Q.a, K = kp2;
+    pc_s128 p2 = S.p2_local + S.p2_dot;
+    if (K > a)
+        p2 += (K - a) * (B - 1) - ((K - 1) * K / 2 - (a - 1) * a / 2);
+    const pc_s128 phi = S.s1 + S.s2t + S.s2e + s2h;
+    const pc_s128 pi = phi + a - 1 - p2;
+    out->s1 = S.s1;
+    out->s2t = S.s2t;
+    out->s2e = S.s2e;
+    out->s2h = s2h;
+    out->p2 = p2;
+    out->phi = phi;
+    out->pi = (uint64_t)pi;
+    out->ok = (pi >= 0 && (pi >> 64) == 0) ? 1 : 0;
+}

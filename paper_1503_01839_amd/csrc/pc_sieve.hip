@@ -130,7 +130,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
     if (tile.col_lo >= tile.col_hi) { // a split that owns no column
-        if (MODE != PC_MODE_COUNT && tid == 0) {
+        if (MODE != PC_MODE_COUNT && tid == 0 && A.part_hard) {
             A.part_hard[blockIdx.x] = 0;
             A.part_p2[blockIdx.x] = 0;
         }
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     const uint64_t lo = A.lo_base + ((seg - A.seg_base) << (LOG2_S + 1));
     const uint64_t hi = lo + (2ull << LOG2_S);
     const uint64_t row = seg - A.seg0;
-    const pc_query &Q = A.Q;
+    const pc_query &Q = A.Qs[tile.q];
     const pc_tables &TB = A.T;
     const uint64_t rhi = pc_recip(hi);
     const uint64_t rlo = lo ? pc_recip(lo) : 0;
@@ -669,11 +669,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 if (col >= col_lo && col < col_hi) {
                     const uint64_t idx = row * ncol + col;
                     if (MODE != PC_MODE_LEAVES)
-                        A.cnt[idx] = total - ex;
+                        Q.cnt[idx] = total - ex;
                     if (MODE == PC_MODE_TALLY)
-                        A.wgt[idx] = c_w[tid];
+                        Q.wgt[idx] = c_w[tid];
                     if (MODE == PC_MODE_LEAVES && c_w[tid] != 0)
-                        acc_carry += (pc_s128)c_w[tid] * (pc_s128)A.carry[idx];
+                        acc_carry += (pc_s128)c_w[tid] * (pc_s128)Q.carry[idx];
                 }
             }
             total -= tot;
@@ -710,11 +710,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             const uint64_t idx = row * ncol + Q.nb;
             const uint32_t np = k2 >= k1 ? k2 - k1 + 1 : 0;
             if (MODE != PC_MODE_LEAVES)
-                A.cnt[idx] = total;
+                Q.cnt[idx] = total;
             if (MODE == PC_MODE_TALLY)
-                A.wgt[idx] = (int32_t)np;
+                Q.wgt[idx] = (int32_t)np;
             if (MODE == PC_MODE_LEAVES)
-                extra_p2 = (pc_s128)np * (pc_s128)A.carry[idx];
+                extra_p2 = (pc_s128)np * (pc_s128)Q.carry[idx];
         }
     }
 #undef BW
@@ -746,8 +746,13 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             }
         }
         if (tid == 0) {
-            A.part_hard[blockIdx.x] = h;
-            A.part_p2[blockIdx.x] = q;
+            if (A.part_hard) {
+                A.part_hard[blockIdx.x] = h;
+                A.part_p2[blockIdx.x] = q;
+            } else {
+                pc_atomic_add128(&Q.sums->hard_local, h);
+                pc_atomic_add128(&Q.sums->p2_local, q);
+            }
         }
     }
 }

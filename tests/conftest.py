@@ -36,3 +36,11 @@ def paper_pow10():
 @pytest.fixture(scope="session")
 def paper_pow2():
     return read_table("paper_pi_pow2.txt")
+
+
+@pytest.fixture(scope="session")
+def pc():
+    """The HIP library's Python binding (raises if libpicount.so is missing)."""
+    import paper_1503_01839_amd as pc
+    pc.lib()
+    return pc

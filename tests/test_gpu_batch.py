@@ -1,0 +1,60 @@
+"""Batched pi(x) on the GPU: every result of a batch equals the same query
+run alone (the plain per-query path, itself pinned to the oracle and to the
+paper's tables), whether the batch runs as a HIP graph, phase by phase, or one
+query after another.  Inputs: x log-uniform from a fixed seed, plus edge
+values (tiny x, duplicates, Table 1 and Table 2 entries)."""
+import random
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def log_uniform(n, lo_exp, hi_exp, seed):
+    rng = random.Random(seed)
+    return [int(10 ** rng.uniform(lo_exp, hi_exp)) for _ in range(n)]
+
+
+def test_batch_equals_solo(pc):
+    xs = log_uniform(96, 8, 12.5, 1503)
+    say("case: batch vs solo", len(xs))
+    solo = [pc.pi_count(x) for x in xs]
+    assert pc.pi_count_batch(xs) == solo
+    assert pc.pi_count_batch(xs, flags=pc.FLAG_NO_GRAPH) == solo
+    assert pc.pi_count_batch(xs, flags=pc.FLAG_BATCH_SEQUENTIAL) == solo
+
+
+def test_batch_edges(pc, paper_pow10, paper_pow2):
+    xs = [0, 1, 2, 3, 4, 100, 2**20 - 1, 2**20, 2**20 + 1, 10**9, 10**9, 10**11, 2**40,
+          10**13, 7, 10**8]
+    say("case: batch edges")
+    got = pc.pi_count_batch(xs)
+    assert got[:6] == [0, 0, 1, 2, 2, 25]
+    assert got[9] == got[10] == paper_pow10[9]
+    assert got[11] == paper_pow10[11]
+    assert got[12] == paper_pow2[40]
+    assert got[13] == paper_pow10[13]
+    assert got == [pc.pi_count(x) for x in xs]
+    assert pc.pi_count_batch([]) == []
+
+
+def test_batch_rounds_and_windows(pc):
+    # a small carry budget splits the batch into many rounds, and sends the
+    # queries that do not fit alone to the windowed path
+    xs = log_uniform(40, 9, 13, 1839)
+    say("case: batch rounds")
+    solo = [pc.pi_count(x) for x in xs]
+    for budget in (1 << 20, 1 << 24):
+        assert pc.pi_count_batch(xs, carry_budget=budget) == solo, budget
+
+
+def test_batch_alpha_invariance(pc):
+    xs = log_uniform(32, 10, 13, 7)
+    say("case: batch alpha")
+    ref = pc.pi_count_batch(xs)
+    for alpha in (1, 3):
+        assert pc.pi_count_batch(xs, alpha=alpha) == ref, alpha

@@ -15,12 +15,6 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_decomp.json")
 
 
-@pytest.fixture(scope="module")
-def pc():
-    import paper_1503_01839_amd as pc
-    return pc
-
-
 def golden():
     with open(GOLDEN) as f:
         return json.load(f)["records"]
