@@ -132,6 +132,39 @@ pc_status pc_pi_count_batch(const uint64_t *xs, size_t n, uint64_t *pi_out);
 pc_status pc_pi_count_batch_ex(const uint64_t *xs, size_t n, const pc_config *cfg,
                                uint64_t *pi_out);
 
+/* Serving: an open-loop stream of pi(x) requests replayed in real time, with
+ * continuous batching.  Request i (x = xs[i]) arrives arrival_s[i] seconds
+ * after the call starts (non-decreasing, finite, >= 0).  Arrived requests wait
+ * in order; whenever one of max_inflight slots (a stream and its buffers) is
+ * free and the device-memory budget allows, the waiting requests go to the
+ * device as one batch round (as pc_pi_count_batch), so later arrivals overlap
+ * the rounds already running.  A request whose per-segment counts exceed a
+ * round's budget runs alone, windowed, beside the rounds.  pi_out[i] = pi(xs[i])
+ * (identical to pc_pi_count), latency_s_out[i] (may be NULL) = completion -
+ * arrival on the host clock.  max_inflight = max_round = 1 is the plain
+ * per-query server.  Host arrays of n elements; outputs written only on PC_OK. */
+typedef struct {
+    uint32_t max_inflight; /* batch rounds on the device at once, 1..16; 0 = 3            */
+    uint32_t max_round;    /* requests per round; 0 = 4096                                 */
+    uint64_t mem_budget;   /* device bytes for the counts of the rounds in flight; 0 = 18 GiB */
+    double alpha;          /* y = alpha * icbrt(x) for every request; 0 = tuned             */
+    uint32_t flags;        /* PC_FLAG_NO_GRAPH                                              */
+    uint32_t pad;
+} pc_serve_config;
+
+typedef struct {
+    double wall_s;              /* start of the replay to the last completion          */
+    uint64_t rounds;            /* batch rounds launched                                */
+    uint64_t windowed;          /* requests run alone through the windowed path         */
+    uint64_t max_round_size;    /* most requests in one round                           */
+    uint64_t max_inflight_seen; /* most rounds on the device at once                    */
+    uint64_t device_bytes;      /* peak device bytes held by the library                */
+} pc_serve_stats;
+
+pc_status pc_serve(const uint64_t *xs, const double *arrival_s, size_t n,
+                   const pc_serve_config *cfg, uint64_t *pi_out, double *latency_s_out,
+                   pc_serve_stats *stats);
+
 /* Wheel size c used by the library (c = min(pc_wheel_c(), a)). */
 int pc_wheel_c(void);
 

@@ -23,8 +23,8 @@ FLAG_NO_GRAPH = 16
 FLAG_BATCH_SEQUENTIAL = 32
 
 EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
-           "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_wheel_c", "pc_status_str",
-           "pc_last_error", "pc_shutdown"]
+           "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_serve", "pc_wheel_c",
+           "pc_status_str", "pc_last_error", "pc_shutdown"]
 
 
 class PicountError(RuntimeError):
@@ -96,6 +96,17 @@ class Result:
     ms_k_easy: float
     ms_k_s1: float
 
+class ServeConfig(C.Structure):
+    _fields_ = [("max_inflight", C.c_uint32), ("max_round", C.c_uint32),
+                ("mem_budget", C.c_uint64), ("alpha", C.c_double), ("flags", C.c_uint32),
+                ("pad", C.c_uint32)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("wall_s", C.c_double)] + [(n, C.c_uint64) for n in (
+        "rounds", "windowed", "max_round_size", "max_inflight_seen", "device_bytes")]
+
+
 _lib = None
 
 
@@ -115,8 +126,10 @@ def lib():
         L.pc_p2.argtypes = [u64, u64, P(u64)]
         L.pc_pi_count_batch.argtypes = [P(u64), C.c_size_t, P(u64)]
         L.pc_pi_count_batch_ex.argtypes = [P(u64), C.c_size_t, P(Config), P(u64)]
+        L.pc_serve.argtypes = [P(u64), P(C.c_double), C.c_size_t, P(ServeConfig), P(u64),
+                               P(C.c_double), P(ServeStats)]
         for f in ("pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
-                  "pc_pi_count_batch", "pc_pi_count_batch_ex"):
+                  "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_serve"):
             getattr(L, f).restype = C.c_int
         L.pc_wheel_c.restype = C.c_int
         L.pc_status_str.argtypes = [C.c_int]
@@ -192,6 +205,28 @@ def pi_count_batch(xs, **cfg) -> list[int]:
     else:
         _check(lib().pc_pi_count_batch(arr, n, out))
     return list(out[:n])
+
+
+def serve(xs, arrivals, max_inflight=0, max_round=0, mem_budget=0, alpha=0.0, flags=0):
+    """Replay an open-loop request stream (x values, arrival times in seconds)
+    in real time with continuous batching; returns (pi values, latencies in
+    seconds, stats dict)."""
+    xs = list(xs)
+    arrivals = [float(t) for t in arrivals]
+    n = len(xs)
+    if len(arrivals) != n:
+        raise ValueError("xs and arrivals differ in length")
+    if n == 0:
+        return [], [], {}
+    xa = (C.c_uint64 * n)(*xs)
+    ta = (C.c_double * n)(*arrivals)
+    out = (C.c_uint64 * n)()
+    lat = (C.c_double * n)()
+    st = ServeStats()
+    cfg = ServeConfig(max_inflight, max_round, mem_budget, float(alpha), flags, 0)
+    _check(lib().pc_serve(xa, ta, n, C.byref(cfg), out, lat, C.byref(st)))
+    stats = {f: getattr(st, f) for f, _ in ServeStats._fields_}
+    return list(out), list(lat), stats
 
 
 def wheel_c() -> int:

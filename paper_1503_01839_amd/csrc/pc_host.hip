@@ -6,13 +6,18 @@
 // back one small result record.  Every arithmetic step of the method runs
 // in the kernels of pc_tables.hip, pc_leaves.hip and pc_sieve.hip.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/picount.h"
@@ -44,7 +49,7 @@ struct DevBuf {
     size_t cap = 0;
 };
 
-size_t g_dev_bytes = 0, g_dev_peak = 0;
+std::atomic<size_t> g_dev_bytes{0}, g_dev_peak{0}; // device bytes held, and their peak
 
 hipStream_t g_stream = nullptr;  // the library stream
 hipStream_t g_stream2 = nullptr; // easy leaves, concurrent with the sieve (same priority)
@@ -78,7 +83,7 @@ void ensure(DevBuf &b, size_t bytes, const char *what)
     }
     b.cap = bytes;
     g_dev_bytes += bytes;
-    g_dev_peak = std::max(g_dev_peak, g_dev_bytes);
+    g_dev_peak = std::max<size_t>(g_dev_peak.load(), g_dev_bytes.load());
 }
 
 template <typename T> T *ptr(DevBuf &b) { return static_cast<T *>(b.p); }
@@ -927,20 +932,84 @@ struct BatchQuery {
     uint64_t bytes() const { return nseg * ncol * 8; }
 };
 
-struct BatchBufs {
-    DevBuf arena, qs, tiles, blk;
-};
-BatchBufs g_Bt;
-
 constexpr uint32_t kBatchLog2S = 18; // 32 KiB segments
 constexpr uint32_t kBatchWG = 512;
 
-void run_batch_round(const std::vector<BatchQuery> &R, const Knobs &K, bool use_graph,
-                     uint64_t *out)
+// Everything one batch round keeps while it is on the device: its stream
+// (null: the library stream), buffers, pinned results, and the host arrays
+// its copies read from.
+struct BatchSlot {
+    hipStream_t st = nullptr;
+    DevBuf arena, qs, tiles, blk, err;
+    pc_final *h_fin = nullptr; // pinned
+    size_t h_fin_cap = 0;
+    int32_t *h_err = nullptr;  // pinned
+    hipEvent_t done = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<BatchQuery> R;
+    std::vector<pc_query> Qv;
+    std::vector<pc_tile> tiles_h;
+    std::vector<uint32_t> blk_h;
+    uint64_t bytes = 0;
+    bool busy = false;
+};
+
+// grow a slot buffer, waiting only for the slot's own stream
+void slot_ensure(BatchSlot &sl, DevBuf &b, size_t bytes, const char *what)
 {
+    if (bytes == 0)
+        bytes = 16;
+    if (b.cap >= bytes)
+        return;
+    if (b.p) {
+        (void)hipStreamSynchronize(sl.st ? sl.st : g_stream);
+        (void)hipFree(b.p);
+        g_dev_bytes -= b.cap;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(PC_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) +
+                            " bytes for " + what + " failed");
+    }
+    b.cap = bytes;
+    g_dev_bytes += bytes;
+    g_dev_peak = std::max<size_t>(g_dev_peak.load(), g_dev_bytes.load());
+}
+
+void slot_release(BatchSlot &sl)
+{
+    if (sl.st)
+        (void)hipStreamSynchronize(sl.st);
+    for (DevBuf *b : {&sl.arena, &sl.qs, &sl.tiles, &sl.blk, &sl.err})
+        if (b->p) {
+            (void)hipFree(b->p);
+            g_dev_bytes -= b->cap;
+            b->p = nullptr;
+            b->cap = 0;
+        }
+    if (sl.h_fin)
+        (void)hipHostFree(sl.h_fin);
+    if (sl.h_err)
+        (void)hipHostFree(sl.h_err);
+    if (sl.done)
+        (void)hipEventDestroy(sl.done);
+    if (sl.st)
+        (void)hipStreamDestroy(sl.st);
+    sl = BatchSlot{};
+}
+
+// Queue one round (sl.R) on the slot's stream: set-up, easy leaves, sieve,
+// carries, combination (as a HIP graph unless use_graph is false), then the
+// copies of the results into pinned memory and the slot's completion event.
+void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
+{
+    const std::vector<BatchQuery> &R = sl.R;
     const uint32_t nq = (uint32_t)R.size();
     const uint64_t S = 1ull << kBatchLog2S;
-    QueryBufs &QB = g_Q;
+    hipStream_t st = sl.st ? sl.st : g_stream;
     const pc_tables T = tables_view(kWheelC);
 
     // arena: sums, easy totals, results, then each query's arrays
@@ -952,26 +1021,35 @@ void run_batch_round(const std::vector<BatchQuery> &R, const Knobs &K, bool use_
     };
     const size_t o_sums = take(nq * sizeof(pc_sums)), o_et = take(nq * 8),
                  o_fin = take(nq * sizeof(pc_final));
-    std::vector<size_t> o_xb(nq), o_ub(nq), o_es(nq), o_ec(nq), o_eo(nq), o_cnt(nq), o_wgt(nq);
-    for (uint32_t i = 0; i < nq; i++) {
-        const uint64_t na = R[i].a + 2;
-        o_xb[i] = take(na * 8);
-        o_ub[i] = take(na * 16);
-        o_es[i] = take(na * 8);
-        o_ec[i] = take(na * 8);
-        o_eo[i] = take(na * 8);
-        o_cnt[i] = take(R[i].nseg * R[i].ncol * 4);
-        o_wgt[i] = take(R[i].nseg * R[i].ncol * 4);
-    }
-    ensure(g_Bt.arena, tot, "batch arena");
-    char *base = static_cast<char *>(g_Bt.arena.p);
+    // each query's chunk: X_b, Ub, three easy arrays, counts, weights, each
+    // rounded up to 256 bytes exactly as carve() below takes them
+    auto r256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    auto chunk = [&](const BatchQuery &b) {
+        const size_t na = b.a + 2, cells = b.nseg * b.ncol;
+        return r256(na * 8) + r256(na * 16) + 3 * r256(na * 8) + 2 * r256(cells * 4);
+    };
+    std::vector<size_t> o_q(nq);
+    for (uint32_t i = 0; i < nq; i++)
+        o_q[i] = take(chunk(R[i]));
+    slot_ensure(sl, sl.arena, tot, "batch arena");
+    char *base = static_cast<char *>(sl.arena.p);
     pc_sums *sums = reinterpret_cast<pc_sums *>(base + o_sums);
     pc_final *fin = reinterpret_cast<pc_final *>(base + o_fin);
 
-    std::vector<pc_query> Qv(nq);
+    sl.Qv.assign(nq, pc_query{});
     for (uint32_t i = 0; i < nq; i++) {
         const BatchQuery &b = R[i];
-        pc_query &Q = Qv[i];
+        pc_query &Q = sl.Qv[i];
+        size_t o = o_q[i];
+        const size_t o_end = o_q[i] + chunk(b);
+        auto carve = [&](size_t bytes) {
+            char *p = base + o;
+            o += r256(bytes);
+            if (o > o_end) // the chunk sizes above and these carves must agree
+                fail(PC_EINTERNAL, "batch arena layout");
+            return p;
+        };
+        const uint64_t na = b.a + 2;
         Q.x = b.x;
         Q.y = b.y;
         Q.z = b.z;
@@ -987,24 +1065,24 @@ void run_batch_round(const std::vector<BatchQuery> &R, const Knobs &K, bool use_
         Q.nb = b.nb;
         Q.ncol = b.ncol;
         Q.kx = (uint32_t)b.kx;
-        Q.Xb = Q.Xb_w = reinterpret_cast<uint64_t *>(base + o_xb[i]);
-        Q.Ub = Q.Ub_w = reinterpret_cast<ulonglong2 *>(base + o_ub[i]);
-        Q.e_start = reinterpret_cast<uint64_t *>(base + o_es[i]);
-        Q.e_count = reinterpret_cast<uint64_t *>(base + o_ec[i]);
-        Q.e_off = reinterpret_cast<uint64_t *>(base + o_eo[i]);
+        Q.Xb = Q.Xb_w = reinterpret_cast<uint64_t *>(carve(na * 8));
+        Q.Ub = Q.Ub_w = reinterpret_cast<ulonglong2 *>(carve(na * 16));
+        Q.e_start = reinterpret_cast<uint64_t *>(carve(na * 8));
+        Q.e_count = reinterpret_cast<uint64_t *>(carve(na * 8));
+        Q.e_off = reinterpret_cast<uint64_t *>(carve(na * 8));
+        Q.cnt = reinterpret_cast<uint32_t *>(carve(b.nseg * b.ncol * 4));
+        Q.wgt = reinterpret_cast<int32_t *>(carve(b.nseg * b.ncol * 4));
         Q.e_total = reinterpret_cast<uint64_t *>(base + o_et) + i;
         Q.sums = sums + i;
-        Q.cnt = reinterpret_cast<uint32_t *>(base + o_cnt[i]);
-        Q.wgt = reinterpret_cast<int32_t *>(base + o_wgt[i]);
         Q.carry = nullptr;
         Q.nseg = b.nseg;
         Q.sieve_end = b.nseg * 2 * S;
     }
 
     // block tables: the query of each block and each query's first block
-    std::vector<uint32_t> blk;
+    sl.blk_h.clear();
     auto table = [&](auto nblocks_of, uint32_t *nblocks) {
-        const size_t at = blk.size();
+        const size_t at = sl.blk_h.size();
         std::vector<uint32_t> first(nq + 1);
         uint32_t nbk = 0;
         for (uint32_t i = 0; i < nq; i++) {
@@ -1014,15 +1092,20 @@ void run_batch_round(const std::vector<BatchQuery> &R, const Knobs &K, bool use_
         first[nq] = nbk;
         for (uint32_t i = 0; i < nq; i++)
             for (uint32_t k = first[i]; k < first[i + 1]; k++)
-                blk.push_back(i);
-        blk.insert(blk.end(), first.begin(), first.end());
+                sl.blk_h.push_back(i);
+        sl.blk_h.insert(sl.blk_h.end(), first.begin(), first.end());
         *nblocks = nbk;
         return at; // q at [at, at + nbk), first at [at + nbk, at + nbk + nq + 1)
     };
     uint32_t nb_xb, nb_s1, nb_ez, nb_sc;
-    const size_t t_xb = table([](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, (b.a + 2 + 255) / 256); }, &nb_xb);
-    const size_t t_s1 = table([](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, b.y / 4096 + 1); }, &nb_s1);
-    const size_t t_ez = table([](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(1024, b.y / 4096 + 1); }, &nb_ez);
+    const size_t t_xb = table(
+        [](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, (b.a + 2 + 255) / 256); },
+        &nb_xb);
+    const size_t t_s1 = table(
+        [](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, b.y / 4096 + 1); }, &nb_s1);
+    const size_t t_ez = table(
+        [](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(1024, b.y / 4096 + 1); },
+        &nb_ez);
     const size_t t_sc = table([](const BatchQuery &b) { return (b.ncol + 255) / 256; }, &nb_sc);
 
     // sieve tiles, largest queries first, each query's low (leaf-dense) segments first
@@ -1031,85 +1114,107 @@ void run_batch_round(const std::vector<BatchQuery> &R, const Knobs &K, bool use_
         order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t u, uint32_t v) { return R[u].bytes() > R[v].bytes(); });
-    std::vector<pc_tile> tiles;
+    sl.tiles_h.clear();
     for (uint32_t i : order)
         for (uint64_t sg = 0; sg < R[i].nseg; sg++)
-            tiles.push_back(pc_tile{(uint32_t)sg, 0, R[i].ncol, i});
+            sl.tiles_h.push_back(pc_tile{(uint32_t)sg, 0, R[i].ncol, i});
 
-    ensure(g_Bt.qs, nq * sizeof(pc_query), "batch queries");
-    ensure(g_Bt.tiles, tiles.size() * sizeof(pc_tile), "batch tiles");
-    ensure(g_Bt.blk, blk.size() * 4, "batch blocks");
-    ensure(QB.err, 8, "error flag");
-    hipck(hipMemcpyAsync(g_Bt.qs.p, Qv.data(), nq * sizeof(pc_query), hipMemcpyHostToDevice, g_stream), "H2D");
-    hipck(hipMemcpyAsync(g_Bt.tiles.p, tiles.data(), tiles.size() * sizeof(pc_tile), hipMemcpyHostToDevice, g_stream), "H2D");
-    hipck(hipMemcpyAsync(g_Bt.blk.p, blk.data(), blk.size() * 4, hipMemcpyHostToDevice, g_stream), "H2D");
-    hipck(pc_launch_fill_u64(ptr<uint64_t>(QB.err), 1, 0, g_stream), "fill");
-    const pc_query *qs = ptr<pc_query>(g_Bt.qs);
-    const uint32_t *bk = ptr<uint32_t>(g_Bt.blk);
+    slot_ensure(sl, sl.qs, nq * sizeof(pc_query), "batch queries");
+    slot_ensure(sl, sl.tiles, sl.tiles_h.size() * sizeof(pc_tile), "batch tiles");
+    slot_ensure(sl, sl.blk, sl.blk_h.size() * 4, "batch blocks");
+    slot_ensure(sl, sl.err, 8, "error flag");
+    if (sl.h_fin_cap < nq) {
+        if (sl.h_fin)
+            (void)hipHostFree(sl.h_fin);
+        sl.h_fin = nullptr;
+        hipck(hipHostMalloc((void **)&sl.h_fin, nq * sizeof(pc_final)), "hipHostMalloc");
+        sl.h_fin_cap = nq;
+    }
+    if (!sl.h_err)
+        hipck(hipHostMalloc((void **)&sl.h_err, 8), "hipHostMalloc");
+    if (!sl.done)
+        hipck(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "hipEventCreate");
+    hipck(hipMemcpyAsync(sl.qs.p, sl.Qv.data(), nq * sizeof(pc_query), hipMemcpyHostToDevice, st),
+          "H2D");
+    hipck(hipMemcpyAsync(sl.tiles.p, sl.tiles_h.data(), sl.tiles_h.size() * sizeof(pc_tile),
+                         hipMemcpyHostToDevice, st),
+          "H2D");
+    hipck(hipMemcpyAsync(sl.blk.p, sl.blk_h.data(), sl.blk_h.size() * 4, hipMemcpyHostToDevice, st),
+          "H2D");
+    const pc_query *qs = ptr<pc_query>(sl.qs);
+    const uint32_t *bk = ptr<uint32_t>(sl.blk);
+    const uint32_t ntiles = (uint32_t)sl.tiles_h.size();
 
     auto launches = [&]() {
-        hipck(pc_launch_fill_u64(reinterpret_cast<uint64_t *>(sums), nq * sizeof(pc_sums) / 8, 0, g_stream), "fill");
+        hipck(pc_launch_fill_u64(ptr<uint64_t>(sl.err), 1, 0, st), "fill");
+        hipck(pc_launch_fill_u64(reinterpret_cast<uint64_t *>(sums), nq * sizeof(pc_sums) / 8, 0, st),
+              "fill");
         hipck(pc_launch_batch_setup(T, qs, bk + t_xb, bk + t_xb + nb_xb, nb_xb, bk + t_s1,
-                                    bk + t_s1 + nb_s1, nb_s1, nq, g_stream),
+                                    bk + t_s1 + nb_s1, nb_s1, nq, st),
               "batch set-up");
-        hipck(pc_launch_batch_easy(T, qs, bk + t_ez, bk + t_ez + nb_ez, nb_ez, g_stream), "batch easy");
+        hipck(pc_launch_batch_easy(T, qs, bk + t_ez, bk + t_ez + nb_ez, nb_ez, st), "batch easy");
         pc_sieve_args A{};
         A.T = T;
         A.Qs = qs;
-        A.tiles = ptr<pc_tile>(g_Bt.tiles);
-        A.ntiles = (uint32_t)tiles.size();
-        A.err = ptr<int32_t>(QB.err);
-        hipck(pc_launch_sieve(A, kBatchLog2S, kBatchWG, PC_MODE_TALLY | (K.batch ? 0 : 0x100), g_stream),
+        A.tiles = ptr<pc_tile>(sl.tiles);
+        A.ntiles = ntiles;
+        A.err = ptr<int32_t>(sl.err);
+        hipck(pc_launch_sieve(A, kBatchLog2S, kBatchWG, PC_MODE_TALLY | (K.batch ? 0 : 0x100), st),
               "batch sieve");
-        hipck(pc_launch_batch_finish(qs, bk + t_sc, bk + t_sc + nb_sc, nb_sc, nq, fin, g_stream),
+        hipck(pc_launch_batch_finish(qs, bk + t_sc, bk + t_sc + nb_sc, nb_sc, nq, fin, st),
               "batch finish");
     };
     if (use_graph) {
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        hipck(hipStreamBeginCapture(g_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        hipck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         try {
             launches();
         } catch (...) {
-            (void)hipStreamEndCapture(g_stream, &graph);
-            if (graph)
-                (void)hipGraphDestroy(graph);
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(st, &g);
+            if (g)
+                (void)hipGraphDestroy(g);
             throw;
         }
-        hipck(hipStreamEndCapture(g_stream, &graph), "hipStreamEndCapture");
-        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e == hipSuccess)
-            e = hipGraphLaunch(exec, g_stream);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(g_stream);
-        if (exec)
-            (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        hipck(e, "batch graph");
+        hipck(hipStreamEndCapture(st, &sl.graph), "hipStreamEndCapture");
+        hipck(hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        hipck(hipGraphLaunch(sl.exec, st), "hipGraphLaunch");
     } else {
         launches();
     }
-    std::vector<pc_final> f(nq);
-    int32_t err = 0;
-    hipck(hipMemcpyAsync(f.data(), fin, nq * sizeof(pc_final), hipMemcpyDeviceToHost, g_stream), "D2H");
-    hipck(hipMemcpyAsync(&err, QB.err.p, 4, hipMemcpyDeviceToHost, g_stream), "D2H");
-    hipck(hipStreamSynchronize(g_stream), "sync");
-    if (err)
+    hipck(hipMemcpyAsync(sl.h_fin, fin, nq * sizeof(pc_final), hipMemcpyDeviceToHost, st), "D2H");
+    hipck(hipMemcpyAsync(sl.h_err, sl.err.p, 4, hipMemcpyDeviceToHost, st), "D2H");
+    hipck(hipEventRecord(sl.done, st), "hipEventRecord");
+    sl.busy = true;
+}
+
+// After the slot's event: results to out[], graph released, slot free.
+void collect_round(BatchSlot &sl, uint64_t *out)
+{
+    if (sl.exec)
+        (void)hipGraphExecDestroy(sl.exec);
+    if (sl.graph)
+        (void)hipGraphDestroy(sl.graph);
+    sl.exec = nullptr;
+    sl.graph = nullptr;
+    sl.busy = false;
+    if (*sl.h_err)
         fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment (batch)");
-    for (uint32_t i = 0; i < nq; i++) {
-        if (!f[i].ok)
+    for (size_t i = 0; i < sl.R.size(); i++) {
+        if (!sl.h_fin[i].ok)
             fail(PC_EINTERNAL, "pi(x) outside [0, 2^64) (batch)");
-        out[R[i].idx] = f[i].pi;
+        out[sl.R[i].idx] = sl.h_fin[i].pi;
     }
 }
 
-void run_batch(const uint64_t *xs, size_t n, const Knobs &K, double alpha, bool use_graph,
-               uint64_t *out)
+BatchSlot g_slot; // the synchronous batch path's slot, on the library stream
+
+// Parameters of every query x >= kSmallX (small x are answered into out),
+// with the tables all of them need.
+std::vector<BatchQuery> plan_queries(const uint64_t *xs, size_t n, double alpha, uint64_t *out)
 {
     if (std::isnan(alpha) || alpha < 0)
         fail(PC_EINVAL, "alpha must be >= 0 (0 = tuned)");
     init_stream();
-    // parameters of every query, and the tables they need
     std::vector<uint64_t> ys(n, 0);
     uint64_t need = kSmallX, ymax = 0;
     for (size_t i = 0; i < n; i++) {
@@ -1123,15 +1228,10 @@ void run_batch(const uint64_t *xs, size_t n, const Knobs &K, double alpha, bool 
     std::vector<uint64_t> pts;
     pts.reserve(3 * n);
     for (size_t i = 0; i < n; i++) {
-        if (xs[i] < kSmallX) {
-            pts.push_back(xs[i]);
-            pts.push_back(0);
-            pts.push_back(0);
-        } else {
-            pts.push_back(ys[i]);
-            pts.push_back(pc_isqrt(xs[i]));
-            pts.push_back(pc_isqrt(xs[i] / ys[i]));
-        }
+        const bool small = xs[i] < kSmallX;
+        pts.push_back(small ? xs[i] : ys[i]);
+        pts.push_back(small ? 0 : pc_isqrt(xs[i]));
+        pts.push_back(small ? 0 : pc_isqrt(xs[i] / ys[i]));
     }
     const std::vector<uint64_t> lk = lookup(pts);
     uint64_t amax = 0;
@@ -1156,19 +1256,29 @@ void run_batch(const uint64_t *xs, size_t n, const Knobs &K, double alpha, bool 
         amax = std::max(amax, b.a);
         big.push_back(b);
     }
-    if (big.empty())
-        return;
-    ensure_mulpf(ymax);
-    ensure_recip(amax + 1);
-    ensure_wheel(kWheelC);
+    if (!big.empty()) {
+        ensure_mulpf(ymax);
+        ensure_recip(amax + 1);
+        ensure_wheel(kWheelC);
+        hipck(hipStreamSynchronize(g_stream), "sync");
+    }
+    return big;
+}
+
+void run_batch(const uint64_t *xs, size_t n, const Knobs &K, double alpha, bool use_graph,
+               uint64_t *out)
+{
+    const std::vector<BatchQuery> big = plan_queries(xs, n, alpha, out);
     // rounds in input order, each within the carry budget
-    std::vector<BatchQuery> round;
-    uint64_t bytes = 0;
+    BatchSlot &sl = g_slot;
     auto flush = [&]() {
-        if (!round.empty())
-            run_batch_round(round, K, use_graph, out);
-        round.clear();
-        bytes = 0;
+        if (sl.R.empty())
+            return;
+        submit_round(sl, K, use_graph);
+        hipck(hipEventSynchronize(sl.done), "hipEventSynchronize");
+        collect_round(sl, out);
+        sl.R.clear();
+        sl.bytes = 0;
     };
     for (const BatchQuery &b : big) {
         if (b.bytes() > K.carry_budget) { // alone, windowed
@@ -1178,12 +1288,206 @@ void run_batch(const uint64_t *xs, size_t n, const Knobs &K, double alpha, bool 
             out[b.idx] = r.pi;
             continue;
         }
-        if (bytes + b.bytes() > K.carry_budget || round.size() >= 65536)
+        if (sl.bytes + b.bytes() > K.carry_budget || sl.R.size() >= 65536)
             flush();
-        round.push_back(b);
-        bytes += b.bytes();
+        sl.R.push_back(b);
+        sl.bytes += b.bytes();
     }
     flush();
+}
+
+// ---------------------------------------------------------------------------
+// Serving: an open-loop request stream replayed in real time.  Requests that
+// have arrived wait in a FIFO; whenever a slot (a stream with its own round
+// buffers) is free and the device-memory budget allows, the waiting requests
+// form a round that goes to the device at once, so rounds of later arrivals
+// overlap the ones already running.  A request whose counts exceed a round's
+// budget runs alone through the windowed path on a worker thread (the library
+// stream), beside the rounds.  x < 2^20 is answered from the pi table on
+// arrival.  Latency = completion - arrival, on the host clock.
+// ---------------------------------------------------------------------------
+void run_serve(const uint64_t *xs, const double *arr, size_t n, const pc_serve_config &C,
+               uint64_t *pi_out, double *lat_out, pc_serve_stats *stats)
+{
+    for (size_t i = 0; i < n; i++) {
+        if (!(arr[i] >= 0) || !std::isfinite(arr[i]))
+            fail(PC_EINVAL, "arrival times must be finite and >= 0");
+        if (i && arr[i] < arr[i - 1])
+            fail(PC_EINVAL, "arrival times must not decrease");
+    }
+    const Knobs K;
+    const bool use_graph = (C.flags & PC_FLAG_NO_GRAPH) == 0;
+    const uint32_t nslot = C.max_inflight ? C.max_inflight : 3;
+    const uint32_t maxr = C.max_round ? C.max_round : 4096;
+    const uint64_t budget = C.mem_budget ? C.mem_budget : (18ull << 30);
+    const uint64_t round_cap = std::min<uint64_t>(K.carry_budget, budget);
+    if (nslot > 16)
+        fail(PC_EINVAL, "max_inflight must be at most 16");
+
+    std::vector<uint64_t> out(n, 0);
+    const std::vector<BatchQuery> big = plan_queries(xs, n, C.alpha, out.data());
+    std::vector<int> kind(n, 0); // 0: answered from the table, 1: rounds, 2: windowed
+    std::vector<const BatchQuery *> byidx(n, nullptr);
+    for (const BatchQuery &b : big) {
+        byidx[b.idx] = &b;
+        kind[b.idx] = b.bytes() > round_cap ? 2 : 1;
+    }
+    std::vector<double> tdone(n, -1.0);
+
+    std::vector<BatchSlot> slots(nslot);
+    std::mutex m;
+    std::condition_variable cv;
+    std::deque<size_t> wq;      // windowed requests waiting
+    std::vector<size_t> wdone;  // finished, not yet counted
+    std::string werr;
+    pc_status wst = PC_OK;
+    bool stop = false;
+    using sclk = std::chrono::steady_clock;
+    const auto t0 = sclk::now();
+    auto now = [&]() { return std::chrono::duration<double>(sclk::now() - t0).count(); };
+    std::thread worker([&]() {
+        for (;;) {
+            size_t i;
+            {
+                std::unique_lock<std::mutex> lk(m);
+                cv.wait(lk, [&] { return stop || !wq.empty(); });
+                if (wq.empty())
+                    return;
+                i = wq.front();
+                wq.pop_front();
+            }
+            pc_status st = PC_OK;
+            std::string msg;
+            try {
+                pc_result r;
+                run_query(xs[i], byidx[i]->y, K, &r);
+                out[i] = r.pi;
+            } catch (const pc_error &e) {
+                st = e.st;
+                msg = e.msg;
+            } catch (...) {
+                st = PC_EINTERNAL;
+                msg = "unexpected exception (windowed request)";
+            }
+            std::lock_guard<std::mutex> lk(m);
+            tdone[i] = now();
+            wdone.push_back(i);
+            if (st != PC_OK && wst == PC_OK) {
+                wst = st;
+                werr = msg;
+            }
+        }
+    });
+    struct Guard { // stop the worker and free the slots however the loop ends
+        std::function<void()> f;
+        ~Guard() { f(); }
+    } guard{[&]() {
+        {
+            std::lock_guard<std::mutex> lk(m);
+            stop = true;
+        }
+        cv.notify_all();
+        if (worker.joinable())
+            worker.join();
+        for (BatchSlot &sl : slots)
+            slot_release(sl);
+    }};
+    for (BatchSlot &sl : slots)
+        hipck(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking), "hipStreamCreate");
+
+    size_t next = 0, ndone = 0;
+    std::deque<size_t> pending;
+    uint64_t inflight = 0, rounds = 0, windowed = 0, max_round = 0, max_inflight_seen = 0;
+    while (ndone < n) {
+        bool moved = false;
+        double t = now();
+        while (next < n && arr[next] <= t) {
+            const size_t i = next++;
+            moved = true;
+            if (kind[i] == 0) {
+                tdone[i] = t;
+                ndone++;
+            } else if (kind[i] == 2) {
+                windowed++;
+                std::lock_guard<std::mutex> lk(m);
+                wq.push_back(i);
+                cv.notify_one();
+            } else {
+                pending.push_back(i);
+            }
+        }
+        uint32_t busy = 0;
+        for (BatchSlot &sl : slots) {
+            if (!sl.busy)
+                continue;
+            const hipError_t e = hipEventQuery(sl.done);
+            if (e == hipErrorNotReady) {
+                busy++;
+                continue;
+            }
+            hipck(e, "hipEventQuery");
+            collect_round(sl, out.data());
+            const double tc = now();
+            for (const BatchQuery &b : sl.R)
+                tdone[b.idx] = tc;
+            ndone += sl.R.size();
+            inflight -= sl.bytes;
+            sl.R.clear();
+            sl.bytes = 0;
+            moved = true;
+        }
+        {
+            std::lock_guard<std::mutex> lk(m);
+            if (wst != PC_OK)
+                fail(wst, werr);
+            ndone += wdone.size();
+            moved |= !wdone.empty();
+            wdone.clear();
+        }
+        for (BatchSlot &sl : slots) {
+            if (sl.busy || pending.empty())
+                continue;
+            const uint64_t room = std::min<uint64_t>(round_cap, budget - inflight);
+            while (!pending.empty() && sl.R.size() < maxr) {
+                const BatchQuery &b = *byidx[pending.front()];
+                if (sl.bytes + b.bytes() > room)
+                    break;
+                sl.R.push_back(b);
+                sl.bytes += b.bytes();
+                pending.pop_front();
+            }
+            if (sl.R.empty())
+                break; // the oldest request waits for memory
+            submit_round(sl, K, use_graph);
+            inflight += sl.bytes;
+            rounds++;
+            max_round = std::max<uint64_t>(max_round, sl.R.size());
+            busy++;
+            moved = true;
+        }
+        max_inflight_seen = std::max<uint64_t>(max_inflight_seen, busy);
+        if (!moved) { // nothing to do until a completion or the next arrival
+            double wait = 2e-4;
+            if (next < n && busy == 0 && pending.empty())
+                wait = std::min(wait, std::max(0.0, arr[next] - now()));
+            std::this_thread::sleep_for(std::chrono::duration<double>(std::max(wait, 2e-5)));
+        }
+    }
+    const double wall = now();
+    for (size_t i = 0; i < n; i++) {
+        pi_out[i] = out[i];
+        if (lat_out)
+            lat_out[i] = tdone[i] - arr[i];
+    }
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        stats->wall_s = wall;
+        stats->rounds = rounds;
+        stats->windowed = windowed;
+        stats->max_round_size = max_round;
+        stats->max_inflight_seen = max_inflight_seen;
+        stats->device_bytes = g_dev_peak.load();
+    }
 }
 
 } // namespace
@@ -1293,6 +1597,31 @@ pc_status pc_pi_count_batch_ex(const uint64_t *xs, size_t n, const pc_config *cf
     return st;
 }
 
+pc_status pc_serve(const uint64_t *xs, const double *arrival_s, size_t n,
+                   const pc_serve_config *cfg, uint64_t *pi_out, double *latency_s_out,
+                   pc_serve_stats *stats)
+{
+    if (n == 0)
+        return PC_OK;
+    if (!xs || !arrival_s || !pi_out)
+        return PC_EINVAL;
+    pc_serve_config C{};
+    if (cfg)
+        C = *cfg;
+    std::vector<uint64_t> out(n);
+    std::vector<double> lat(n);
+    pc_serve_stats st{};
+    pc_status s = guarded([&] { run_serve(xs, arrival_s, n, C, out.data(), lat.data(), &st); });
+    if (s == PC_OK) {
+        memcpy(pi_out, out.data(), n * 8);
+        if (latency_s_out)
+            memcpy(latency_s_out, lat.data(), n * 8);
+        if (stats)
+            *stats = st;
+    }
+    return s;
+}
+
 pc_status pc_pi_count_batch(const uint64_t *xs, size_t n, uint64_t *pi_out)
 {
     return pc_pi_count_batch_ex(xs, n, nullptr, pi_out);
@@ -1324,6 +1653,7 @@ const char *pc_last_error(void) { return t_err.c_str(); }
 void pc_shutdown(void)
 {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    slot_release(g_slot);
     drop_tables();
     drop_query_bufs();
     if (g_stream2) {
@@ -1340,7 +1670,7 @@ void pc_shutdown(void)
             (void)hipEventDestroy(*e);
             *e = nullptr;
         }
-    g_dev_peak = g_dev_bytes;
+    g_dev_peak = g_dev_bytes.load();
 }
 
 } // extern "C"
