@@ -38,8 +38,15 @@ INT_PEAK = CUS * LANES * CLOCK_HZ  # 32-bit integer lane operations per second
 OPS_CROSSING, OPS_VISIT, OPS_LEAF = 3, 8, 18
 
 # Bounded oracle sample of the same workload (alpha = 16, the library's choice
-# at 1e18): the special leaves with 1000 <= b < 1250, hard ones with u <= 5e7.
-CPU_SAMPLE = dict(y=16000000, c=6, b_lo=1000, b_hi=1250, u_max=5 * 10**7)
+# at 1e18): the special leaves with 1000 <= b < 1500, hard ones with u <= 5e7.
+CPU_SAMPLE = dict(y=16000000, c=6, b_lo=1000, b_hi=1500, u_max=5 * 10**7)
+
+# Batch and serving workloads (paper_1503_01839_amd.workloads): 4096 queries
+# log-uniform in [1e8, 1e15] (seed 1503); a Poisson stream log-uniform in
+# [1e10, 1e18] (seed 1839) at a rate frozen at 0.8 x the batched throughput
+# measured on that mix (25.4 queries/s for 1000 requests on MI355X).
+BATCH_N = 4096
+SERVE_RATE = 20.3
 
 # HBM traffic of the sieve kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by the same counters on a plain copy of known size; reported only while
@@ -94,6 +101,49 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes}), flush=True)
 
 
+def batch_leg(pc, n):
+    """n queries in batch rounds (one HIP graph per round) against the plain
+    per-query path, same inputs; results must agree."""
+    from paper_1503_01839_amd import workloads as W
+    xs = W.batch_queries(n)
+    pc.pi_count_batch(xs[:64])
+    t0 = time.perf_counter()
+    rb = pc.pi_count_batch(xs)
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rs = pc.pi_count_batch(xs, flags=pc.FLAG_BATCH_SEQUENTIAL)
+    ts = time.perf_counter() - t0
+    if rb != rs:
+        raise SystemExit("batch results differ from the per-query path")
+    return {"queries": n, "x": "log-uniform [1e8, 1e15], PCG64(1503)", "queries_per_s": n / tb,
+            "ms": tb * 1e3, "plain_queries_per_s": n / ts, "plain_ms": ts * 1e3,
+            "speedup": ts / tb, "match_plain": True}
+
+
+def serve_leg(pc, n):
+    """An open-loop Poisson stream served with continuous batching, and by the
+    one-request-at-a-time server; p50/p99 of completion - arrival."""
+    import numpy as np
+    from paper_1503_01839_amd import workloads as W
+    xs, arr = W.serve_stream(n, rate_per_s=SERVE_RATE)
+    pc.pi_count_batch(xs[:16])
+    out = {"requests": n, "x": "log-uniform [1e10, 1e18], PCG64(1839)",
+           "arrivals": f"Poisson, {SERVE_RATE}/s"}
+    ref = None
+    for name, kw in (("served", {}), ("plain", dict(max_inflight=1, max_round=1))):
+        pis, lat, st = pc.serve(xs, arr, **kw)
+        if ref is None:
+            ref = pis
+        elif pis != ref:
+            raise SystemExit("served results differ from the per-request server")
+        lat = np.array(lat) * 1e3
+        out[name] = {"requests_per_s": n / st["wall_s"], "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "rounds": st["rounds"],
+                     "windowed": st["windowed"], "max_round": st["max_round_size"],
+                     "max_inflight": st["max_inflight_seen"]}
+    return out
+
+
 def cpu_baseline():
     import oracle
     s = CPU_SAMPLE
@@ -119,6 +169,9 @@ def main():
     ap.add_argument("--keep-tables", action="store_true",
                     help="reuse device tables across steps (default: rebuild every step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-queries", type=int, default=BATCH_N, help="0 = skip the batch leg")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests of the serving leg (the full stream is 20000); 0 = skip")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -196,6 +249,10 @@ def main():
         "paper_context": "Table 3: pi(1e18) took 108 node-s (v2015.01.30) on 2x Xeon E5-2670 "
                          "(16 cores); not a target",
     }
+    if args.batch_queries:
+        out["batch"] = batch_leg(pc, args.batch_queries)
+    if args.serve_requests:
+        out["serve"] = serve_leg(pc, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
