@@ -1,0 +1,84 @@
+"""Autotuner for alpha = y / icbrt(x), the one knob that moves work between
+the sieve (which shrinks as alpha grows: z = x / y) and the easy leaves (which
+grow).  For each half decade of x it times pi(x) at every candidate alpha on
+this GPU (tables cached, median of repeats) and writes the winners to
+csrc/pc_alpha_table.h, the table the library reads when alpha = 0.
+
+    python -m paper_1503_01839_amd.autotune            # tune, write the header
+    python -m paper_1503_01839_amd.autotune --dry-run  # tune, print only
+
+Rebuild the library afterwards (__graft_entry__.build())."""
+from __future__ import annotations
+
+import argparse
+import os
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HEADER = os.path.join(HERE, "csrc", "pc_alpha_table.h")
+ALPHAS = [1, 1.5, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48]
+
+
+def candidates(log10x: float) -> list[float]:
+    """alpha values worth timing at this size (small alpha at large x means a
+    sieve too long to be competitive, and minutes of tuning)."""
+    lo = 1 if log10x < 12 else 2 if log10x < 15 else 4 if log10x < 17 else 8
+    return [a for a in ALPHAS if a >= lo]
+
+
+def tune(lo: float = 7.0, hi: float = 19.0, reps: int = 3, log=print) -> list[tuple[float, float, float]]:
+    import paper_1503_01839_amd as pc
+    table = []
+    d = lo
+    while d <= hi + 1e-9:
+        x = int(10 ** d)
+        best = None
+        for a in candidates(d):
+            pc.pi_count_ex(x, alpha=a)  # tables sized for this alpha
+            ts = [pc.pi_count_ex(x, alpha=a).ms_total for _ in range(reps if d < 17 else 2)]
+            t = statistics.median(ts)
+            if best is None or t < best[1]:
+                best = (a, t)
+        table.append((d, best[0], best[1]))
+        log(f"log10 x = {d:4.1f}: alpha {best[0]:5.1f}  {best[1]:9.2f} ms", flush=True)
+        d += 0.5
+    return table
+
+
+def header_text(table) -> str:
+    rows = "\n".join(f"    {{{d:.1f}, {a:g}}}, // {t:.2f} ms" for d, a, t in table)
+    return f"""// pc_alpha_table.h -- alpha = y / icbrt(x) per half decade of x, written by
+// paper_1503_01839_amd/autotune.py from pi(x) timings on MI355X; the entry
+// whose log10 x is nearest is used.  Regenerate with the tuner, do not edit.
+#pragma once
+
+struct pc_alpha_entry {{
+    double log10x;
+    double alpha;
+}};
+
+static const pc_alpha_entry kAlphaTable[] = {{
+{rows}
+}};
+"""
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dry-run", action="store_true")
+    ap.add_argument("--lo", type=float, default=7.0)
+    ap.add_argument("--hi", type=float, default=19.0)
+    ap.add_argument("--out", default=HEADER, help="where to write the header")
+    args = ap.parse_args()
+    table = tune(args.lo, args.hi)
+    text = header_text(table)
+    if args.dry_run:
+        print(text)
+    else:
+        with open(args.out, "w") as f:
+            f.write(text)
+        print("wrote", args.out)
+
+
+if __name__ == "__main__":
+    main()

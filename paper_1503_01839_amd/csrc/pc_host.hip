@@ -22,6 +22,7 @@
 
 #include "../../include/picount.h"
 #include "pc_internal.h"
+#include "pc_alpha_table.h"
 
 namespace {
 
@@ -299,20 +300,18 @@ pc_i128 to_abi(pc_s128 v)
     return r;
 }
 
+// alpha for x from the tuning table (pc_alpha_table.h): the entry nearest in
+// log10 x.  alpha only moves work between the sieve (falls as 1/alpha) and
+// the easy leaves (rise); it never changes a result.
 double default_alpha(uint64_t x)
 {
-    // Tuned on MI355X for 128 KiB-class segments; alpha only moves work
-    // between the sieve (falls as 1/alpha) and the easy leaves (rise).
-    double lx = std::log10((double)x);
-    if (lx < 10)
-        return 1;
-    if (lx < 12)
-        return 2;
-    if (lx < 14)
-        return 4;
-    if (lx < 16.5)
-        return 8;
-    return 16;
+    const double lx = std::log10((double)x);
+    const size_t n = sizeof kAlphaTable / sizeof kAlphaTable[0];
+    size_t best = 0;
+    for (size_t i = 1; i < n; i++)
+        if (std::fabs(kAlphaTable[i].log10x - lx) < std::fabs(kAlphaTable[best].log10x - lx))
+            best = i;
+    return kAlphaTable[best].alpha;
 }
 
 uint64_t choose_y(uint64_t x, double alpha)
