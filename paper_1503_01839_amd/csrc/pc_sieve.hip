@@ -314,8 +314,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 atomicAdd(&c_new[cg0 + lane], v_rem);
             v_rem = 0;
         };
-        // cross p_b of column j in this wave's region, one lane per multiple
-        auto cross_region = [&](uint32_t j) {
+        // the group of 64 columns that holds column j
+        auto ensure_group = [&](uint32_t j) {
             if (j - cg0 >= 64) {
                 flush_removed();
                 cg0 = j;
@@ -346,10 +346,10 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                     v_nm = f < R1 ? quot(R1 - 1 - f) + 1 : 0;
                 }
             }
-            const int32_t k = (int32_t)(j - cg0);
-            const uint32_t nm = (uint32_t)__builtin_amdgcn_readlane((int)v_nm, k);
-            if (nm == 0)
-                return;
+        };
+        // cross column cg0 + k, which has nm > 0 multiples in this wave's
+        // region, one lane per multiple
+        auto cross_k = [&](int32_t k, uint32_t nm) {
             const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)v_f, k);
             const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)v_p, k);
             uint32_t removed = 0;
@@ -367,6 +367,28 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             rc -= removed;
             if (lane == (uint32_t)k)
                 v_rem = removed;
+        };
+        auto cross_region = [&](uint32_t j) {
+            ensure_group(j);
+            const int32_t k = (int32_t)(j - cg0);
+            const uint32_t nm = (uint32_t)__builtin_amdgcn_readlane((int)v_nm, k);
+            if (nm)
+                cross_k(k, nm);
+        };
+        // cross the leafless columns [j, je) in this wave's region, visiting
+        // only those with a multiple in it
+        auto cross_run = [&](uint32_t j, uint32_t je) {
+            while (j < je) {
+                ensure_group(j);
+                const uint32_t ge = min(je, cg0 + 64);
+                uint64_t msk = __ballot(v_nm != 0 && cg0 + lane >= j && cg0 + lane < ge);
+                while (msk) {
+                    const int32_t k = (int32_t)__builtin_ctzll(msk);
+                    msk &= msk - 1;
+                    cross_k(k, (uint32_t)__builtin_amdgcn_readlane((int)v_nm, k));
+                }
+                j = ge;
+            }
         };
 
         // Gather rounds.  The leaves of up to KMAX light leafy columns (whole
@@ -389,7 +411,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             }
             g_used = 0;
         };
-        auto gather = [&](uint32_t j0) {
+        // returns the end of the gathered window: every light leafy column of
+        // [j0, that end) is gathered
+        auto gather = [&](uint32_t j0, uint32_t we) -> uint32_t {
             PC_PH(4);
             __syncthreads(); // every wave is past the open round's columns
             settle();
@@ -403,6 +427,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 if (msk)
                     hvn = min(jend, wd * 64 + (uint32_t)__builtin_ctzll(msk));
             }
+            hvn = min(hvn, we);
             const uint32_t jt = tid;
             uint32_t v = 0;
             if (jt >= j0 && jt < hvn) {
@@ -466,16 +491,12 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             g_used = used;
             __syncthreads();
             PC_PH(2);
+            return min(hvn, gend);
         };
-        // this wave's part of the leaves of gathered column j: it records its
-        // region count, and counts a prefix of its region for each leaf in it
+        // this wave's part of the leaves of gathered column j that lie in its
+        // region: a prefix of the region for each
         auto answer = [&](uint32_t j) {
             const uint32_t g = c_lc[j];
-            const uint32_t k = (g >> 22) & 0x7Fu;
-            if (lane == 0)
-                g_rc[k * NWV + wv] = (uint16_t)rc;
-            if (!((g_rm[k] >> wv) & 1u))
-                return;
             const uint32_t s0 = (g >> 11) & 0x7FFu, s1 = s0 + (g & 0x7FFu);
             bool have = false;
             uint32_t pe = 0, pc0 = 0; // lane prefix of the region's block counts; first block
@@ -572,6 +593,37 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             __syncthreads(); // every read of the column's state precedes its crossing
             PC_PH(3);
         };
+        // Columns [j, we) of one cached group, their light leaves gathered:
+        // each wave visits, in order, the columns that have a leaf in its
+        // region (answered before the crossing) or a multiple in it, then
+        // records its region count before each gathered column (its count at
+        // j minus the removals of the window's earlier columns).
+        auto window = [&](uint32_t j, uint32_t we) {
+            const uint32_t rc0 = rc;
+            const uint32_t col = cg0 + lane;
+            const bool inw = col >= j && col < we;
+            uint32_t g = 0;
+            if (inw)
+                g = c_lc[col];
+            const bool gath = (g & GATH) != 0;
+            const uint32_t ord = (g >> 22) & 0x7Fu;
+            const uint32_t rm = gath ? g_rm[ord] : 0u;
+            const uint64_t own = __ballot(gath && ((rm >> wv) & 1u));
+            const uint64_t crs = __ballot(inw && v_nm != 0);
+            uint64_t todo = own | crs;
+            while (todo) {
+                const int32_t k = (int32_t)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                if ((own >> k) & 1)
+                    answer(cg0 + (uint32_t)k);
+                if ((crs >> k) & 1)
+                    cross_k(k, (uint32_t)__builtin_amdgcn_readlane((int)v_nm, k));
+            }
+            const uint32_t rem = inw ? v_rem : 0u;
+            const uint32_t before = pc_wave_incl_scan_u32(rem) - rem;
+            if (gath)
+                g_rc[ord * NWV + wv] = (uint16_t)(rc0 - before);
+        };
         // Leafless columns [j, jb) of primes with p^3 >= hi, one lane per
         // prime: an integer n = p k unsieved at the start of the run is first
         // removed by p exactly when k = 1 or k >= p.
@@ -628,32 +680,37 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 lw_at = j >> 6;
                 lw = c_leafy[lw_at];
             }
-            const bool lf = (lw >> (j & 63)) & 1;
-            if (lf) {
+            if ((lw >> (j & 63)) & 1) { // leaves, then the crossing
                 const bool hv = (c_heavy[j >> 6] >> (j & 63)) & 1;
                 if (hv) {
                     heavy_col(j);
-                } else {
-                    if (!(c_lc[j] & GATH))
-                        gather(j);
-                    answer(j);
+                    cross_region(j);
+                    j++;
+                } else { // a window within j's group of 64 columns
+                    ensure_group(j);
+                    const uint32_t we = gather(j, min(jend, cg0 + 64));
+                    window(j, we);
+                    j = we;
                 }
-            } else if (BATCH && j >= first_large) {
-                if (jb_next <= j) { // the next leafy column at or after j
-                    uint32_t wd = j >> 6;
-                    uint64_t msk = c_leafy[wd] & (~0ull << (j & 63));
-                    while (!msk && ++wd < (jend + 63) / 64)
-                        msk = c_leafy[wd];
-                    jb_next = msk ? min(jend, wd * 64 + (uint32_t)__builtin_ctzll(msk)) : jend;
-                }
-                if (jb_next - j >= GAPB) {
-                    batch(j, jb_next);
-                    j = jb_next;
-                    continue;
-                }
+                continue;
             }
-            cross_region(j);
-            j++;
+            if (jb_next <= j) { // the next leafy column after j
+                uint32_t wd = j >> 6;
+                uint64_t msk = c_leafy[wd] & (~0ull << (j & 63));
+                while (!msk && ++wd < (jend + 63) / 64)
+                    msk = c_leafy[wd];
+                jb_next = msk ? min(jend, wd * 64 + (uint32_t)__builtin_ctzll(msk)) : jend;
+            }
+            if (BATCH && j >= first_large && jb_next - j >= GAPB) {
+                batch(j, jb_next);
+                j = jb_next;
+                continue;
+            }
+            // a leafless run: stop where large primes begin, so that a long
+            // remainder can still be batched
+            const uint32_t je = j < first_large ? min(jb_next, first_large) : jb_next;
+            cross_run(j, je);
+            j = je;
         }
         flush_removed();
         PC_PH(4);
