@@ -32,11 +32,12 @@ def test_serve_equals_solo(pc):
 
 
 def test_serve_windowed_requests(pc):
-    # a tiny memory budget sends every request through the windowed path
+    # a one-byte memory budget: no request's counts fit a round, so every
+    # request (x >= 2^20) goes through the windowed path
     xs, t = stream(24, 200.0, 9.0, 12.0, 5)
     say("case: serve windowed")
     solo = [pc.pi_count(x) for x in xs]
-    pis, lat, st = pc.serve(xs, t, mem_budget=1 << 12)
+    pis, lat, st = pc.serve(xs, t, mem_budget=1)
     assert pis == solo
     assert st["windowed"] == sum(1 for x in xs if x >= 2**20)
 
