@@ -6,6 +6,21 @@
 
 __device__ __forceinline__ uint32_t pc_lane() { return __lane_id(); }
 
+// A value the whole wavefront holds alike, moved to scalar registers (the
+// compiler then keeps loads through it scalar and out of vector registers).
+__device__ __forceinline__ uint32_t pc_uniform(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t pc_uniform64(uint64_t v)
+{
+    return ((uint64_t)pc_uniform((uint32_t)(v >> 32)) << 32) | pc_uniform((uint32_t)v);
+}
+template <typename P> __device__ __forceinline__ P *pc_uniform_ptr(P *p)
+{
+    return (P *)pc_uniform64((uint64_t)p);
+}
+
 // 32-bit wavefront sum and inclusive scan with DPP lane moves (gfx9 row
 // operations), no LDS traffic.  Every lane must be active.
 #define PC_DPP(v, ctrl, rm) ((uint32_t)__builtin_amdgcn_update_dpp(0, (int)(v), ctrl, rm, 0xF, false))

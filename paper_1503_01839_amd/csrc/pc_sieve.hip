@@ -84,6 +84,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     // (GATH is not PC_CAND: a column not yet gathered keeps its PC_CAND bit)
     constexpr uint32_t GATH = 0x40000000u;
     static_assert(GCAP < 2048 && LIGHT < 2048 && KMAX <= 128, "gathered-column fields");
+    static_assert(GCAP >= 64 * NWV, "64 slots of gbuf per wave in a heavy column");
 
     // Word w of the segment lives at bm[w + w/16]: the 16 words of a counting
     // block are contiguous and consecutive blocks start 17 words apart, so the
@@ -126,7 +127,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     do {         \
     } while (0)
 #endif
-    const pc_tile tile = A.tiles[blockIdx.x];
+    pc_tile tile = A.tiles[blockIdx.x];
+    tile.seg = pc_uniform(tile.seg);
+    tile.col_lo = pc_uniform(tile.col_lo);
+    tile.col_hi = pc_uniform(tile.col_hi);
+    tile.q = pc_uniform(tile.q);
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
     if (tile.col_lo >= tile.col_hi) { // a split that owns no column
@@ -141,6 +146,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     const uint64_t hi = lo + (2ull << LOG2_S);
     const uint64_t row = seg - A.seg0;
     const pc_query &Q = A.Qs[tile.q];
+    const uint32_t qc = pc_uniform(Q.c);
+    const uint64_t *const Xb1 = pc_uniform_ptr(Q.Xb) + qc + 1; // X_b of column j of chunk cb: Xb1[cb + j]
     const pc_tables &TB = A.T;
     const uint64_t rhi = pc_recip(hi);
     const uint64_t rlo = lo ? pc_recip(lo) : 0;
@@ -243,8 +250,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         return true;
     };
     // q = bits of the segment below u = floor(X_b / m), u in [lo, hi)
-    auto leaf_q = [&](uint32_t cb, uint32_t j, uint64_t m, bool *ok) -> uint32_t {
-        const uint64_t u = pc_div_small_q(Q.Xb[Q.c + 1 + cb + j], m);
+    auto leaf_q = [&](uint64_t X, uint64_t m, bool *ok) -> uint32_t {
+        const uint64_t u = pc_div_small_q(X, m);
         *ok = u >= lo && u < hi;
         if (!*ok) // cannot happen if the m range is right
             atomicOr(A.err, 2);
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         // --- one lane per column: first multiple, leaf range ---
         bool leafy = false, heavy = false, large = false;
         if (tid < jend) {
-            const uint32_t j = tid, col = cb + j, b = Q.c + 1 + col;
+            const uint32_t j = tid, col = cb + j, b = qc + 1 + col;
             const uint64_t p = TB.primes[b];
             const uint64_t rp = TB.recip[b];
             c_p[j] = (uint32_t)p;
@@ -469,7 +476,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 uint32_t e = 0;
                 if (leaf_filter(a, s - (pa >> 10), &m, &w)) {
                     bool ok;
-                    const uint32_t q = leaf_q(cb, a, m, &ok);
+                    const uint32_t q = leaf_q(Xb1[cb + a], m, &ok);
                     if (ok) {
                         const uint32_t r = q >> RSL;
                         e = (kk << 22) | (q << 2) | (w < 0 ? 2u : 0u) | 1u;
@@ -527,19 +534,23 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             }
         };
         // Many leaves: the whole workgroup answers them against pre[].  Prime
-        // items are all leaves; candidates are first filtered into gbuf, so
-        // the divisions and counts run on full wavefronts.
+        // items are all leaves (each thread loads HU of them before it divides);
+        // each wave filters its own candidates, HU * 64 loads at a time, and
+        // packs the survivors into its 64 slots of gbuf, so the divisions and
+        // counts run on full wavefronts without workgroup barriers.
         auto heavy_col = [&](uint32_t j) {
+            constexpr uint32_t HU = 4;
             PC_PH(4);
             __syncthreads(); // every wave has crossed the columns before j
             settle();
             build_pre();     // (its barriers also end settle's reads of gbuf)
             const uint32_t lc = c_lc[j], n = lc & ~PC_CAND, ls = c_ls[j];
+            const uint64_t X = pc_uniform64(Xb1[cb + j]);
             int32_t wsum = 0;
             int64_t lsum = 0;
             auto one = [&](uint64_t m, int32_t w) {
                 bool ok;
-                const uint32_t q = leaf_q(cb, j, m, &ok);
+                const uint32_t q = leaf_q(X, m, &ok);
                 if (ok) {
                     lsum += (int64_t)w * (int64_t)count_pre(q);
                     wsum += w;
@@ -547,39 +558,61 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 }
             };
             if (!(lc & PC_CAND)) {
-                for (uint32_t it = tid; it < n; it += T)
-                    one(TB.primes[ls + it], 1);
-            } else {
-                for (uint32_t base = 0; base < n; base += GCAP) {
-                    if (tid == 0)
-                        s_hn = 0;
-                    __syncthreads();
-                    const uint32_t nb = min(GCAP, n - base);
-                    for (uint32_t t0 = 0; t0 < nb; t0 += T) {
-                        const uint32_t it = t0 + tid;
-                        bool keep = false;
-                        int32_t w = 0;
-                        if (it < nb) {
-                            uint64_t m;
-                            keep = leaf_filter(j, base + it, &m, &w);
-                        }
-                        const uint64_t bal = __ballot(keep);
-                        uint32_t at = 0;
-                        if (lane == 0 && bal)
-                            at = atomicAdd(&s_hn, (uint32_t)__builtin_popcountll(bal));
-                        at = (uint32_t)__shfl((int)at, 0, 64) +
-                             (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1));
-                        if (keep)
-                            gbuf[at] = it | (w < 0 ? 0x80000000u : 0u);
-                    }
-                    __syncthreads();
-                    const uint32_t nk = s_hn;
-                    for (uint32_t s = tid; s < nk; s += T) {
-                        const uint32_t e = gbuf[s];
-                        one(ls + base + (e & 0x7FFFFFFFu), (e >> 31) ? -1 : 1);
-                    }
-                    __syncthreads(); // gbuf and s_hn are reused
+                for (uint32_t it0 = tid; it0 < n; it0 += HU * T) {
+                    uint32_t mm[HU];
+#pragma unroll
+                    for (uint32_t u = 0; u < HU; u++)
+                        mm[u] = it0 + u * T < n ? TB.primes[ls + it0 + u * T] : 0u;
+#pragma unroll
+                    for (uint32_t u = 0; u < HU; u++)
+                        if (it0 + u * T < n)
+                            one(mm[u], 1);
                 }
+            } else {
+                const uint32_t p = c_p[j];
+                uint32_t *const slot = gbuf + wv * 64; // this wave's slots
+                uint32_t held = 0;                     // filled slots (uniform)
+                // slot entry: candidate index | (mu(m) > 0) << 31
+                auto drain = [&]() {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (lane < held) {
+                        const uint32_t e = slot[lane];
+                        one(ls + (e & 0x7FFFFFFFu), (e >> 31) ? -1 : 1);
+                    }
+                    held = 0;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                };
+                // the loop bound is uniform: drain() needs every lane of the wave
+                for (uint32_t base = wv * 64 * HU; base < n; base += HU * T) {
+                    const uint32_t it0 = base + lane;
+                    int32_t v[HU];
+#pragma unroll
+                    for (uint32_t u = 0; u < HU; u++)
+                        v[u] = it0 + u * 64 < n ? TB.mulpf[ls + it0 + u * 64] : 0;
+#pragma unroll
+                    for (uint32_t u = 0; u < HU; u++) {
+                        const uint32_t it = it0 + u * 64;
+                        n_cand += it < n ? 1u : 0u;
+                        const uint32_t av = v[u] < 0 ? (uint32_t)(-v[u]) : (uint32_t)v[u];
+                        const bool keep = av > p; // squarefree (v != 0), lpf(m) > p_b
+                        const uint64_t bal = __ballot(keep);
+                        const uint32_t k = (uint32_t)__builtin_popcountll(bal);
+                        if (held + k > 64)
+                            drain();
+                        if (keep)
+                            slot[held + (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1))] =
+                                it | (v[u] > 0 ? 0x80000000u : 0u);
+                        held += k;
+                        if (held == 64)
+                            drain();
+                    }
+                }
+                if (held)
+                    drain();
             }
             acc_local += lsum;
             const uint32_t ws = pc_wave_sum_u32((uint32_t)wsum);
