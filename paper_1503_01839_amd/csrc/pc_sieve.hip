@@ -52,7 +52,7 @@ template <int LOG2_S, int T, int CH> constexpr int pc_sieve_waves_per_simd()
     constexpr long NWV = T / 64;
     constexpr long KMAX = 64; // gathered columns per round (g_rc, g_rm)
     constexpr long lds = 4 * (NWP + 16) + 4 * (NBLK + 1) + 4 * pc_sieve_gcap<LOG2_S, T, CH>() +
-                         2 * KMAX * NWV + 4 * KMAX + 24 * CH + 16 * (CH / 64) + 16 + 8 * NWV +
+                         2 * KMAX * NWV + 8 * KMAX + 24 * CH + 16 * (CH / 64) + 4 + 8 * NWV +
                          16 * NWV;
     constexpr long wg = 163840 / lds;
     constexpr long waves = wg * NWV < 32 ? wg * NWV : 32;
@@ -80,29 +80,26 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     constexpr uint32_t LIGHT = GCAP / 2; // more leaf items: the column is answered workgroup-wide
     constexpr uint32_t GAPB = 8;         // leafless large-prime columns worth one batched crossing
     constexpr uint32_t KMAX = 64;         // columns per gather round (as in pc_sieve_waves_per_simd)
-    // c_lc of a gathered column: GATH | ordinal k << 22 | slot offset << 11 | count
-    // (GATH is not PC_CAND: a column not yet gathered keeps its PC_CAND bit)
-    constexpr uint32_t GATH = 0x40000000u;
-    static_assert(GCAP < 2048 && LIGHT < 2048 && KMAX <= 128, "gathered-column fields");
+    static_assert(GCAP < 2048 && LIGHT < 2048, "gathered-column fields");
     static_assert(GCAP >= 64 * NWV, "64 slots of gbuf per wave in a heavy column");
 
     // Word w of the segment lives at bm[w + w/16]: the 16 words of a counting
     // block are contiguous and consecutive blocks start 17 words apart, so the
     // threads of a wavefront walking their own blocks hit distinct banks.
     __shared__ uint32_t bm[NWP + 16];  // 16 spare words: a query at q = S reads past the end
-    __shared__ uint32_t pre[NBLK + 1]; // prefix of the block counts; in a gather, slot offsets
+    __shared__ uint32_t pre[NBLK + 1]; // prefix of the block counts; or a gather round's table
     __shared__ uint32_t gbuf[GCAP];    // gathered leaves: k << 22 | q << 2 | (mu(m) > 0) << 1 | 1
     __shared__ uint16_t g_rc[KMAX * NWV]; // each wave's region count at gathered column k
-    __shared__ uint32_t g_rm[KMAX];       // regions that hold a leaf of gathered column k
+    __shared__ uint32_t g_rm[2 * KMAX];   // regions that hold a leaf of gathered column k (2 rounds)
     __shared__ uint32_t c_p[CH];       // p_b
     __shared__ uint32_t c_i0[CH];      // bit of the first multiple in the segment, S if none
     __shared__ uint32_t c_ls[CH];      // first leaf item (m, or index of the prime m)
-    __shared__ uint32_t c_lc[CH];      // leaf items; PC_CAND: items are candidate m; or GATH
+    __shared__ uint32_t c_lc[CH];      // leaf items; PC_CAND: items are candidate m
     __shared__ uint32_t c_new[CH];     // integers first removed by p_b in this segment
     __shared__ int32_t c_w[CH];        // sum of -mu(m) over the leaves of the column
     __shared__ uint64_t c_leafy[CH / 64];
     __shared__ uint64_t c_heavy[CH / 64];
-    __shared__ uint32_t s_first_large, s_gend, s_used, s_hn;
+    __shared__ uint32_t s_first_large;
     __shared__ uint32_t reg_dec[NWV];  // integers a batched crossing removed, per region
     __shared__ uint32_t scr32[NWV];
     __shared__ pc_s128 scr128[NWV];
@@ -169,6 +166,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     }
     if (tid < NWV)
         reg_dec[tid] = 0;
+    if (tid < 2 * KMAX)
+        g_rm[tid] = 0;
     __syncthreads();
 
     // unsieved integers in each of the blocks thread tid counts
@@ -232,6 +231,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     int64_t acc_local = 0;             // sum of -mu(m) * in-segment count (hard leaves)
     int64_t acc_p2 = 0;                // sum of in-segment counts (P2 terms)
     pc_s128 acc_carry = 0;             // PC_MODE_LEAVES: carry * w
+    uint32_t g_par = 0;                // g_rm half of the current gather round
 
     // Leaf item it of column j: *m and *w = -mu(m), false if the candidate m
     // is not squarefree with lpf(m) > p_b.
@@ -398,12 +398,16 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             }
         };
 
-        // Gather rounds.  The leaves of up to KMAX light leafy columns (whole
-        // columns, in order, stopping at the next heavy column) go to gbuf,
-        // one candidate per slot.  Each wave answers only the leaves whose u
-        // lies in its own region, and records its region count per column in
-        // g_rc; when the round is over (every wave past its columns), settle()
-        // adds, for every leaf, the counts of the regions below its own.
+        // Gather rounds.  The leaves of the light leafy columns of a window
+        // (whole columns of one cached group of 64, in order, stopping at the
+        // next heavy column or when GCAP slots are full) go to gbuf, one
+        // candidate per slot; column cg0 + k is the round's column k.  Each
+        // wave answers only the leaves whose u lies in its own region, and
+        // records its region count per column in g_rc; when the round is over
+        // (every wave past its columns), settle() adds, for every leaf, the
+        // counts of the regions below its own.  Every wave computes the
+        // round's slot offsets itself, and thread t only ever reads and writes
+        // slots t, t + T, ..., so a round needs two barriers.
         uint32_t g_used = 0; // slots of the open round (uniform); 0 = none open
         auto settle = [&]() { // after a barrier that every wave reached past the round
             for (uint32_t s = tid; s < g_used; s += T) {
@@ -418,12 +422,15 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             }
             g_used = 0;
         };
-        // returns the end of the gathered window: every light leafy column of
-        // [j0, that end) is gathered
+        // j0 lies in the cached group and we <= cg0 + 64; returns the end of
+        // the round's window: every light leafy column of [j0, that end) is
+        // gathered, and pre[k] = slot offset << 11 | items of column cg0 + k
+        // (0 for columns outside the round or without leaves).
         auto gather = [&](uint32_t j0, uint32_t we) -> uint32_t {
             PC_PH(4);
             __syncthreads(); // every wave is past the open round's columns
             settle();
+            g_par ^= 1;
             // the next heavy column at or after j0 ends the round
             uint32_t hvn = jend;
             {
@@ -435,76 +442,66 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                     hvn = min(jend, wd * 64 + (uint32_t)__builtin_ctzll(msk));
             }
             hvn = min(hvn, we);
-            const uint32_t jt = tid;
+            const uint32_t col = cg0 + lane;
             uint32_t v = 0;
-            if (jt >= j0 && jt < hvn) {
-                const uint32_t lc = c_lc[jt];
-                if (lc != 0 && !(lc & GATH))
-                    v = lc & ~PC_CAND; // light: heavy columns lie at or past hvn
-            }
-            if (tid == 0) {
-                s_gend = jend;
-                s_used = 0;
-            }
+            if (col >= j0 && col < hvn)
+                v = c_lc[col] & ~PC_CAND; // light: heavy columns lie at or past hvn
+            const uint32_t inc = pc_wave_incl_scan_u32(v), off = inc - v;
+            const uint64_t over = __ballot(v != 0 && inc > GCAP);
+            const uint32_t kend = over ? (uint32_t)__builtin_ctzll(over) : 64u;
+            const uint32_t used = kend ? (uint32_t)__builtin_amdgcn_readlane((int)off, (int)(kend - 1)) +
+                                             (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(kend - 1))
+                                       : 0u;
+            uint32_t *const rm = g_rm + g_par * KMAX;
             if (tid < KMAX)
-                g_rm[tid] = 0;
-            uint32_t tot;
-            // items (high bits) and columns (low 10 bits) before this column
-            const uint32_t ex = pc_block_excl_scan<T>((v << 10) | (v ? 1u : 0u), scr32, &tot);
-            const uint32_t off = ex >> 10, k = ex & 1023u;
-            const bool fit = off + v <= GCAP && k < KMAX;
-            if (jt >= j0 && jt < jend)
-                pre[jt] = fit ? (off << 10) | k : GCAP << 10; // slot offset, ordinal
-            if (v && !fit)
-                atomicMin(&s_gend, jt);
-            if (v && fit)
-                atomicMax(&s_used, off + v);
-            __syncthreads();
-            const uint32_t used = s_used, gend = s_gend;
-            for (uint32_t s = tid; s < used; s += T) {
-                uint32_t a = j0, z = gend; // the column: largest in [j0, gend) starting at or below s
-                while (z - a > 1) {
-                    const uint32_t mid = (a + z) >> 1;
-                    if ((pre[mid] >> 10) <= s)
-                        a = mid;
-                    else
-                        z = mid;
-                }
-                const uint32_t pa = pre[a], kk = pa & 1023u;
-                uint64_t m;
-                int32_t w;
-                uint32_t e = 0;
-                if (leaf_filter(a, s - (pa >> 10), &m, &w)) {
-                    bool ok;
-                    const uint32_t q = leaf_q(Xb1[cb + a], m, &ok);
-                    if (ok) {
-                        const uint32_t r = q >> RSL;
-                        e = (kk << 22) | (q << 2) | (w < 0 ? 2u : 0u) | 1u;
-                        atomicAdd(&c_w[a], w);
-                        if (r < NWV)
-                            atomicOr(&g_rm[kk], 1u << r);
-                        nleaf++;
+                g_rm[(g_par ^ 1) * KMAX + tid] = 0; // the next round's masks
+            for (uint32_t s0 = 0; s0 < used; s0 += T) {
+                // the column of slot s: the last lane whose offset is <= s
+                const uint32_t s = s0 + tid;
+                uint32_t a = 0, oa = 0;
+#pragma unroll
+                for (uint32_t h = 32; h; h >>= 1) {
+                    const uint32_t o = (uint32_t)__shfl((int)off, (int)(a + h), 64);
+                    if (o <= s) {
+                        a += h;
+                        oa = o;
                     }
                 }
-                gbuf[s] = e;
+                if (s < used) {
+                    const uint32_t aj = cg0 + a;
+                    uint64_t m;
+                    int32_t w;
+                    uint32_t e = 0;
+                    if (leaf_filter(aj, s - oa, &m, &w)) {
+                        bool ok;
+                        const uint32_t q = leaf_q(Xb1[cb + aj], m, &ok);
+                        if (ok) {
+                            const uint32_t r = q >> RSL;
+                            e = (a << 22) | (q << 2) | (w < 0 ? 2u : 0u) | 1u;
+                            atomicAdd(&c_w[aj], w);
+                            if (r < NWV)
+                                atomicOr(&rm[a], 1u << r);
+                            nleaf++;
+                        }
+                    }
+                    gbuf[s] = e;
+                }
             }
-            __syncthreads(); // every reader of c_lc, c_ls and pre is done
-            if (v && fit) {
-                c_lc[jt] = GATH | (k << 22) | (off << 11) | v;
-                n_leafy++;
-                if (jt < first_large)
-                    n_leafy_small++;
+            if (wv == 0) { // the round's table
+                const bool g = lane < kend && v != 0;
+                pre[lane] = g ? (off << 11) | v : 0u;
+                n_leafy += g ? 1u : 0u;
+                n_leafy_small += g && col < first_large ? 1u : 0u;
             }
             g_used = used;
             __syncthreads();
             PC_PH(2);
-            return min(hvn, gend);
+            return over ? min(hvn, cg0 + kend) : hvn;
         };
         // this wave's part of the leaves of gathered column j that lie in its
         // region: a prefix of the region for each
-        auto answer = [&](uint32_t j) {
-            const uint32_t g = c_lc[j];
-            const uint32_t s0 = (g >> 11) & 0x7FFu, s1 = s0 + (g & 0x7FFu);
+        auto answer = [&](uint32_t g) {
+            const uint32_t s0 = g >> 11, s1 = s0 + (g & 0x7FFu);
             bool have = false;
             uint32_t pe = 0, pc0 = 0; // lane prefix of the region's block counts; first block
             for (uint32_t s = s0; s < s1; s += 64) {
@@ -635,12 +632,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             const uint32_t rc0 = rc;
             const uint32_t col = cg0 + lane;
             const bool inw = col >= j && col < we;
-            uint32_t g = 0;
-            if (inw)
-                g = c_lc[col];
-            const bool gath = (g & GATH) != 0;
-            const uint32_t ord = (g >> 22) & 0x7Fu;
-            const uint32_t rm = gath ? g_rm[ord] : 0u;
+            const uint32_t g = inw ? pre[lane] : 0u; // the round's table
+            const bool gath = g != 0;
+            const uint32_t rm = gath ? g_rm[g_par * KMAX + lane] : 0u;
             const uint64_t own = __ballot(gath && ((rm >> wv) & 1u));
             const uint64_t crs = __ballot(inw && v_nm != 0);
             uint64_t todo = own | crs;
@@ -648,14 +642,14 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 const int32_t k = (int32_t)__builtin_ctzll(todo);
                 todo &= todo - 1;
                 if ((own >> k) & 1)
-                    answer(cg0 + (uint32_t)k);
+                    answer((uint32_t)__builtin_amdgcn_readlane((int)g, k));
                 if ((crs >> k) & 1)
                     cross_k(k, (uint32_t)__builtin_amdgcn_readlane((int)v_nm, k));
             }
             const uint32_t rem = inw ? v_rem : 0u;
             const uint32_t before = pc_wave_incl_scan_u32(rem) - rem;
             if (gath)
-                g_rc[ord * NWV + wv] = (uint16_t)(rc0 - before);
+                g_rc[lane * NWV + wv] = (uint16_t)(rc0 - before);
         };
         // Leafless columns [j, jb) of primes with p^3 >= hi, one lane per
         // prime: an integer n = p k unsieved at the start of the run is first
