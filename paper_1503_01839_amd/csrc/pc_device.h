@@ -51,6 +51,54 @@ PC_HD uint64_t pc_div_small_q(uint64_t n, uint32_t d)
     return q;
 }
 
+// Quotients on the leaf paths, where the divisor changes from lane to lane
+// and the dividend is shared (the caller converts it to fp64 once).  1/d is
+// the hardware fp64 reciprocal estimate refined by two Newton steps; each
+// step squares the relative error, so any estimate better than 2^-20 ends
+// within a few units of 2^-52.  The product with fl(n) is then within
+// n/d * 2^-49 of n/d, under 1/4 for n/d < 2^47, and the truncated estimate
+// is floor(n/d) or one off, which one exact remainder test corrects.
+__device__ __forceinline__ double pc_rcp_f64(uint32_t d)
+{
+    const double dd = (double)d;
+    double r = __builtin_amdgcn_rcp(dd);
+    r = __builtin_fma(__builtin_fma(-dd, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-dd, r, 1.0), r, r);
+    return r;
+}
+
+// floor(n / d) for 1 <= d < 2^32 when the quotient is known to be below
+// 2^32 - 1; nd = (double)n.
+__device__ __forceinline__ uint32_t pc_quot32(uint64_t n, double nd, uint32_t d)
+{
+    uint32_t q = (uint32_t)(nd * pc_rcp_f64(d));
+    const int64_t rem = (int64_t)(n - (uint64_t)q * d);
+    if (rem < 0)
+        q--;
+    else if (rem >= (int64_t)d)
+        q++;
+    return q;
+}
+
+// floor(n / d) - base for 1 <= d < 2^32, base < 2^47, n/d < 2^47:
+// returns false if the quotient lies outside [base, base + span), span <
+// 2^30, else true with *off = the quotient - base.  nd = (double)n.
+__device__ __forceinline__ bool pc_quot_in(uint64_t n, double nd, uint32_t d, uint64_t base,
+                                           uint32_t span, uint32_t *off)
+{
+    const double t = nd * pc_rcp_f64(d) - (double)base;
+    if (!(t > -2.0 && t < (double)span + 2.0))
+        return false;
+    int32_t q = (int32_t)t;
+    const int64_t rem = (int64_t)(n - (base + (uint64_t)(int64_t)q) * d);
+    if (rem < 0)
+        q--;
+    else if (rem >= (int64_t)d)
+        q++;
+    *off = (uint32_t)q;
+    return q >= 0 && (uint32_t)q < span;
+}
+
 // Exact floor(n / d) for any n < 2^64, 1 <= d < 2^32: fp64 estimate, one
 // exact refinement of the remainder, then a final one-step correction.
 PC_HD uint64_t pc_div_any(uint64_t n, uint32_t d)

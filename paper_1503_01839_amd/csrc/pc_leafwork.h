@@ -117,8 +117,8 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
 // calls) takes tiles lb, lb + nlb, ... of NT * PER consecutive items; one
 // search finds the b of a tile's first item, then thread t takes items
 // i0 + t, i0 + t + NT, ... so neighbouring lanes read neighbouring primes m
-// and neighbouring pi(u) entries.  u = x/(m p_b) <= y < 2^50, so the fp64
-// estimate quotient is exact after its remainder check.
+// and neighbouring pi(u) entries.  u = x/(m p_b) <= y < 2^32 - 1, so the
+// reciprocal estimate quotient is exact after its remainder check.
 template <int NT, int PER>
 __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query &Q, uint64_t lb,
                                               uint64_t nlb, uint32_t *s_b0, int64_t *acc,
@@ -142,6 +142,7 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
         __syncthreads();
         uint32_t b = *s_b0;
         uint64_t off = e_off[b], cn = e_count[b], st = e_start[b], X = Q.Xb[b];
+        double Xd = (double)X;
         uint32_t p = T.primes[b];
         const uint64_t iend = i0 + TILE < E ? i0 + TILE : E;
         for (uint64_t i = i0 + threadIdx.x; i < iend; i += NT) {
@@ -151,6 +152,7 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
                 cn = e_count[b];
                 st = e_start[b];
                 X = Q.Xb[b];
+                Xd = (double)X;
                 p = T.primes[b];
             }
             const uint64_t o = i - off;
@@ -167,7 +169,7 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
                 m = T.primes[st + o];
                 w = 1;
             }
-            const uint64_t u = pc_div_small_q(X, m);
+            const uint32_t u = pc_quot32(X, Xd, m); // u <= y < 2^32 - 1
             *acc += (int64_t)w * ((int64_t)pc_pi_lookup(T.pitab, u) - (int64_t)b + 2);
             (*nleaf)++;
         }

@@ -781,15 +781,18 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 k2 = pc_pi_lookup(TB.pitab, ph);
             }
         }
-        if (MODE != PC_MODE_COUNT)
+        if (MODE != PC_MODE_COUNT) {
+            const uint64_t x = Q.x;
+            const double xd = (double)x;
             for (uint32_t k = k1 + tid; k <= k2; k += T) {
-                const uint64_t v = pc_div_small_q(Q.x, TB.primes[k]);
-                if (v < lo || v >= hi) {
+                uint32_t off; // x/p_k - lo
+                if (!pc_quot_in(x, xd, TB.primes[k], lo, 2u << LOG2_S, &off)) {
                     atomicOr(A.err, 4);
                     continue;
                 }
-                acc_p2 += count_pre((uint32_t)((v - lo + 1) >> 1));
+                acc_p2 += count_pre((off + 1) >> 1);
             }
+        }
         if (tid == 0) {
             const uint64_t idx = row * ncol + Q.nb;
             const uint32_t np = k2 >= k1 ? k2 - k1 + 1 : 0;
@@ -847,10 +850,17 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
 // carry[s][col] = carry_in[col] + sum_{s' < s} cnt[s'][col].  Workgroups take
 // tickets in order; a workgroup owns rows_per_chunk rows of 256 columns,
 // publishes its column sums, and looks back through earlier chunks until one
-// has published an inclusive prefix (decoupled look-back).  PC_MODE_TALLY
-// forms sum w * carry; PC_MODE_COUNT writes the carries out for the leaf pass.
+// has published an inclusive prefix (decoupled look-back).
+//
+// PC_MODE_TALLY needs only sum w * carry, which splits over a chunk as
+//   sum_r w_r (P + l_r) = P * sum_r w_r + sum_r w_r l_r,
+// P = the carry at the chunk's first row (from the look-back), l_r = the
+// counts of the chunk's rows above r: one pass over cnt and wgt before the
+// look-back, each read once, SCAN_U rows of loads in flight per thread.
+// PC_MODE_COUNT writes every carry out for the leaf pass (a second pass).
 // ---------------------------------------------------------------------------
 #define SCAN_T 256
+#define SCAN_U 8
 #define LB_A (1ull << 62)
 #define LB_P (2ull << 62)
 #define LB_V ((1ull << 62) - 1)
@@ -870,9 +880,42 @@ template <int MODE> __global__ __launch_bounds__(SCAN_T) void k_scan(pc_scan_arg
     const uint64_t r1 = min(r0 + A.rows_per_chunk, A.nrows);
     const uint64_t ncol = A.ncol;
     uint64_t agg = 0, pre = 0;
+    int64_t wsum = 0;   // PC_MODE_TALLY: sum of w over the chunk
+    pc_s128 wl = 0;     //                sum of w * (counts of the chunk above the row)
     if (act) {
-        for (uint64_t r = r0; r < r1; r++)
-            agg += A.cnt[r * ncol + col];
+        if (MODE == PC_MODE_TALLY) {
+            const uint32_t *cp = A.cnt + r0 * ncol + col;
+            const int32_t *wp = A.wgt + r0 * ncol + col;
+            uint64_t r = r0;
+            for (; r + SCAN_U <= r1; r += SCAN_U, cp += SCAN_U * ncol, wp += SCAN_U * ncol) {
+                uint32_t c[SCAN_U];
+                int32_t w[SCAN_U];
+#pragma unroll
+                for (uint32_t u = 0; u < SCAN_U; u++) {
+                    c[u] = cp[u * ncol];
+                    w[u] = wp[u * ncol];
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < SCAN_U; u++) {
+                    if (w[u]) {
+                        wsum += w[u];
+                        wl += (pc_s128)((int64_t)w[u] * (int64_t)agg);
+                    }
+                    agg += c[u];
+                }
+            }
+            for (; r < r1; r++, cp += ncol, wp += ncol) {
+                const int32_t w = *wp;
+                if (w) {
+                    wsum += w;
+                    wl += (pc_s128)((int64_t)w * (int64_t)agg);
+                }
+                agg += *cp;
+            }
+        } else {
+            for (uint64_t r = r0; r < r1; r++)
+                agg += A.cnt[r * ncol + col];
+        }
         uint64_t *st = A.status + (uint64_t)rc * ncol + col;
         if (rc == 0) {
             __hip_atomic_store(st, LB_P | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -903,24 +946,23 @@ template <int MODE> __global__ __launch_bounds__(SCAN_T) void k_scan(pc_scan_arg
     }
     pc_s128 dh = 0, dp = 0;
     if (act) {
-        uint64_t carry = A.carry_in[col] + pre;
-        for (uint64_t r = r0; r < r1; r++) {
-            const uint64_t idx = r * ncol + col;
-            if (MODE == PC_MODE_TALLY) {
-                const int32_t w = A.wgt[idx];
-                if (w) {
-                    if (col == A.nb)
-                        dp += (pc_s128)w * (pc_s128)carry;
-                    else
-                        dh += (pc_s128)w * (pc_s128)carry;
-                }
-            } else {
+        const uint64_t P = A.carry_in[col] + pre; // carry at the chunk's first row
+        if (MODE == PC_MODE_TALLY) {
+            const pc_s128 d = (pc_s128)wsum * (pc_s128)P + wl;
+            if (col == A.nb)
+                dp = d;
+            else
+                dh = d;
+        } else {
+            uint64_t carry = P;
+            for (uint64_t r = r0; r < r1; r++) {
+                const uint64_t idx = r * ncol + col;
                 A.carry_rows[idx] = carry;
+                carry += A.cnt[idx];
             }
-            carry += A.cnt[idx];
         }
         if (rc == A.nchunk - 1)
-            A.carry_out[col] = carry;
+            A.carry_out[col] = P + agg;
     }
     if (MODE == PC_MODE_TALLY) {
         dh = pc_block_sum128<SCAN_T>(dh, scr);
