@@ -359,18 +359,31 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         auto cross_k = [&](int32_t k, uint32_t nm) {
             const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)v_f, k);
             const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)v_p, k);
-            uint32_t removed = 0;
+            // a lane's multiples lie 64 p bits apart, a multiple of 32: they
+            // all sit at the same bit of their words
             uint32_t bit = f + lane * p;
-            for (uint32_t t0 = 0; t0 < nm; t0 += 64, bit += 64 * p) {
-                bool hit = false;
-                if (t0 + lane < nm) {
-                    const uint32_t mask = 1u << (bit & 31);
-                    const uint32_t old = __hip_atomic_fetch_and(
-                        &BW(bit >> 5), ~mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    hit = (old & mask) != 0;
+            const uint32_t sh = bit & 31, keep = ~(1u << sh), step = 64 * p;
+            auto clear = [&](uint32_t b) -> uint32_t {
+                const uint32_t old = __hip_atomic_fetch_and(&BW(b >> 5), keep, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+                return (old >> sh) & 1u;
+            };
+            uint32_t removed = 0;
+            const uint32_t full = nm >> 6; // rounds in which every lane has a multiple
+            if (full) {
+                uint32_t hits = 0, t = 0;
+                for (; t + 2 <= full; t += 2, bit += 2 * step) // two clears in flight
+                    hits += clear(bit) + clear(bit + step);
+                if (t < full) {
+                    hits += clear(bit);
+                    bit += step;
                 }
-                removed += (uint32_t)__builtin_popcountll(__ballot(hit));
+                removed = pc_wave_sum_u32(hits);
             }
+            bool hit = false;
+            if (lane < (nm & 63))
+                hit = clear(bit) != 0;
+            removed += (uint32_t)__builtin_popcountll(__ballot(hit));
             rc -= removed;
             if (lane == (uint32_t)k)
                 v_rem = removed;
