@@ -68,16 +68,14 @@ __device__ __forceinline__ double pc_rcp_f64(uint32_t d)
 }
 
 // floor(n / d) for 1 <= d < 2^32 when the quotient is known to be below
-// 2^32 - 1; nd = (double)n.
+// 2^32 - 1; nd = (double)n.  The estimate is raised by 2^-10, more than its
+// error (2^-17 here), so the truncation is floor(n/d) or one above it, and
+// only the sign of the remainder needs testing.
 __device__ __forceinline__ uint32_t pc_quot32(uint64_t n, double nd, uint32_t d)
 {
-    uint32_t q = (uint32_t)(nd * pc_rcp_f64(d));
+    const uint32_t q = (uint32_t)__builtin_fma(nd, pc_rcp_f64(d), 0x1p-10);
     const int64_t rem = (int64_t)(n - (uint64_t)q * d);
-    if (rem < 0)
-        q--;
-    else if (rem >= (int64_t)d)
-        q++;
-    return q;
+    return q - (rem < 0 ? 1u : 0u);
 }
 
 // floor(n / d) - base for 1 <= d < 2^32, base < 2^47, n/d < 2^47:
@@ -153,4 +151,12 @@ PC_HD uint32_t pc_pi_lookup(const uint2 *tab, uint64_t n)
     uint2 e = tab[i >> 5];
     uint32_t sh = 31u - (uint32_t)(i & 31);
     return 1u + e.y + (uint32_t)__builtin_popcount((e.x << sh)); // bits 0..(i&31)
+}
+
+// The same for 2 <= n < 2^32, in 32-bit arithmetic.
+PC_HD uint32_t pc_pi_lookup32(const uint2 *tab, uint32_t n)
+{
+    const uint32_t i = (n - 1) >> 1;
+    const uint2 e = tab[i >> 5];
+    return 1u + e.y + (uint32_t)__builtin_popcount(e.x << (31u - (i & 31)));
 }

@@ -118,7 +118,10 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
 // search finds the b of a tile's first item, then thread t takes items
 // i0 + t, i0 + t + NT, ... so neighbouring lanes read neighbouring primes m
 // and neighbouring pi(u) entries.  u = x/(m p_b) <= y < 2^32 - 1, so the
-// reciprocal estimate quotient is exact after its remainder check.
+// reciprocal estimate quotient is exact after its remainder check.  The
+// candidate-m items (p_b^2 <= y) all precede the prime items (p_b^2 > y), so a
+// tile that starts in a prime range has only prime items: every one is a
+// leaf with -mu(m) = 1, and the loop needs no filter.
 template <int NT, int PER>
 __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query &Q, uint64_t lb,
                                               uint64_t nlb, uint32_t *s_b0, int64_t *acc,
@@ -141,37 +144,65 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
         }
         __syncthreads();
         uint32_t b = *s_b0;
-        uint64_t off = e_off[b], cn = e_count[b], st = e_start[b], X = Q.Xb[b];
-        double Xd = (double)X;
-        uint32_t p = T.primes[b];
-        const uint64_t iend = i0 + TILE < E ? i0 + TILE : E;
-        for (uint64_t i = i0 + threadIdx.x; i < iend; i += NT) {
-            while (i >= off + (cn & ~PC_MODEBIT)) {
-                b++;
-                off = e_off[b];
-                cn = e_count[b];
-                st = e_start[b];
-                X = Q.Xb[b];
-                Xd = (double)X;
-                p = T.primes[b];
+        const uint32_t n = (uint32_t)(i0 + TILE < E ? TILE : E - i0); // items of the tile
+        uint64_t cn = e_count[b];
+        if (!(cn & PC_MODEBIT)) {
+            // prime items only; item t of the tile is item t - rs of its b
+            int64_t rs = (int64_t)(e_off[b] - i0), re = rs + (int64_t)cn;
+            uint32_t st = (uint32_t)e_start[b], bm2 = b - 2;
+            uint64_t X = Q.Xb[b];
+            double Xd = (double)X;
+            int64_t a = 0;
+            for (uint32_t t = threadIdx.x; t < n; t += NT) {
+                while ((int64_t)t >= re) {
+                    b++;
+                    rs = re;
+                    re = rs + (int64_t)e_count[b];
+                    st = (uint32_t)e_start[b];
+                    bm2 = b - 2;
+                    X = Q.Xb[b];
+                    Xd = (double)X;
+                }
+                const uint32_t m = T.primes[st + (uint32_t)((int64_t)t - rs)];
+                const uint32_t u = pc_quot32(X, Xd, m); // p_b <= u <= y
+                a += pc_pi_lookup32(T.pitab, u) - bm2;  // phi(u, b-1) = pi(u) - b + 2 >= 1
             }
-            const uint64_t o = i - off;
-            uint32_t m;
-            int32_t w;
-            if (cn & PC_MODEBIT) {
-                m = (uint32_t)(st + o);
-                const int32_t v = T.mulpf[m];
-                const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
-                if (l <= p) // mu(m) = 0 or lpf(m) <= p_b
-                    continue;
-                w = v > 0 ? -1 : 1;
-            } else {
-                m = T.primes[st + o];
-                w = 1;
+            *acc += a;
+            if (threadIdx.x == 0)
+                *nleaf += n;
+        } else {
+            uint64_t off = e_off[b], st = e_start[b], X = Q.Xb[b];
+            double Xd = (double)X;
+            uint32_t p = T.primes[b];
+            const uint64_t iend = i0 + n;
+            for (uint64_t i = i0 + threadIdx.x; i < iend; i += NT) {
+                while (i >= off + (cn & ~PC_MODEBIT)) {
+                    b++;
+                    off = e_off[b];
+                    cn = e_count[b];
+                    st = e_start[b];
+                    X = Q.Xb[b];
+                    Xd = (double)X;
+                    p = T.primes[b];
+                }
+                const uint64_t o = i - off;
+                uint32_t m;
+                int32_t w;
+                if (cn & PC_MODEBIT) {
+                    m = (uint32_t)(st + o);
+                    const int32_t v = T.mulpf[m];
+                    const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
+                    if (l <= p) // mu(m) = 0 or lpf(m) <= p_b
+                        continue;
+                    w = v > 0 ? -1 : 1;
+                } else {
+                    m = T.primes[st + o];
+                    w = 1;
+                }
+                const uint32_t u = pc_quot32(X, Xd, m); // u <= y < 2^32 - 1
+                *acc += (int64_t)w * ((int64_t)pc_pi_lookup32(T.pitab, u) - (int64_t)b + 2);
+                (*nleaf)++;
             }
-            const uint32_t u = pc_quot32(X, Xd, m); // u <= y < 2^32 - 1
-            *acc += (int64_t)w * ((int64_t)pc_pi_lookup(T.pitab, u) - (int64_t)b + 2);
-            (*nleaf)++;
         }
         __syncthreads();
     }
