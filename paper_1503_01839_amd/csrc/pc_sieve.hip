@@ -79,6 +79,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     constexpr uint32_t GCAP = pc_sieve_gcap<LOG2_S, T, CH>(); // gathered leaf items
     constexpr uint32_t LIGHT = GCAP / 2; // more leaf items: the column is answered workgroup-wide
     constexpr uint32_t GAPB = 8;         // leafless large-prime columns worth one batched crossing
+    constexpr uint32_t XB_P = RS / 32;   // p >= XB_P: at most 32 multiples in a wave's region
     constexpr uint32_t KMAX = 64;         // columns per gather round (as in pc_sieve_waves_per_simd)
     static_assert(GCAP < 2048 && LIGHT < 2048, "gathered-column fields");
     static_assert(GCAP >= 64 * NWV, "64 slots of gbuf per wave in a heavy column");
@@ -108,9 +109,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     uint32_t n_cand = 0, n_leafy = 0, n_leafy_small = 0;
 #if PC_PHASE_TRACE
     // 0 set-up, 1 per-column set-up, 2 gathers, 3 heavy columns, 4 wavefront
-    // columns, 5 batched crossings, 7 chunk results, 8 final column
-    uint32_t ph[9] = {};
+    // columns, 5 batched crossings, 7 chunk results, 8 final column; event
+    // counts: 0 column crossings by a wave, 1 answered columns, 2 gather rounds
+    uint32_t ph[9] = {}, ev[3] = {};
     uint64_t ph_last = t_start;
+#define PC_EV(k) (ev[k]++)
 #define PC_PH(k)                                                                        \
     do {                                                                                \
         if (A.trace) {                                                                  \
@@ -123,6 +126,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
 #define PC_PH(k) \
     do {         \
     } while (0)
+#define PC_EV(k) ((void)0)
 #endif
     pc_tile tile = A.tiles[blockIdx.x];
     tile.seg = pc_uniform(tile.seg);
@@ -357,6 +361,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         // cross column cg0 + k, which has nm > 0 multiples in this wave's
         // region, one lane per multiple
         auto cross_k = [&](int32_t k, uint32_t nm) {
+            PC_EV(0);
             const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)v_f, k);
             const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)v_p, k);
             // a lane's multiples lie 64 p bits apart, a multiple of 32: they
@@ -395,18 +400,142 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             if (nm)
                 cross_k(k, nm);
         };
+        // Large columns [ja, jb) of the cached group (every one at or past
+        // first_large, with p >= XB_P) crossed in this wave's region in one
+        // step, one lane per column.  An integer n = p k unsieved at the start
+        // is first removed by p exactly when k = 1 or k >= p (p^3 >= hi leaves
+        // n at most two prime factors, none below the first column's prime),
+        // so each lane first reads its multiples and credits those, then
+        // clears them; the order of the columns no longer matters.  Gathered
+        // leaves in slots [es0, es1) that lie in this region are answered in
+        // between: their count at the start, less the credited multiples
+        // below them of the earlier columns.
+        auto xbatch = [&](uint32_t ja, uint32_t jb, uint32_t es0, uint32_t es1) {
+            const uint32_t col = cg0 + lane;
+            const uint32_t nm = col >= ja && col < jb ? v_nm : 0u;
+            const uint32_t f = v_f, p = v_p;
+            // n = lo + 2 bit + 1 >= p^2  <=>  bit >= tb;  n = p  <=>  bit = ip
+            const uint64_t p2 = (uint64_t)p * p;
+            const uint32_t tb = p2 <= lo ? 0u : (uint32_t)min<uint64_t>(S, (p2 - lo - 1) >> 1);
+            const uint32_t ip = lo <= p ? (uint32_t)((p - lo - 1) >> 1) : S;
+            uint32_t cm = 0; // credited multiples: bit i <-> f + i p
+            for (uint32_t i = 0; __ballot(i < nm); i++)
+                if (i < nm) {
+                    const uint32_t bit = f + i * p;
+                    if (((BW(bit >> 5) >> (bit & 31)) & 1u) && (bit >= tb || bit == ip))
+                        cm |= 1u << i;
+                }
+            if (es0 < es1) {
+                bool have = false;
+                uint32_t pe = 0, pc0 = 0; // lane prefix of the region's block counts; first block
+                const float rp = __builtin_amdgcn_rcpf((float)p);
+                for (uint32_t s = es0; s < es1; s += 64) {
+                    const uint32_t e = s + lane < es1 ? gbuf[s + lane] : 0u;
+                    const uint32_t q = (e >> 2) & 0xFFFFFu;
+                    const bool in = (e & 1) && (q >> RSL) == wv;
+                    uint64_t pend = __ballot(in);
+                    if (!pend)
+                        continue;
+                    if (!have) {
+                        uint32_t cnt[BPT];
+                        const uint32_t sum = block_counts(cnt);
+                        pe = pc_wave_incl_scan_u32(sum) - sum;
+                        pc0 = cnt[0];
+                        have = true;
+                    }
+                    const uint32_t bl = in ? (q >> BL) - (R0 >> BL) : 0u;
+                    const uint32_t src = bl / BPT;
+                    uint32_t c = (uint32_t)__shfl((int)pe, (int)src, 64);
+                    if (BPT > 1) {
+                        const uint32_t c0 = (uint32_t)__shfl((int)pc0, (int)src, 64);
+                        c += (bl % BPT) ? c0 : 0u;
+                    }
+                    if (in)
+                        c += in_block(q);
+                    // less the earlier columns' credited multiples below q:
+                    // leaf by leaf (all lanes count for one leaf) or column
+                    // by column (all leaves count one column), the shorter
+                    uint64_t cols = __ballot(cm != 0);
+                    if (__builtin_popcountll(pend) <= __builtin_popcountll(cols)) {
+                        while (pend) {
+                            const int32_t l = (int32_t)__builtin_ctzll(pend);
+                            pend &= pend - 1;
+                            const uint32_t ql = (uint32_t)__builtin_amdgcn_readlane((int)q, l);
+                            const uint32_t kl = (uint32_t)__builtin_amdgcn_readlane((int)e, l) >> 22;
+                            uint32_t below = 0;
+                            if (lane < kl && cm != 0 && ql > f) {
+                                const uint32_t d = ql - f - 1; // multiples f + t p, t <= d / p
+                                uint32_t t = (uint32_t)((float)d * rp);
+                                const int32_t r = (int32_t)(d - t * p);
+                                if (r < 0)
+                                    t--;
+                                else if (r >= (int32_t)p)
+                                    t++;
+                                below = (uint32_t)__builtin_popcount(t >= 31 ? cm : cm & ((2u << t) - 1));
+                            }
+                            const uint32_t tot = pc_wave_sum_u32(below);
+                            if (lane == (uint32_t)l)
+                                c -= tot;
+                        }
+                    } else {
+                        const uint32_t ke = e >> 22;
+                        while (cols) {
+                            const int32_t k = (int32_t)__builtin_ctzll(cols);
+                            cols &= cols - 1;
+                            const uint32_t fk = (uint32_t)__builtin_amdgcn_readlane((int)f, k);
+                            const uint32_t pk = (uint32_t)__builtin_amdgcn_readlane((int)p, k);
+                            const uint32_t ck = (uint32_t)__builtin_amdgcn_readlane((int)cm, k);
+                            if (in && ke > (uint32_t)k && q > fk) {
+                                const uint32_t d = q - fk - 1;
+                                uint32_t t = (uint32_t)((float)d * __builtin_amdgcn_rcpf((float)pk));
+                                const int32_t r = (int32_t)(d - t * pk);
+                                if (r < 0)
+                                    t--;
+                                else if (r >= (int32_t)pk)
+                                    t++;
+                                c -= (uint32_t)__builtin_popcount(t >= 31 ? ck : ck & ((2u << t) - 1));
+                            }
+                        }
+                    }
+                    if (in)
+                        acc_local += (e & 2) ? -(int64_t)c : (int64_t)c;
+                }
+            }
+            for (uint32_t i = 0; __ballot(i < nm); i++)
+                if (i < nm) {
+                    const uint32_t bit = f + i * p;
+                    __hip_atomic_fetch_and(&BW(bit >> 5), ~(1u << (bit & 31)), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            const uint32_t cr = (uint32_t)__builtin_popcount(cm);
+            if (nm)
+                v_rem = cr;
+            rc -= pc_wave_sum_u32(cr);
+        };
+        // the first column of [j, je) (within the cached group) from which on
+        // xbatch applies, or je
+        auto xbatch_from = [&](uint32_t j, uint32_t je) -> uint32_t {
+            if (!BATCH)
+                return je;
+            const uint32_t col = cg0 + lane;
+            const uint64_t lg = __ballot(col >= j && col < je && col >= first_large && v_p >= XB_P);
+            return lg ? cg0 + (uint32_t)__builtin_ctzll(lg) : je;
+        };
         // cross the leafless columns [j, je) in this wave's region, visiting
         // only those with a multiple in it
         auto cross_run = [&](uint32_t j, uint32_t je) {
             while (j < je) {
                 ensure_group(j);
                 const uint32_t ge = min(je, cg0 + 64);
-                uint64_t msk = __ballot(v_nm != 0 && cg0 + lane >= j && cg0 + lane < ge);
+                const uint32_t xb = xbatch_from(j, ge);
+                uint64_t msk = __ballot(v_nm != 0 && cg0 + lane >= j && cg0 + lane < xb);
                 while (msk) {
                     const int32_t k = (int32_t)__builtin_ctzll(msk);
                     msk &= msk - 1;
                     cross_k(k, (uint32_t)__builtin_amdgcn_readlane((int)v_nm, k));
                 }
+                if (xb < ge)
+                    xbatch(xb, ge, 0, 0);
                 j = ge;
             }
         };
@@ -443,6 +572,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             PC_PH(4);
             __syncthreads(); // every wave is past the open round's columns
             settle();
+            PC_EV(2);
             g_par ^= 1;
             // the next heavy column at or after j0 ends the round
             uint32_t hvn = jend;
@@ -514,6 +644,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         // this wave's part of the leaves of gathered column j that lie in its
         // region: a prefix of the region for each
         auto answer = [&](uint32_t g) {
+            PC_EV(1);
             const uint32_t s0 = g >> 11, s1 = s0 + (g & 0x7FFu);
             bool have = false;
             uint32_t pe = 0, pc0 = 0; // lane prefix of the region's block counts; first block
@@ -645,11 +776,14 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             const uint32_t rc0 = rc;
             const uint32_t col = cg0 + lane;
             const bool inw = col >= j && col < we;
+            const uint32_t xb = xbatch_from(j, we); // columns from xb on: one xbatch step
+            const bool sm = col < xb;
             const uint32_t g = inw ? pre[lane] : 0u; // the round's table
             const bool gath = g != 0;
             const uint32_t rm = gath ? g_rm[g_par * KMAX + lane] : 0u;
-            const uint64_t own = __ballot(gath && ((rm >> wv) & 1u));
-            const uint64_t crs = __ballot(inw && v_nm != 0);
+            const bool mine = gath && ((rm >> wv) & 1u);
+            const uint64_t own = __ballot(mine && sm);
+            const uint64_t crs = __ballot(inw && sm && v_nm != 0);
             uint64_t todo = own | crs;
             while (todo) {
                 const int32_t k = (int32_t)__builtin_ctzll(todo);
@@ -658,6 +792,15 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                     answer((uint32_t)__builtin_amdgcn_readlane((int)g, k));
                 if ((crs >> k) & 1)
                     cross_k(k, (uint32_t)__builtin_amdgcn_readlane((int)v_nm, k));
+            }
+            if (xb < we) {
+                // the large columns' slots run from the first one gathered to
+                // the end of the round
+                const uint64_t gl = __ballot(mine && !sm);
+                const uint32_t es0 =
+                    gl ? (uint32_t)__builtin_amdgcn_readlane((int)g, (int)__builtin_ctzll(gl)) >> 11
+                       : g_used;
+                xbatch(xb, we, es0, g_used);
             }
             const uint32_t rem = inw ? v_rem : 0u;
             const uint32_t before = pc_wave_incl_scan_u32(rem) - rem;
@@ -842,6 +985,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
 #if PC_PHASE_TRACE
                 for (int k = 0; k < 9; k++)
                     tr[5 + k] = ph[k];
+                tr[11] = ev[0]; // phase 6 is unused
+                tr[14] = ev[1];
+                tr[15] = ev[2];
 #endif
             }
         }
@@ -857,6 +1003,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     }
 }
 #undef PC_PH
+#undef PC_EV
 
 // ---------------------------------------------------------------------------
 // Look-back scan over the segments of a window, independently per column:
