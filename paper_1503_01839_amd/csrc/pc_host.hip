@@ -111,7 +111,7 @@ struct Tables {
 Tables g_T;
 
 struct QueryBufs {
-    DevBuf Ub, Xb, e_start, e_count, e_off, e_tmp, e_total, part, sums, fin, qdev;
+    DevBuf Ub, Xb, e_start, e_count, e_off, e_tmp, e_total, e_clu, part, sums, fin, qdev;
     DevBuf work, hot, bounds, tiles_a, trace;
     DevBuf tiles, cnt, wgt, carry_rows, carry_a, carry_b, status, ticket, part_tile_h,
         part_tile_p, part_scan_h, part_scan_p, err;
@@ -284,7 +284,7 @@ void drop_tables()
 void drop_query_bufs()
 {
     QueryBufs &B = g_Q;
-    DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.e_start, &B.e_count, &B.e_off, &B.e_tmp, &B.e_total, &B.part,
+    DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.e_start, &B.e_count, &B.e_off, &B.e_tmp, &B.e_total, &B.e_clu, &B.part,
                      &B.sums, &B.fin, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
                      &B.carry_a, &B.carry_b, &B.status, &B.ticket, &B.part_tile_h,
                      &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err, &B.qdev};
@@ -589,6 +589,7 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     ensure(B.e_start, (a + 2) * 8, "easy ranges");
     ensure(B.e_count, (a + 2) * 8, "easy ranges");
     ensure(B.e_off, (a + 2) * 8, "easy offsets");
+    ensure(B.e_clu, (a + 2) * 16, "easy clusters");
     ensure(B.e_tmp, ((a + 2) / 4096 + 2) * 8, "scan");
     ensure(B.Ub, (a + 2) * 16, "hard-leaf u ranges");
     Q.Ub = Q.Ub_w = ptr<ulonglong2>(B.Ub);
@@ -596,6 +597,7 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     Q.e_count = ptr<uint64_t>(B.e_count);
     Q.e_off = ptr<uint64_t>(B.e_off);
     Q.e_total = ptr<uint64_t>(B.e_total);
+    Q.e_clu = ptr<uint4>(B.e_clu);
     hipck(pc_launch_leaf_setup(T, Q, ptr<pc_s128>(B.part), ls_blocks, g_stream), "leaf setup");
     hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ls_blocks, &sums->s2t, g_stream), "S2t sum");
     hipck(pc_launch_strip(ptr<uint64_t>(B.e_count), ptr<uint64_t>(B.e_off), a + 1, g_stream),
@@ -1025,7 +1027,7 @@ void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
     auto r256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
     auto chunk = [&](const BatchQuery &b) {
         const size_t na = b.a + 2, cells = b.nseg * b.ncol;
-        return r256(na * 8) + r256(na * 16) + 3 * r256(na * 8) + 2 * r256(cells * 4);
+        return r256(na * 8) + 2 * r256(na * 16) + 3 * r256(na * 8) + 2 * r256(cells * 4);
     };
     std::vector<size_t> o_q(nq);
     for (uint32_t i = 0; i < nq; i++)
@@ -1069,6 +1071,7 @@ void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
         Q.e_start = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_count = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_off = reinterpret_cast<uint64_t *>(carve(na * 8));
+        Q.e_clu = reinterpret_cast<uint4 *>(carve(na * 16));
         Q.cnt = reinterpret_cast<uint32_t *>(carve(b.nseg * b.ncol * 4));
         Q.wgt = reinterpret_cast<int32_t *>(carve(b.nseg * b.ncol * 4));
         Q.e_total = reinterpret_cast<uint64_t *>(base + o_et) + i;

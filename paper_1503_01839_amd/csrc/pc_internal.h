@@ -55,6 +55,7 @@ struct pc_query {
     uint64_t *e_count;      //   exclusive prefix of the counts and their total
     uint64_t *e_off;
     uint64_t *e_total;
+    uint4 *e_clu;           // prime-item b: {single-m items, first K, m split, last m}
     ulonglong2 *Ub_w;       // writable view of Ub (set-up kernels)
     uint64_t *Xb_w;         // writable view of Xb (set-up kernels)
 };

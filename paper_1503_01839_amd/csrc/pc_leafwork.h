@@ -45,7 +45,11 @@ __device__ __forceinline__ bool pc_s1_item(const pc_tables &T, const pc_query &Q
 //   easy range:     max(y/p_b, H_b, p_b) < m <= min(y, x/p_b^2),
 //                   H_b = max(x/p_b^3, x/(p_b (y+1)));
 // for p_b^2 > y every m in the range is prime, so the range is stored as
-// prime indices; otherwise as candidate m (bit 63 of the count).  For a
+// prime indices; otherwise as candidate m (bit 63 of the count).  A prime
+// range is cut at s = 1.5 isqrt(x/p_b): each m <= s is one item; above s,
+// where u = x/(m p_b) < m and consecutive m share pi(u), the items are the
+// values K = pi(u) instead, each standing for the primes m with
+// x/(p_b p_{K+1}) < m <= x/(p_b p_K), all with phi(u, b-1) = K - b + 2.  For a
 // sieving prime it also records the u range of its hard leaves (Ub) and the
 // odd multiples below the sieve end (*cross).
 __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_query &Q,
@@ -77,6 +81,7 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
     }
     if (b <= Q.a) {
         uint64_t st = 0, cn = 0;
+        uint4 clu = make_uint4(0, 0, 0, 0);
         if (b > Q.c && b < Q.a) {
             const uint64_t p = T.primes[b], rp = T.recip[b];
             const uint64_t X = Q.Xb[b];
@@ -91,11 +96,23 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
             uint64_t e2 = tp < Q.y ? tp : Q.y;
             if (p > Q.sqrty) {
                 if (e1 <= e2) {
+                    const uint64_t sx = pc_isqrt(X);
+                    uint64_t s = sx + sx / 2; // single-m items: m <= s
+                    if (s < e1 - 1)
+                        s = e1 - 1;
+                    if (s > e2)
+                        s = e2;
                     const uint64_t k1 = pc_pi_lookup(T.pitab, e1 - 1) + 1;
-                    const uint64_t k2 = pc_pi_lookup(T.pitab, e2);
-                    if (k1 <= k2) {
+                    const uint64_t ns = pc_pi_lookup(T.pitab, s) + 1 - k1;
+                    uint64_t klo = 0, nk = 0;
+                    if (s < e2) { // K = pi(u) for u in [X / e2, X / (s + 1)]
+                        klo = pc_pi_lookup(T.pitab, pc_div_any(X, (uint32_t)e2));
+                        nk = pc_pi_lookup(T.pitab, pc_div_any(X, (uint32_t)(s + 1))) + 1 - klo;
+                    }
+                    if (ns + nk) {
                         st = k1;
-                        cn = k2 - k1 + 1;
+                        cn = ns + nk;
+                        clu = make_uint4((uint32_t)ns, (uint32_t)klo, (uint32_t)s, (uint32_t)e2);
                     }
                 }
                 // trivial: m prime, m > max(m1 - 1, tp), m <= y
@@ -109,6 +126,32 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
         }
         Q.e_start[b] = st;
         Q.e_count[b] = cn;
+        Q.e_clu[b] = clu;
+    }
+}
+
+// Item o of a prime-item b (cl = its e_clu entry, st its first prime index,
+// bm2 = b - 2, Xd = (double)X_b): the prime m = p_{st+o} for o < cl.x, else
+// K = cl.y + o - cl.x and the primes m in (max(X_b / p_{K+1}, cl.z),
+// min(X_b / p_K, cl.w)].  Adds the item's part of S2e to *acc and its
+// leaves to *nl.  Every quotient is at most y < 2^32 - 1.
+__device__ __forceinline__ void pc_easy_prime_item(const pc_tables &T, uint4 cl, uint32_t st,
+                                                   uint64_t X, double Xd, uint32_t bm2, uint32_t o,
+                                                   int64_t *acc, uint32_t *nl)
+{
+    if (o < cl.x) {
+        const uint32_t u = pc_quot32(X, Xd, T.primes[st + o]); // p_b <= u <= y
+        *acc += pc_pi_lookup32(T.pitab, u) - bm2;              // phi(u, b-1) = pi(u) - b + 2
+        (*nl)++;
+    } else {
+        const uint32_t K = cl.y + (o - cl.x);
+        const uint32_t hi = min(pc_quot32(X, Xd, T.primes[K]), cl.w);
+        const uint32_t lo = max(pc_quot32(X, Xd, T.primes[K + 1]), cl.z);
+        if (hi > lo) {
+            const uint32_t n = pc_pi_lookup32(T.pitab, hi) - pc_pi_lookup32(T.pitab, lo);
+            *acc += (int64_t)n * (int64_t)(K - bm2);
+            *nl += n;
+        }
     }
 }
 
@@ -120,8 +163,9 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
 // and neighbouring pi(u) entries.  u = x/(m p_b) <= y < 2^32 - 1, so the
 // reciprocal estimate quotient is exact after its remainder check.  The
 // candidate-m items (p_b^2 <= y) all precede the prime items (p_b^2 > y), so a
-// tile that starts in a prime range has only prime items: every one is a
-// leaf with -mu(m) = 1, and the loop needs no filter.
+// tile that starts in a prime range has only prime items (single primes m,
+// -mu(m) = 1, or groups of them sharing K = pi(u); pc_easy_prime_item), and
+// its loop needs no filter.
 template <int NT, int PER>
 __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query &Q, uint64_t lb,
                                               uint64_t nlb, uint32_t *s_b0, int64_t *acc,
@@ -150,26 +194,26 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
             // prime items only; item t of the tile is item t - rs of its b
             int64_t rs = (int64_t)(e_off[b] - i0), re = rs + (int64_t)cn;
             uint32_t st = (uint32_t)e_start[b], bm2 = b - 2;
+            uint4 cl = Q.e_clu[b];
             uint64_t X = Q.Xb[b];
             double Xd = (double)X;
             int64_t a = 0;
+            uint32_t nl = 0;
             for (uint32_t t = threadIdx.x; t < n; t += NT) {
                 while ((int64_t)t >= re) {
                     b++;
                     rs = re;
                     re = rs + (int64_t)e_count[b];
                     st = (uint32_t)e_start[b];
+                    cl = Q.e_clu[b];
                     bm2 = b - 2;
                     X = Q.Xb[b];
                     Xd = (double)X;
                 }
-                const uint32_t m = T.primes[st + (uint32_t)((int64_t)t - rs)];
-                const uint32_t u = pc_quot32(X, Xd, m); // p_b <= u <= y
-                a += pc_pi_lookup32(T.pitab, u) - bm2;  // phi(u, b-1) = pi(u) - b + 2 >= 1
+                pc_easy_prime_item(T, cl, st, X, Xd, bm2, (uint32_t)((int64_t)t - rs), &a, &nl);
             }
             *acc += a;
-            if (threadIdx.x == 0)
-                *nleaf += n;
+            *nleaf += nl;
         } else {
             uint64_t off = e_off[b], st = e_start[b], X = Q.Xb[b];
             double Xd = (double)X;
@@ -186,21 +230,23 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
                     p = T.primes[b];
                 }
                 const uint64_t o = i - off;
-                uint32_t m;
-                int32_t w;
-                if (cn & PC_MODEBIT) {
-                    m = (uint32_t)(st + o);
-                    const int32_t v = T.mulpf[m];
-                    const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
-                    if (l <= p) // mu(m) = 0 or lpf(m) <= p_b
-                        continue;
-                    w = v > 0 ? -1 : 1;
-                } else {
-                    m = T.primes[st + o];
-                    w = 1;
+                if (!(cn & PC_MODEBIT)) { // a prime-item b past the tile's start
+                    int64_t a = 0;
+                    uint32_t nl = 0;
+                    pc_easy_prime_item(T, Q.e_clu[b], (uint32_t)st, X, Xd, b - 2, (uint32_t)o, &a,
+                                       &nl);
+                    *acc += a;
+                    *nleaf += nl;
+                    continue;
                 }
+                const uint32_t m = (uint32_t)(st + o);
+                const int32_t v = T.mulpf[m];
+                const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
+                if (l <= p) // mu(m) = 0 or lpf(m) <= p_b
+                    continue;
                 const uint32_t u = pc_quot32(X, Xd, m); // u <= y < 2^32 - 1
-                *acc += (int64_t)w * ((int64_t)pc_pi_lookup32(T.pitab, u) - (int64_t)b + 2);
+                const int64_t phi = (int64_t)pc_pi_lookup32(T.pitab, u) - (int64_t)b + 2;
+                *acc += v > 0 ? -phi : phi; // -mu(m) phi(u, b-1)
                 (*nleaf)++;
             }
         }
