@@ -75,10 +75,12 @@ __global__ __launch_bounds__(BT) void k_leaf_setup_b(pc_tables T, const pc_query
 }
 
 // e_off = exclusive prefix of the easy item counts of b = 0..a, one workgroup
-// per query, in chunks of BT entries.
+// per query, in chunks of BT entries; then the suffix maxima of the hard-leaf
+// u ranges (pc_ub_suffix).
 __global__ __launch_bounds__(BT) void k_escan_b(const pc_query *Qs)
 {
     __shared__ uint64_t scr[BT / 64];
+    __shared__ uint64_t sh[BT];
     const pc_query &Q = Qs[blockIdx.x];
     uint64_t run = 0;
     for (uint32_t b0 = 0; b0 <= Q.a; b0 += BT) {
@@ -92,6 +94,7 @@ __global__ __launch_bounds__(BT) void k_escan_b(const pc_query *Qs)
     }
     if (threadIdx.x == 0)
         *Q.e_total = run;
+    pc_ub_suffix<BT>(Q, sh);
 }
 
 __global__ __launch_bounds__(BT) void k_easy_b(pc_tables T, const pc_query *Qs, pc_blk B)

@@ -46,7 +46,8 @@ struct pc_query {
     const uint64_t *Xb;     // Xb[b] = floor(x / p_b), 1-based, b <= a
     uint64_t sieve_end;     // the sieve covers [0, sieve_end): segments * 2S integers
     uint64_t nseg;          // segments (rows of cnt and wgt when the query has one window)
-    const ulonglong2 *Ub;   // Ub[b] = [u_lo, u_hi]: u of every hard leaf of b (x > y: none)
+    const ulonglong2 *Ub;   // Ub[b].x <= u of every hard leaf of b <= Ub[b].y, and Ub[b].y is
+                            // also >= that bound for every later sieving prime (x > y: none)
     pc_sums *sums;          // device accumulators of this query
     uint32_t *cnt;          // sieve counts [row * ncol + col], row = seg - seg0
     int32_t *wgt;           // leaf weights, same layout

@@ -130,6 +130,36 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
     }
 }
 
+// After the per-b set-up: Ub[b].y becomes the largest u of a hard leaf of any
+// sieving prime p_b' with b' >= b, so that in a segment [lo, hi) the columns
+// whose Ub.y < lo form a suffix: no prime from there on has a hard leaf at or
+// above lo, and the sieve needs neither their counts nor their order (they
+// are only cleared).  The calling workgroup (NT threads) does one query.
+template <int NT> __device__ __forceinline__ void pc_ub_suffix(const pc_query &Q, uint64_t *sh)
+{
+    const uint32_t b0 = Q.c + 1, n = Q.nb;
+    const uint32_t per = (n + NT - 1) / NT;
+    const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
+    uint64_t m = 0;
+    for (uint32_t i = lo; i < hi; i++)
+        m = max(m, Q.Ub_w[b0 + i].y);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (uint32_t d = 1; d < NT; d <<= 1) { // suffix maximum over the threads' pieces
+        uint64_t v = sh[threadIdx.x];
+        if (threadIdx.x + d < NT)
+            v = max(v, sh[threadIdx.x + d]);
+        __syncthreads();
+        sh[threadIdx.x] = v;
+        __syncthreads();
+    }
+    uint64_t run = threadIdx.x + 1 < NT ? sh[threadIdx.x + 1] : 0;
+    for (uint32_t i = hi; i > lo; i--) {
+        run = max(run, Q.Ub_w[b0 + i - 1].y);
+        Q.Ub_w[b0 + i - 1].y = run;
+    }
+}
+
 // Item o of a prime-item b (cl = its e_clu entry, st its first prime index,
 // bm2 = b - 2, Xd = (double)X_b): the prime m = p_{st+o} for o < cl.x, else
 // K = cl.y + o - cl.x and the primes m in (max(X_b / p_{K+1}, cl.z),

@@ -48,10 +48,17 @@ __global__ __launch_bounds__(LV_T) void k_leaf_setup(pc_tables T, pc_query Q, pc
     }
 }
 
+__global__ __launch_bounds__(1024) void k_ub_suffix(pc_query Q)
+{
+    __shared__ uint64_t sh[1024];
+    pc_ub_suffix<1024>(Q, sh);
+}
+
 hipError_t pc_launch_leaf_setup(const pc_tables &T, const pc_query &Q, pc_s128 *part_trivial,
                                 uint32_t nblocks, hipStream_t s)
 {
     k_leaf_setup<<<nblocks, LV_T, 0, s>>>(T, Q, part_trivial);
+    k_ub_suffix<<<1, 1024, 0, s>>>(Q);
     return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ template <int LOG2_S, int T, int CH> constexpr int pc_sieve_waves_per_simd()
     constexpr long NWV = T / 64;
     constexpr long KMAX = 64; // gathered columns per round (g_rc, g_rm)
     constexpr long lds = 4 * (NWP + 16) + 4 * (NBLK + 1) + 4 * pc_sieve_gcap<LOG2_S, T, CH>() +
-                         2 * KMAX * NWV + 8 * KMAX + 24 * CH + 16 * (CH / 64) + 4 + 8 * NWV +
+                         2 * KMAX * NWV + 8 * KMAX + 24 * CH + 16 * (CH / 64) + 8 + 8 * NWV +
                          16 * NWV;
     constexpr long wg = 163840 / lds;
     constexpr long waves = wg * NWV < 32 ? wg * NWV : 32;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     __shared__ int32_t c_w[CH];        // sum of -mu(m) over the leaves of the column
     __shared__ uint64_t c_leafy[CH / 64];
     __shared__ uint64_t c_heavy[CH / 64];
-    __shared__ uint32_t s_first_large;
+    __shared__ uint32_t s_first_large, s_first_skip;
     __shared__ uint32_t reg_dec[NWV];  // integers a batched crossing removed, per region
     __shared__ uint32_t scr32[NWV];
     __shared__ pc_s128 scr128[NWV];
@@ -265,13 +265,15 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     const uint32_t col_lo = tile.col_lo, col_hi = tile.col_hi;
     const uint32_t ncross = min(col_hi, Q.nb);
     for (uint32_t cb = 0; cb < ncross; cb += CH) {
-        const uint32_t jend = min((uint32_t)CH, ncross - cb);
-        if (tid == 0)
-            s_first_large = jend;
+        const uint32_t jall = min((uint32_t)CH, ncross - cb);
+        if (tid == 0) {
+            s_first_large = jall;
+            s_first_skip = jall;
+        }
         __syncthreads();
         // --- one lane per column: first multiple, leaf range ---
-        bool leafy = false, heavy = false, large = false;
-        if (tid < jend) {
+        bool leafy = false, heavy = false, large = false, skip = false;
+        if (tid < jall) {
             const uint32_t j = tid, col = cb + j, b = qc + 1 + col;
             const uint64_t p = TB.primes[b];
             const uint64_t rp = TB.recip[b];
@@ -290,11 +292,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             c_i0[j] = first < hi ? (uint32_t)((first - lo - 1) >> 1) : S;
             large = (pc_u128)p * p * p >= hi;
             uint32_t ls = 0, lc = 0;
-            if (MODE != PC_MODE_COUNT && col >= col_lo && col < col_hi) {
-                const ulonglong2 ub = Q.Ub[b]; // u range of every hard leaf of b
-                if (ub.x < hi && ub.y >= lo)
-                    pc_leaf_range(TB, Q, b, p, rp, lo, hi, rhi, rlo, &ls, &lc);
-            }
+            // every hard leaf of b and of the later primes lies below ub.y
+            const ulonglong2 ub = Q.Ub[b];
+            skip = ub.y < lo;
+            if (MODE != PC_MODE_COUNT && col >= col_lo && col < col_hi && ub.x < hi && !skip)
+                pc_leaf_range(TB, Q, b, p, rp, lo, hi, rhi, rlo, &ls, &lc);
             c_ls[j] = ls;
             c_lc[j] = lc;
             c_new[j] = 0;
@@ -304,16 +306,22 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         }
         {
             const uint64_t bl = __ballot(leafy), bh = __ballot(heavy), bg = __ballot(large);
+            const uint64_t bs = __ballot(skip);
             if (lane == 0) {
                 c_leafy[tid >> 6] = bl;
                 c_heavy[tid >> 6] = bh;
                 if (bg)
                     atomicMin(&s_first_large, (tid & ~63u) + (uint32_t)__builtin_ctzll(bg));
+                if (bs)
+                    atomicMin(&s_first_skip, (tid & ~63u) + (uint32_t)__builtin_ctzll(bs));
             }
         }
         __syncthreads();
         PC_PH(1);
-        const uint32_t first_large = BATCH ? s_first_large : jend;
+        // columns [jend, jall) and every later chunk's are past their last hard
+        // leaf (skip, a suffix): they are only cleared, after this chunk
+        const uint32_t jend = s_first_skip;
+        const uint32_t first_large = BATCH ? min(s_first_large, jend) : jend;
 
         // For 64 columns from cg0 on (one column per lane): p, the first
         // multiple of p at or above R0 and the number of its multiples in
@@ -904,28 +912,59 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             const uint32_t v = tid < jend ? c_new[tid] : 0;
             uint32_t tot;
             const uint32_t ex = pc_block_excl_scan<T>(v, scr32, &tot);
-            if (tid < jend) {
+            if (tid < jall) {
                 const uint32_t col = cb + tid;
+                const bool cut = tid >= jend; // a count no leaf reads: 0
                 if (col >= col_lo && col < col_hi) {
                     const uint64_t idx = row * ncol + col;
                     if (MODE != PC_MODE_LEAVES)
-                        Q.cnt[idx] = total - ex;
+                        Q.cnt[idx] = cut ? 0u : total - ex;
                     if (MODE == PC_MODE_TALLY)
-                        Q.wgt[idx] = c_w[tid];
-                    if (MODE == PC_MODE_LEAVES && c_w[tid] != 0)
+                        Q.wgt[idx] = cut ? 0 : c_w[tid];
+                    if (MODE == PC_MODE_LEAVES && !cut && c_w[tid] != 0)
                         acc_carry += (pc_s128)c_w[tid] * (pc_s128)Q.carry[idx];
                 }
             }
             total -= tot;
         }
         PC_PH(7);
+        if (jend < jall) {
+            // Every column from cb + jend on is past its last hard leaf: its
+            // count is read by no leaf and it removes nothing a later leaf of
+            // this segment counts, so its multiples are only cleared, in any
+            // order, one thread per column.  Its counts are written as 0.
+            for (uint32_t col = cb + jend + tid; col < ncross; col += T) {
+                const uint32_t b = qc + 1 + col;
+                const uint64_t p = TB.primes[b];
+                uint64_t first = p;
+                if (lo > p) {
+                    first = pc_div(lo, p, TB.recip[b]) * p;
+                    if (first < lo)
+                        first += p;
+                    if ((first & 1) == 0)
+                        first += p;
+                }
+                if (first < hi)
+                    for (uint32_t bit = (uint32_t)((first - lo - 1) >> 1); bit < S; bit += (uint32_t)p)
+                        __hip_atomic_fetch_and(&BW(bit >> 5), ~(1u << (bit & 31)), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (MODE != PC_MODE_LEAVES && col >= cb + jall && col >= col_lo && col < col_hi) {
+                    const uint64_t idx = row * ncol + col;
+                    Q.cnt[idx] = 0;
+                    if (MODE == PC_MODE_TALLY)
+                        Q.wgt[idx] = 0;
+                }
+            }
+            PC_PH(5);
+            break;
+        }
     }
 
     // --- final column: P2 lookups pi(x/p) = phi(x/p, bmax) + bmax - 1 ---
     pc_s128 extra_p2 = 0; // PC_MODE_LEAVES: carry * (lookups), kept by thread 0
     if (col_hi == ncol) {
         __syncthreads();
-        build_pre();
+        total = build_pre(); // (the running total skips the cleared-only columns)
         uint32_t k1 = 1, k2 = 0;
         {
             const uint64_t tA = pc_div(Q.x, hi, rhi);              // x/p < hi  <=> p > x/hi
