@@ -103,7 +103,7 @@ struct Tables {
     uint64_t recip_n = 0;
     DevBuf mulpf;
     uint64_t y_limit = 0;
-    DevBuf pattern[kWheelC + 1], phitab[kWheelC + 1];
+    DevBuf pattern[kWheelC + 1], phitab[kWheelC + 1], wres[kWheelC + 1];
     bool wheel_ok[kWheelC + 1] = {};
     uint32_t pattern_bits[kWheelC + 1] = {}, Qc[kWheelC + 1] = {}, phiQ[kWheelC + 1] = {};
     DevBuf lk_in, lk_out;
@@ -240,8 +240,9 @@ void ensure_wheel(uint32_t c)
     uint32_t words = (period + 64) / 32 + 2;
     ensure(T.pattern[c], words * 4, "wheel pattern");
     ensure(T.phitab[c], (size_t)Q * 4, "wheel phi table");
+    ensure(T.wres[c], (size_t)phiQ * 4, "wheel residues");
     hipck(pc_launch_wheel(c, ptr<uint32_t>(T.primes), ptr<uint32_t>(T.pattern[c]), words,
-                          ptr<uint32_t>(T.phitab[c]), g_stream),
+                          ptr<uint32_t>(T.phitab[c]), ptr<uint32_t>(T.wres[c]), g_stream),
           "wheel");
     T.pattern_bits[c] = period;
     T.Qc[c] = Q;
@@ -259,9 +260,11 @@ pc_tables tables_view(uint32_t c)
     v.mulpf = ptr<int32_t>(T.mulpf);
     v.pattern = ptr<uint32_t>(T.pattern[c]);
     v.phitab = ptr<uint32_t>(T.phitab[c]);
+    v.wres = ptr<uint32_t>(T.wres[c]);
     v.pattern_bits = T.pattern_bits[c];
     v.Qc = T.Qc[c];
     v.phiQ = T.phiQ[c];
+    v.rphiQ = 1.0f / (float)T.phiQ[c];
     return v;
 }
 
@@ -275,6 +278,7 @@ void drop_tables()
     for (int c = 0; c <= kWheelC; c++) {
         dfree(T.pattern[c]);
         dfree(T.phitab[c]);
+        dfree(T.wres[c]);
         T.wheel_ok[c] = false;
     }
     T.base_ok = false;

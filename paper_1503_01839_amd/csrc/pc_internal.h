@@ -26,10 +26,11 @@ struct pc_tables {
     const int32_t *mulpf;   // mu(n)*lpf(n) for n <= ymax; INT32_MAX at n = 1; 0 if mu = 0
     const uint32_t *pattern; // odd-only pre-sieve bits for p_2..p_c, period pattern_bits (+64 bits)
     const uint32_t *phitab; // phi(r, c) for r < Q_c
+    const uint32_t *wres;   // the residues r < Q_c prime to p_1..p_c, ascending (phi(Q_c, c) of them)
     uint32_t pattern_bits;  // prod_{2 <= i <= c} p_i
     uint32_t Qc;            // prod_{1 <= i <= c} p_i
     uint32_t phiQ;          // phi(Q_c, c)
-    uint32_t pad;
+    float rphiQ;            // 1 / phi(Q_c, c)
 };
 
 struct pc_sums;
@@ -91,7 +92,8 @@ hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, uint32_t n, 
 hipError_t pc_launch_mulpf(const uint32_t *primes, uint32_t nsmall, uint64_t ymax,
                            int32_t *mulpf, hipStream_t s);
 hipError_t pc_launch_wheel(uint32_t c, const uint32_t *primes, uint32_t *pattern,
-                           uint32_t pattern_words, uint32_t *phitab, hipStream_t s);
+                           uint32_t pattern_words, uint32_t *phitab, uint32_t *wres,
+                           hipStream_t s);
 hipError_t pc_launch_lookup(const uint2 *pitab, const uint64_t *in, uint32_t n, uint64_t *out,
                             hipStream_t s);
 hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint32_t a, uint64_t *Xb, hipStream_t s);

@@ -8,10 +8,35 @@
 
 #define PC_CAND 0x80000000u
 
+// Candidates m for a prime p_b <= sqrt(y) are the integers prime to
+// p_1..p_c (lpf(m) > p_b > p_c implies it), numbered from 0 in increasing
+// order: candidate k is Q_c (k / phi(Q_c)) + wres[k mod phi(Q_c)], and the
+// candidates up to m number phi(m, c) = phi(Q_c) (m / Q_c) + phitab[m mod Q_c].
+__device__ __forceinline__ uint32_t pc_wheel_m(const pc_tables &T, uint32_t k)
+{
+    uint32_t q = (uint32_t)((float)k * T.rphiQ); // within one of k / phi(Q_c) (k < 2^24 phi(Q_c))
+    int32_t r = (int32_t)(k - q * T.phiQ);
+    if (r < 0) {
+        q--;
+        r += (int32_t)T.phiQ;
+    } else if (r >= (int32_t)T.phiQ) {
+        q++;
+        r -= (int32_t)T.phiQ;
+    }
+    return q * T.Qc + T.wres[r];
+}
+
+__device__ __forceinline__ uint64_t pc_wheel_count(const pc_tables &T, const pc_query &Q, uint64_t m)
+{
+    const uint64_t q = pc_div(m, Q.Qc, Q.recip_Qc);
+    return q * T.phiQ + T.phitab[m - q * Q.Qc];
+}
+
 // The hard leaves (b, m) whose u = floor(X_b/m) lies in [lo, hi): special
 // (y/p_b < m <= y, lpf(m) > p_b) and hard (m <= max(x/p^3, x/(p(y+1)))).
 // For p_b^2 > y every such m is prime and the range is returned as prime
-// indices [ls, ls + lc); otherwise as candidate m values, lc | PC_CAND.
+// indices [ls, ls + lc); otherwise as candidate numbers (pc_wheel_m),
+// lc | PC_CAND.
 __device__ __forceinline__ void pc_leaf_mrange(const pc_query &Q, uint32_t b, uint64_t p,
                                                uint64_t rp, uint64_t lo, uint64_t hi,
                                                uint64_t rhi, uint64_t rlo, uint64_t *m1o,
@@ -54,8 +79,11 @@ __device__ __forceinline__ void pc_leaf_range(const pc_tables &TB, const pc_quer
                 *lc = k2 - k1 + 1;
             }
         } else {
-            *ls = (uint32_t)m1;
-            *lc = (uint32_t)(m2 - m1 + 1) | PC_CAND;
+            const uint64_t k1 = pc_wheel_count(TB, Q, m1 - 1), k2 = pc_wheel_count(TB, Q, m2);
+            if (k1 < k2) {
+                *ls = (uint32_t)k1;
+                *lc = (uint32_t)(k2 - k1) | PC_CAND;
+            }
         }
     }
 }

@@ -30,8 +30,8 @@ __device__ __forceinline__ uint32_t pc_col_items(const pc_tables &TB, const pc_q
     if (m1 > m2)
         return 0;
     const uint64_t n = m2 - m1 + 1;
-    if (p <= Q.sqrty)
-        return (uint32_t)n;
+    if (p <= Q.sqrty) // candidates prime to p_1..p_c
+        return (uint32_t)((float)n * ((float)TB.phiQ / (float)TB.Qc)) + 1u;
     return (uint32_t)(2.0f * (float)n / __logf((float)m2 + 2.0f)) + 1u;
 }
 

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     __shared__ uint32_t c_p[CH];       // p_b
     __shared__ uint32_t c_i0[CH];      // bit of the first multiple in the segment, S if none
     __shared__ uint32_t c_ls[CH];      // first leaf item (m, or index of the prime m)
-    __shared__ uint32_t c_lc[CH];      // leaf items; PC_CAND: items are candidate m
+    __shared__ uint32_t c_lc[CH];      // leaf items; PC_CAND: items are candidates (pc_wheel_m)
     __shared__ uint32_t c_new[CH];     // integers first removed by p_b in this segment
     __shared__ int32_t c_w[CH];        // sum of -mu(m) over the leaves of the column
     __shared__ uint64_t c_leafy[CH / 64];
@@ -242,10 +242,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     auto leaf_filter = [&](uint32_t j, uint32_t it, uint64_t *m, int32_t *w) -> bool {
         const uint32_t lc = c_lc[j], ls = c_ls[j];
         if (lc & PC_CAND) {
-            const int32_t v = TB.mulpf[ls + it];
+            const uint32_t mc = pc_wheel_m(TB, ls + it);
+            const int32_t v = TB.mulpf[mc];
             const uint32_t av = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
             n_cand++;
-            *m = ls + it;
+            *m = mc;
             *w = v > 0 ? -1 : 1;
             return av > c_p[j];
         }
@@ -721,14 +722,14 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 const uint32_t p = c_p[j];
                 uint32_t *const slot = gbuf + wv * 64; // this wave's slots
                 uint32_t held = 0;                     // filled slots (uniform)
-                // slot entry: candidate index | (mu(m) > 0) << 31
+                // slot entry: m | (mu(m) > 0) << 31
                 auto drain = [&]() {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     if (lane < held) {
                         const uint32_t e = slot[lane];
-                        one(ls + (e & 0x7FFFFFFFu), (e >> 31) ? -1 : 1);
+                        one(e & 0x7FFFFFFFu, (e >> 31) ? -1 : 1);
                     }
                     held = 0;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -739,9 +740,12 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 for (uint32_t base = wv * 64 * HU; base < n; base += HU * T) {
                     const uint32_t it0 = base + lane;
                     int32_t v[HU];
+                    uint32_t mm[HU];
 #pragma unroll
-                    for (uint32_t u = 0; u < HU; u++)
-                        v[u] = it0 + u * 64 < n ? TB.mulpf[ls + it0 + u * 64] : 0;
+                    for (uint32_t u = 0; u < HU; u++) {
+                        mm[u] = pc_wheel_m(TB, ls + it0 + u * 64);
+                        v[u] = it0 + u * 64 < n ? TB.mulpf[mm[u]] : 0;
+                    }
 #pragma unroll
                     for (uint32_t u = 0; u < HU; u++) {
                         const uint32_t it = it0 + u * 64;
@@ -754,7 +758,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                             drain();
                         if (keep)
                             slot[held + (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1))] =
-                                it | (v[u] > 0 ? 0x80000000u : 0u);
+                                mm[u] | (v[u] > 0 ? 0x80000000u : 0u);
                         held += k;
                         if (held == 64)
                             drain();

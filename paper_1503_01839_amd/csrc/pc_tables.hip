@@ -322,7 +322,7 @@ hipError_t pc_launch_mulpf(const uint32_t *primes, uint32_t nsmall, uint64_t yma
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_wheel(uint32_t c, const uint32_t *primes,
                                               uint32_t *pattern, uint32_t pattern_words,
-                                              uint32_t *phitab)
+                                              uint32_t *phitab, uint32_t *wres)
 {
     __shared__ uint32_t scr[16];
     const uint32_t t = threadIdx.x;
@@ -364,12 +364,22 @@ __global__ __launch_bounds__(1024) void k_wheel(uint32_t c, const uint32_t *prim
         }
         phitab[r] = run;
     }
+    __syncthreads();
+    // the residues prime to p_1..p_c in order: r is number phi(r, c) - 1
+    for (uint32_t r = max(r0, 1u); r < r1; r++) {
+        bool ok = true;
+        for (uint32_t i = 0; i < c; i++)
+            ok = ok && (r % P[i] != 0);
+        if (ok)
+            wres[phitab[r] - 1] = r;
+    }
 }
 
 hipError_t pc_launch_wheel(uint32_t c, const uint32_t *primes, uint32_t *pattern,
-                           uint32_t pattern_words, uint32_t *phitab, hipStream_t s)
+                           uint32_t pattern_words, uint32_t *phitab, uint32_t *wres,
+                           hipStream_t s)
 {
-    k_wheel<<<1, 1024, 0, s>>>(c, primes, pattern, pattern_words, phitab);
+    k_wheel<<<1, 1024, 0, s>>>(c, primes, pattern, pattern_words, phitab, wres);
     return hipGetLastError();
 }
 
