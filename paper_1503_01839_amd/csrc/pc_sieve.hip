@@ -374,11 +374,12 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)v_f, k);
             const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)v_p, k);
             // a lane's multiples lie 64 p bits apart, a multiple of 32: they
-            // all sit at the same bit of their words
-            uint32_t bit = f + lane * p;
-            const uint32_t sh = bit & 31, keep = ~(1u << sh), step = 64 * p;
-            auto clear = [&](uint32_t b) -> uint32_t {
-                const uint32_t old = __hip_atomic_fetch_and(&BW(b >> 5), keep, __ATOMIC_RELAXED,
+            // all sit at the same bit of their words, 2 p words apart
+            const uint32_t bit = f + lane * p;
+            const uint32_t sh = bit & 31, keep = ~(1u << sh), wstep = 2 * p;
+            uint32_t w = bit >> 5;
+            auto clear = [&](uint32_t wd) -> uint32_t {
+                const uint32_t old = __hip_atomic_fetch_and(&BW(wd), keep, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_WORKGROUP);
                 return (old >> sh) & 1u;
             };
@@ -386,17 +387,17 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             const uint32_t full = nm >> 6; // rounds in which every lane has a multiple
             if (full) {
                 uint32_t hits = 0, t = 0;
-                for (; t + 2 <= full; t += 2, bit += 2 * step) // two clears in flight
-                    hits += clear(bit) + clear(bit + step);
+                for (; t + 2 <= full; t += 2, w += 2 * wstep) // two clears in flight
+                    hits += clear(w) + clear(w + wstep);
                 if (t < full) {
-                    hits += clear(bit);
-                    bit += step;
+                    hits += clear(w);
+                    w += wstep;
                 }
                 removed = pc_wave_sum_u32(hits);
             }
             bool hit = false;
             if (lane < (nm & 63))
-                hit = clear(bit) != 0;
+                hit = clear(w) != 0;
             removed += (uint32_t)__builtin_popcountll(__ballot(hit));
             rc -= removed;
             if (lane == (uint32_t)k)
