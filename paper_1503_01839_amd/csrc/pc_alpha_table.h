@@ -9,29 +9,29 @@ struct pc_alpha_entry {
 };
 
 static const pc_alpha_entry kAlphaTable[] = {
-    {7.0, 24}, // 0.33 ms
-    {7.5, 16}, // 0.37 ms
-    {8.0, 8}, // 0.42 ms
-    {8.5, 6}, // 0.51 ms
-    {9.0, 3}, // 0.62 ms
-    {9.5, 2}, // 0.78 ms
-    {10.0, 1.5}, // 1.00 ms
-    {10.5, 1.5}, // 1.29 ms
-    {11.0, 2}, // 1.75 ms
-    {11.5, 1.5}, // 2.33 ms
-    {12.0, 4}, // 2.63 ms
-    {12.5, 4}, // 3.40 ms
-    {13.0, 3}, // 3.33 ms
-    {13.5, 2}, // 3.69 ms
-    {14.0, 3}, // 3.98 ms
-    {14.5, 2}, // 4.27 ms
-    {15.0, 4}, // 7.98 ms
-    {15.5, 6}, // 9.79 ms
-    {16.0, 8}, // 13.24 ms
-    {16.5, 12}, // 27.78 ms
-    {17.0, 12}, // 58.88 ms
-    {17.5, 16}, // 125.78 ms
-    {18.0, 16}, // 264.63 ms
-    {18.5, 16}, // 585.45 ms
-    {19.0, 24}, // 1258.44 ms
+    {7.0, 8}, // 0.31 ms
+    {7.5, 48}, // 0.33 ms
+    {8.0, 48}, // 0.35 ms
+    {8.5, 48}, // 0.40 ms
+    {9.0, 48}, // 0.47 ms
+    {9.5, 12}, // 0.57 ms
+    {10.0, 12}, // 0.74 ms
+    {10.5, 12}, // 0.97 ms
+    {11.0, 12}, // 1.39 ms
+    {11.5, 6}, // 1.89 ms
+    {12.0, 8}, // 2.59 ms
+    {12.5, 8}, // 2.46 ms
+    {13.0, 6}, // 2.96 ms
+    {13.5, 6}, // 3.40 ms
+    {14.0, 3}, // 3.66 ms
+    {14.5, 2}, // 4.08 ms
+    {15.0, 4}, // 5.50 ms
+    {15.5, 4}, // 7.11 ms
+    {16.0, 4}, // 8.92 ms
+    {16.5, 12}, // 12.56 ms
+    {17.0, 16}, // 24.91 ms
+    {17.5, 24}, // 48.69 ms
+    {18.0, 24}, // 103.71 ms
+    {18.5, 32}, // 211.89 ms
+    {19.0, 32}, // 457.42 ms
 };

@@ -610,8 +610,10 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
                              ptr<uint64_t>(B.e_total), g_stream),
           "easy scan");
     // The easy leaves touch nothing the sieve writes: they run on the second
-    // stream, launched once the first sieve window is queued (the tile plan
-    // before it needs the GPU to itself), and rejoin before the combination.
+    // stream once the last sieve window is queued, and rejoin before the
+    // combination.  Both kernels keep every CU busy, so running them side by
+    // side gains nothing (measured); after the windows, neither delays the
+    // other's launches.
     size_t ev_easy = 0;
     bool forked = false;
     auto fork_easy = [&]() {
@@ -759,7 +761,6 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         const int first = K.two_pass ? PC_MODE_COUNT : PC_MODE_TALLY;
         sieve(true, first);
         sieve(false, first);
-        fork_easy();
 
         pc_scan_args SA{};
         SA.cnt = ptr<uint32_t>(B.cnt);
