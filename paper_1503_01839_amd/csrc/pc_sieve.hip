@@ -220,8 +220,21 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         }
         return s;
     };
-    // unsieved integers among bits [0, q), q <= S, against pre[]
-    auto count_pre = [&](uint32_t q) -> uint32_t { return pre[q >> BL] + in_block(q); };
+    // unsieved integers among bits [0, q), q <= S, against pre[]: from the
+    // nearer end of q's block, so eight of its words are read, not sixteen
+    auto count_pre = [&](uint32_t q) -> uint32_t {
+        const uint32_t blk = q >> BL, nw = (q >> 5) & 15, part = (1u << (q & 31)) - 1;
+        const bool up = nw >= 8; // count the bits at or above q, from the block's end
+        const uint32_t base = blk * 17 + (up ? 8u : 0u), k0 = up ? 8u : 0u;
+        const uint32_t below = up ? 0u : ~0u, at = up ? ~part : part, above = ~below;
+        uint32_t s = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t m = k0 + k < nw ? below : (k0 + k == nw ? at : above);
+            s += (uint32_t)__builtin_popcount(bm[base + k] & m);
+        }
+        return up ? pre[blk + 1] - s : pre[blk] + s;
+    };
 
     uint32_t total = build_pre();
     PC_PH(0);
