@@ -220,19 +220,25 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         }
         return s;
     };
-    // unsieved integers among bits [0, q), q <= S, against pre[]: from the
-    // nearer end of q's block, so eight of its words are read, not sixteen
-    auto count_pre = [&](uint32_t q) -> uint32_t {
-        const uint32_t blk = q >> BL, nw = (q >> 5) & 15, part = (1u << (q & 31)) - 1;
-        const bool up = nw >= 8; // count the bits at or above q, from the block's end
-        const uint32_t base = blk * 17 + (up ? 8u : 0u), k0 = up ? 8u : 0u;
-        const uint32_t below = up ? 0u : ~0u, at = up ? ~part : part, above = ~below;
+    // unsieved integers of q's block on q's side: below q when q lies in the
+    // block's lower half (*up false), at or above q otherwise; eight words
+    auto half_count = [&](uint32_t q, bool *up) -> uint32_t {
+        const uint32_t nw = (q >> 5) & 15, part = (1u << (q & 31)) - 1;
+        *up = nw >= 8;
+        const uint32_t base = (q >> BL) * 17 + (*up ? 8u : 0u), k0 = *up ? 8u : 0u;
+        const uint32_t below = *up ? 0u : ~0u, at = *up ? ~part : part, above = ~below;
         uint32_t s = 0;
 #pragma unroll
         for (uint32_t k = 0; k < 8; k++) {
             const uint32_t m = k0 + k < nw ? below : (k0 + k == nw ? at : above);
             s += (uint32_t)__builtin_popcount(bm[base + k] & m);
         }
+        return s;
+    };
+    // unsieved integers among bits [0, q), q <= S, against pre[]
+    auto count_pre = [&](uint32_t q) -> uint32_t {
+        bool up;
+        const uint32_t s = half_count(q, &up), blk = q >> BL;
         return up ? pre[blk + 1] - s : pre[blk] + s;
     };
 
@@ -472,9 +478,16 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                     if (BPT > 1) {
                         const uint32_t c0 = (uint32_t)__shfl((int)pc0, (int)src, 64);
                         c += (bl % BPT) ? c0 : 0u;
+                        if (in)
+                            c += in_block(q);
+                    } else { // the block's count is its lane's: count from q's side
+                        const uint32_t tb = (uint32_t)__shfl((int)pc0, (int)src, 64);
+                        if (in) {
+                            bool up;
+                            const uint32_t hs = half_count(q, &up);
+                            c += up ? tb - hs : hs;
+                        }
                     }
-                    if (in)
-                        c += in_block(q);
                     // less the earlier columns' credited multiples below q:
                     // leaf by leaf (all lanes count for one leaf) or column
                     // by column (all leaves count one column), the shorter
@@ -690,8 +703,15 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                         const uint32_t c0 = (uint32_t)__shfl((int)pc0, (int)src, 64);
                         c += (bl % BPT) ? c0 : 0u;
                     }
+                    const uint32_t tb = (uint32_t)__shfl((int)pc0, (int)src, 64);
                     if (in) {
-                        c += in_block(q);
+                        if (BPT > 1) {
+                            c += in_block(q);
+                        } else { // the block's count is its lane's: count from q's side
+                            bool up;
+                            const uint32_t hs = half_count(q, &up);
+                            c += up ? tb - hs : hs;
+                        }
                         acc_local += (e & 2) ? -(int64_t)c : (int64_t)c;
                     }
                 }
