@@ -1,8 +1,10 @@
-"""Autotuner for alpha = y / icbrt(x), the one knob that moves work between
-the sieve (which shrinks as alpha grows: z = x / y) and the easy leaves (which
-grow).  For each half decade of x it times pi(x) at every candidate alpha on
-this GPU (tables cached, median of repeats) and writes the winners to
-csrc/pc_alpha_table.h, the table the library reads when alpha = 0.
+"""Autotuner for alpha = y / icbrt(x), the knob that moves work between the
+sieve (which shrinks as alpha grows: z = x / y) and the easy leaves (which
+grow), and for the sieve's shape (LDS segment size and workgroup size).  For
+each half decade of x it times pi(x) at every candidate alpha on this GPU
+(tables cached, median of repeats, default shape), then every shape at the
+best alpha, and writes the winners to csrc/pc_alpha_table.h, the table the
+library reads when alpha = 0 (alpha) and when the caller names no shape.
 
     python -m paper_1503_01839_amd.autotune            # tune, write the header
     python -m paper_1503_01839_amd.autotune --dry-run  # tune, print only
@@ -17,6 +19,7 @@ import statistics
 HERE = os.path.dirname(os.path.abspath(__file__))
 HEADER = os.path.join(HERE, "csrc", "pc_alpha_table.h")
 ALPHAS = [1, 1.5, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48]
+SHAPES = [(32, 512), (32, 256), (64, 512), (64, 1024)]  # (segment KiB, workgroup threads)
 
 
 def candidates(log10x: float) -> list[float]:
@@ -26,28 +29,39 @@ def candidates(log10x: float) -> list[float]:
     return [a for a in ALPHAS if a >= lo]
 
 
-def tune(lo: float = 7.0, hi: float = 19.0, reps: int = 3, log=print) -> list[tuple[float, float, float]]:
+def tune(lo: float = 7.0, hi: float = 19.0, reps: int = 3, log=print):
     import paper_1503_01839_amd as pc
     table = []
     d = lo
     while d <= hi + 1e-9:
         x = int(10 ** d)
+        n = reps if d < 17 else 2
+
+        def time(a, seg, wg):
+            kw = dict(alpha=a, segment_kib=seg, wg_size=wg)
+            pc.pi_count_ex(x, **kw)  # tables sized for this alpha
+            return statistics.median(pc.pi_count_ex(x, **kw).ms_total for _ in range(n))
         best = None
         for a in candidates(d):
-            pc.pi_count_ex(x, alpha=a)  # tables sized for this alpha
-            ts = [pc.pi_count_ex(x, alpha=a).ms_total for _ in range(reps if d < 17 else 2)]
-            t = statistics.median(ts)
+            t = time(a, *SHAPES[0])
+            log(f"  log10 x = {d:4.1f} alpha {a:5.1f} {SHAPES[0]}: {t:9.2f} ms", flush=True)
             if best is None or t < best[1]:
-                best = (a, t)
-        table.append((d, best[0], best[1]))
-        log(f"log10 x = {d:4.1f}: alpha {best[0]:5.1f}  {best[1]:9.2f} ms", flush=True)
+                best = (a, t, SHAPES[0])
+        for shape in SHAPES[1:]:
+            t = time(best[0], *shape)
+            log(f"  log10 x = {d:4.1f} alpha {best[0]:5.1f} {shape}: {t:9.2f} ms", flush=True)
+            if t < best[1]:
+                best = (best[0], t, shape)
+        table.append((d, best[0], best[1], best[2]))
+        log(f"log10 x = {d:4.1f}: alpha {best[0]:5.1f} segment {best[2][0]} KiB "
+            f"workgroup {best[2][1]}  {best[1]:9.2f} ms", flush=True)
         d += 0.5
     return table
 
 
 def header_text(table) -> str:
-    rows = "\n".join(f"    {{{d:.1f}, {a:g}}}, // {t:.2f} ms" for d, a, t in table)
-    return f"""// pc_alpha_table.h -- alpha = y / icbrt(x) per half decade of x, written by
+    rows = "\n".join(f"    {{{d:.1f}, {a:g}, {sh[0]}, {sh[1]}}}, // {t:.2f} ms" for d, a, t, sh in table)
+    return f"""// pc_alpha_table.h -- alpha = y / icbrt(x) and the sieve shape per half decade of x, written by
 // paper_1503_01839_amd/autotune.py from pi(x) timings on MI355X; the entry
 // whose log10 x is nearest is used.  Regenerate with the tuner, do not edit.
 #pragma once
@@ -55,6 +69,8 @@ def header_text(table) -> str:
 struct pc_alpha_entry {{
     double log10x;
     double alpha;
+    unsigned seg_kib; // LDS segment, KiB
+    unsigned wg;      // workgroup threads
 }};
 
 static const pc_alpha_entry kAlphaTable[] = {{

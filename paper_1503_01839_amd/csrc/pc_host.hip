@@ -304,10 +304,11 @@ pc_i128 to_abi(pc_s128 v)
     return r;
 }
 
-// alpha for x from the tuning table (pc_alpha_table.h): the entry nearest in
+// The tuning table's entry for x (pc_alpha_table.h): the one nearest in
 // log10 x.  alpha only moves work between the sieve (falls as 1/alpha) and
-// the easy leaves (rise); it never changes a result.
-double default_alpha(uint64_t x)
+// the easy leaves (rise), the segment and workgroup shape only how the sieve
+// runs; neither ever changes a result.
+const pc_alpha_entry &tuned_entry(uint64_t x)
 {
     const double lx = std::log10((double)x);
     const size_t n = sizeof kAlphaTable / sizeof kAlphaTable[0];
@@ -315,8 +316,10 @@ double default_alpha(uint64_t x)
     for (size_t i = 1; i < n; i++)
         if (std::fabs(kAlphaTable[i].log10x - lx) < std::fabs(kAlphaTable[best].log10x - lx))
             best = i;
-    return kAlphaTable[best].alpha;
+    return kAlphaTable[best];
 }
+
+double default_alpha(uint64_t x) { return tuned_entry(x).alpha; }
 
 uint64_t choose_y(uint64_t x, double alpha)
 {
@@ -340,6 +343,7 @@ struct Knobs {
     uint32_t hot_log2 = 15;          // small one-wavefront segments below hot_span * y
     uint32_t hot_wg = 64;
     uint64_t hot_span = 0;           // 0 = no small segments (the measured best at every size)
+    bool shape_set = false;          // segment and workgroup named by the caller, not the table
 };
 
 Knobs knobs_from(const pc_config *cfg)
@@ -347,6 +351,7 @@ Knobs knobs_from(const pc_config *cfg)
     Knobs k;
     if (!cfg)
         return k;
+    k.shape_set = cfg->segment_kib != 0 || cfg->wg_size != 0;
     switch (cfg->segment_kib) {
     case 0:
         break;
@@ -915,8 +920,14 @@ void pi_one(uint64_t x, const Knobs &K, double alpha, pc_result *res, uint64_t *
     if (alpha == 0)
         alpha = default_alpha(x);
     const uint64_t y = choose_y(x, alpha);
+    Knobs Kx = K;
+    if (!K.shape_set) { // the tuned segment and workgroup for this size
+        const pc_alpha_entry &e = tuned_entry(x);
+        Kx.seg_log2 = e.seg_kib == 64 ? 19 : 18;
+        Kx.wg = e.wg;
+    }
     pc_result r;
-    run_query(x, y, K, &r);
+    run_query(x, y, Kx, &r);
     *pi = r.pi;
     if (res)
         *res = r;
