@@ -453,9 +453,9 @@ double ms_since(clk::time_point t0)
     return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
 
-// Tiles of the window [s0, s0 + rows): segments below plan_end whose hard-leaf
-// work exceeds the target are cut into column ranges of about equal work
-// (these go first, heaviest first); every other segment is one tile.
+// Tiles of the window [s0, s0 + rows): segments below plan_end whose estimated
+// hard-leaf work exceeds the target are cut into column ranges of about equal
+// work (these go first, heaviest first); every other segment is one tile.
 void plan_tiles(const pc_tables &T, const pc_query &Q, const Knobs &K, uint32_t log2s,
                 uint64_t lo_base, uint64_t seg_base, uint64_t s0, uint64_t rows, uint64_t plan_end,
                 std::vector<pc_tile> &tiles)
@@ -473,11 +473,21 @@ void plan_tiles(const pc_tables &T, const pc_query &Q, const Knobs &K, uint32_t 
         hipck(hipMemcpyAsync(work.data(), B.work.p, np * 8, hipMemcpyDeviceToHost, g_stream),
               "D2H");
         hipck(hipStreamSynchronize(g_stream), "sync");
+        // The target: K.tile_leaves, or less when the whole window holds little
+        // leaf work, so that no tile outlasts the rest of the launch (about
+        // 768 workgroups run at once; a tile should carry at most twice its
+        // share of the estimated work).
+        uint64_t total = 0;
+        for (uint64_t i = 0; i < np; i++)
+            total += work[i];
+        const uint64_t target =
+            std::clamp<uint64_t>(total / 384, std::min<uint64_t>(1u << 16, K.tile_leaves),
+                                 K.tile_leaves);
         std::vector<uint4> hot;
         uint32_t off = 0;
         for (uint64_t i = 0; i < np; i++)
-            if (work[i] > K.tile_leaves) {
-                uint64_t k = (work[i] + K.tile_leaves - 1) / K.tile_leaves;
+            if (work[i] > target) {
+                uint64_t k = (work[i] + target - 1) / target;
                 k = std::min<uint64_t>(k, std::min<uint64_t>(4096, Q.nb));
                 if (k < 2)
                     continue;
