@@ -132,6 +132,43 @@ pc_status pc_pi_count_batch(const uint64_t *xs, size_t n, uint64_t *pi_out);
 pc_status pc_pi_count_batch_ex(const uint64_t *xs, size_t n, const pc_config *cfg,
                                uint64_t *pi_out);
 
+/* The batch in caller memory, for callers that own device memory and
+ * streams (a framework's allocator and current stream).
+ *
+ * pc_workspace_bytes: device bytes of workspace that
+ * pc_pi_count_batch_async needs for these n queries (host array xs).  The
+ * figure covers each round's uploaded arrays (query scalars, block tables
+ * and sieve tiles: 16 bytes per segment of every query, a few hundred bytes
+ * per query), one round arena (per-segment counts and weights of a round's
+ * queries, 8 bytes per segment per sieving prime, bounded by the 6 GiB round
+ * budget, plus each query's per-prime arrays) and 16 bytes per query answered
+ * on the host.  n = 0 gives 0.  Returns SIZE_MAX on error (xs null with
+ * n > 0, a device table that cannot be built); pc_last_error() says why.
+ * Builds the shared device tables these queries need, as the other calls do.
+ *
+ * pc_pi_count_batch_async: d_out[i] = pi(d_xs[i]) for i < n, every step on
+ * hip_stream (a hipStream_t; NULL is the null stream).  d_xs, d_out and d_ws
+ * are device pointers owned by the caller: d_xs of n elements, d_out of n
+ * elements, d_ws of ws_bytes >= pc_workspace_bytes(xs, n) bytes (256-byte
+ * aligned, as hipMalloc returns).  The call first waits for the stream's
+ * earlier work and reads d_xs back (it plans on the host), so d_xs may be
+ * reused once it returns.  Queries whose sieve counts exceed the round
+ * budget (x above a few times 10^17 at the tuned alpha) are computed during the call
+ * on the library's own stream; everything else is queued on hip_stream and
+ * the call returns without waiting for it: d_out is complete once the stream
+ * reaches that point, and d_out and d_ws must stay allocated until then.
+ * The call queues no allocation and no memset, but it synchronises the
+ * stream, so it cannot be captured into a HIP graph.  Too small a workspace
+ * gives PC_ENOMEM before anything is queued or written.  d_out[i] is all
+ * ones if the device found an internal inconsistency for that query (pi(x) <
+ * 2^63 for every x < 2^64, so no count has that value).  n = 0 is valid and
+ * touches nothing; d_xs or d_out null with n > 0 gives PC_EINVAL.  The shared
+ * tables stay valid for queued batches: a later call that has to grow them
+ * first waits for every queued batch. */
+size_t pc_workspace_bytes(const uint64_t *xs, size_t n);
+pc_status pc_pi_count_batch_async(const uint64_t *d_xs, size_t n, uint64_t *d_out, void *d_ws,
+                                  size_t ws_bytes, void *hip_stream);
+
 /* Serving: an open-loop stream of pi(x) requests replayed in real time, with
  * continuous batching.  Request i (x = xs[i]) arrives arrival_s[i] seconds
  * after the call starts (non-decreasing, finite, >= 0).  Arrived requests wait

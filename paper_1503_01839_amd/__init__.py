@@ -23,7 +23,8 @@ FLAG_NO_GRAPH = 16
 FLAG_BATCH_SEQUENTIAL = 32
 
 EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
-           "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_serve", "pc_wheel_c",
+           "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_workspace_bytes",
+           "pc_pi_count_batch_async", "pc_serve", "pc_wheel_c",
            "pc_status_str", "pc_last_error", "pc_shutdown"]
 
 
@@ -128,8 +129,13 @@ def lib():
         L.pc_pi_count_batch_ex.argtypes = [P(u64), C.c_size_t, P(Config), P(u64)]
         L.pc_serve.argtypes = [P(u64), P(C.c_double), C.c_size_t, P(ServeConfig), P(u64),
                                P(C.c_double), P(ServeStats)]
+        L.pc_workspace_bytes.argtypes = [P(u64), C.c_size_t]
+        L.pc_workspace_bytes.restype = C.c_size_t
+        L.pc_pi_count_batch_async.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                              C.c_size_t, C.c_void_p]
         for f in ("pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
-                  "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_serve"):
+                  "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_pi_count_batch_async",
+                  "pc_serve"):
             getattr(L, f).restype = C.c_int
         L.pc_wheel_c.restype = C.c_int
         L.pc_status_str.argtypes = [C.c_int]
@@ -205,6 +211,40 @@ def pi_count_batch(xs, **cfg) -> list[int]:
     else:
         _check(lib().pc_pi_count_batch(arr, n, out))
     return list(out[:n])
+
+
+SIZE_MAX = 2**64 - 1
+
+
+def workspace_bytes(xs) -> int:
+    """Device bytes of workspace pi_count_batch_async needs for these x values."""
+    xs = list(xs)
+    n = len(xs)
+    arr = (C.c_uint64 * max(n, 1))(*xs)
+    v = lib().pc_workspace_bytes(arr, n)
+    if v == SIZE_MAX:
+        raise PicountError(-1, lib().pc_last_error().decode())
+    return v
+
+
+def _addr(v) -> int:
+    """A device address: a tensor's data_ptr(), a stream's handle, or an int."""
+    if v is None:
+        return 0
+    for attr in ("data_ptr", "cuda_stream"):
+        a = getattr(v, attr, None)
+        if a is not None:
+            return a() if callable(a) else a
+    return int(v)
+
+
+def pi_count_batch_async(d_xs, n: int, d_out, d_ws, ws_bytes: int, stream=None) -> None:
+    """out[i] = pi(xs[i]) in caller device memory, queued on `stream`.  Each
+    pointer argument is a device address, or a tensor (its data_ptr()); the
+    stream is a handle or a torch stream (its cuda_stream); None is the null
+    stream."""
+    _check(lib().pc_pi_count_batch_async(_addr(d_xs), n, _addr(d_out), _addr(d_ws), ws_bytes,
+                                         _addr(stream)))
 
 
 def serve(xs, arrivals, max_inflight=0, max_round=0, mem_budget=0, alpha=0.0, flags=0):

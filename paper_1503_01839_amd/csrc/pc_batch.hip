@@ -157,6 +157,25 @@ __global__ void k_combine_b(const pc_query *Qs, uint32_t nq, pc_final *out)
         pc_combine_one(*Qs[q].sums, Qs[q], Qs[q].kx, &out[q]);
 }
 
+// A round's results into a caller's array: out[pos[q]] = pi of query q, or all
+// ones (pi(x) < 2^63 for every x < 2^64, so never a count) when a quotient
+// fell outside its segment in the round or the sum left [0, 2^64).
+__global__ void k_batch_out(const pc_final *fin, const uint64_t *pos, uint32_t nq,
+                            const int32_t *err, uint64_t *out)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq)
+        out[pos[q]] = (*err == 0 && fin[q].ok) ? fin[q].pi : ~0ull;
+}
+
+// Results known on the host, as (position, value) pairs, into out.
+__global__ void k_scatter_u64(const ulonglong2 *kv, uint64_t n, uint64_t *out)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        out[kv[i].x] = kv[i].y;
+}
+
 hipError_t pc_launch_batch_setup(const pc_tables &T, const pc_query *Qs, const uint32_t *bq_xb,
                                  const uint32_t *bf_xb, uint32_t nb_xb, const uint32_t *bq_s1,
                                  const uint32_t *bf_s1, uint32_t nb_s1, uint32_t nq,
@@ -181,5 +200,23 @@ hipError_t pc_launch_batch_finish(const pc_query *Qs, const uint32_t *bq, const 
 {
     k_scan_rows_b<<<nblocks, BT, 0, s>>>(Qs, pc_blk{bq, bf});
     k_combine_b<<<(nq + 63) / 64, 64, 0, s>>>(Qs, nq, out);
+    return hipGetLastError();
+}
+
+hipError_t pc_launch_batch_out(const pc_final *fin, const uint64_t *pos, uint32_t nq,
+                               const int32_t *err, uint64_t *out, hipStream_t s)
+{
+    if (nq == 0)
+        return hipSuccess;
+    k_batch_out<<<(nq + 255) / 256, 256, 0, s>>>(fin, pos, nq, err, out);
+    return hipGetLastError();
+}
+
+hipError_t pc_launch_scatter_u64(const ulonglong2 *kv, uint64_t n, uint64_t *out, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    const uint64_t nb = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
+    k_scatter_u64<<<(uint32_t)nb, 256, 0, s>>>(kv, n, out);
     return hipGetLastError();
 }

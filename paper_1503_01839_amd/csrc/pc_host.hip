@@ -55,10 +55,24 @@ std::atomic<size_t> g_dev_bytes{0}, g_dev_peak{0}; // device bytes held, and the
 hipStream_t g_stream = nullptr;  // the library stream
 hipStream_t g_stream2 = nullptr; // easy leaves, concurrent with the sieve (same priority)
 
+// Completion events of caller-memory batches queued on callers' streams
+// (they read the shared tables), and spare events to record the next ones.
+std::vector<hipEvent_t> g_async_live, g_async_spare;
+
+void async_wait_all()
+{
+    for (hipEvent_t e : g_async_live) {
+        (void)hipEventSynchronize(e);
+        g_async_spare.push_back(e);
+    }
+    g_async_live.clear();
+}
+
 void dfree(DevBuf &b)
 {
     if (b.p) {
-        if (g_stream2) // kernels queued earlier may still read the buffer
+        async_wait_all(); // kernels queued earlier may still read the buffer
+        if (g_stream2)
             (void)hipStreamSynchronize(g_stream2);
         if (g_stream)
             (void)hipStreamSynchronize(g_stream);
@@ -962,6 +976,29 @@ struct BatchQuery {
 constexpr uint32_t kBatchLog2S = 18; // 32 KiB segments
 constexpr uint32_t kBatchWG = 512;
 
+size_t r256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// A query's chunk of a round arena: X_b, Ub, three easy arrays, e_clu,
+// counts, weights, each rounded up to 256 bytes exactly as round_queries
+// takes them.
+size_t query_chunk(const BatchQuery &b)
+{
+    const size_t na = b.a + 2, cells = b.nseg * b.ncol;
+    return r256(na * 8) + 2 * r256(na * 16) + 3 * r256(na * 8) + 2 * r256(cells * 4);
+}
+
+// What the host builds for one round: the arena layout (sums, easy totals,
+// results, then each query's chunk), the sieve tiles, and the block tables of
+// the flat kernels (the query of each block and each query's first block).
+struct RoundPlan {
+    size_t arena = 0, o_sums = 0, o_et = 0, o_fin = 0;
+    std::vector<size_t> o_q;
+    std::vector<pc_tile> tiles;
+    std::vector<uint32_t> blk;
+    size_t t_xb = 0, t_s1 = 0, t_ez = 0, t_sc = 0;
+    uint32_t nb_xb = 0, nb_s1 = 0, nb_ez = 0, nb_sc = 0;
+};
+
 // Everything one batch round keeps while it is on the device: its stream
 // (null: the library stream), buffers, pinned results, and the host arrays
 // its copies read from.
@@ -976,8 +1013,7 @@ struct BatchSlot {
     hipGraphExec_t exec = nullptr;
     std::vector<BatchQuery> R;
     std::vector<pc_query> Qv;
-    std::vector<pc_tile> tiles_h;
-    std::vector<uint32_t> blk_h;
+    RoundPlan plan;
     uint64_t bytes = 0;
     bool busy = false;
 };
@@ -1028,51 +1064,80 @@ void slot_release(BatchSlot &sl)
     sl = BatchSlot{};
 }
 
-// Queue one round (sl.R) on the slot's stream: set-up, easy leaves, sieve,
-// carries, combination (as a HIP graph unless use_graph is false), then the
-// copies of the results into pinned memory and the slot's completion event.
-void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
+// The round's arena layout, block tables and tiles.
+void plan_round(const std::vector<BatchQuery> &R, RoundPlan &P)
 {
-    const std::vector<BatchQuery> &R = sl.R;
     const uint32_t nq = (uint32_t)R.size();
-    const uint64_t S = 1ull << kBatchLog2S;
-    hipStream_t st = sl.st ? sl.st : g_stream;
-    const pc_tables T = tables_view(kWheelC);
-
-    // arena: sums, easy totals, results, then each query's arrays
-    size_t tot = 0;
+    P.arena = 0;
     auto take = [&](size_t bytes) {
-        const size_t o = tot;
-        tot += (bytes + 255) & ~(size_t)255;
+        const size_t o = P.arena;
+        P.arena += r256(bytes);
         return o;
     };
-    const size_t o_sums = take(nq * sizeof(pc_sums)), o_et = take(nq * 8),
-                 o_fin = take(nq * sizeof(pc_final));
-    // each query's chunk: X_b, Ub, three easy arrays, counts, weights, each
-    // rounded up to 256 bytes exactly as carve() below takes them
-    auto r256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    auto chunk = [&](const BatchQuery &b) {
-        const size_t na = b.a + 2, cells = b.nseg * b.ncol;
-        return r256(na * 8) + 2 * r256(na * 16) + 3 * r256(na * 8) + 2 * r256(cells * 4);
-    };
-    std::vector<size_t> o_q(nq);
+    P.o_sums = take(nq * sizeof(pc_sums));
+    P.o_et = take(nq * 8);
+    P.o_fin = take(nq * sizeof(pc_final));
+    P.o_q.resize(nq);
     for (uint32_t i = 0; i < nq; i++)
-        o_q[i] = take(chunk(R[i]));
-    slot_ensure(sl, sl.arena, tot, "batch arena");
-    char *base = static_cast<char *>(sl.arena.p);
-    pc_sums *sums = reinterpret_cast<pc_sums *>(base + o_sums);
-    pc_final *fin = reinterpret_cast<pc_final *>(base + o_fin);
+        P.o_q[i] = take(query_chunk(R[i]));
 
-    sl.Qv.assign(nq, pc_query{});
+    P.blk.clear();
+    auto table = [&](auto nblocks_of, uint32_t *nblocks) {
+        const size_t at = P.blk.size();
+        std::vector<uint32_t> first(nq + 1);
+        uint32_t nbk = 0;
+        for (uint32_t i = 0; i < nq; i++) {
+            first[i] = nbk;
+            nbk += std::max<uint32_t>(1, nblocks_of(R[i]));
+        }
+        first[nq] = nbk;
+        for (uint32_t i = 0; i < nq; i++)
+            for (uint32_t k = first[i]; k < first[i + 1]; k++)
+                P.blk.push_back(i);
+        P.blk.insert(P.blk.end(), first.begin(), first.end());
+        *nblocks = nbk;
+        return at; // q at [at, at + nbk), first at [at + nbk, at + nbk + nq + 1)
+    };
+    P.t_xb = table(
+        [](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, (b.a + 2 + 255) / 256); },
+        &P.nb_xb);
+    P.t_s1 = table(
+        [](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, b.y / 4096 + 1); },
+        &P.nb_s1);
+    P.t_ez = table(
+        [](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(1024, b.y / 4096 + 1); },
+        &P.nb_ez);
+    P.t_sc = table([](const BatchQuery &b) { return (b.ncol + 255) / 256; }, &P.nb_sc);
+
+    // sieve tiles, largest queries first, each query's low (leaf-dense) segments first
+    std::vector<uint32_t> order(nq);
+    for (uint32_t i = 0; i < nq; i++)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t u, uint32_t v) { return R[u].bytes() > R[v].bytes(); });
+    P.tiles.clear();
+    for (uint32_t i : order)
+        for (uint64_t sg = 0; sg < R[i].nseg; sg++)
+            P.tiles.push_back(pc_tile{(uint32_t)sg, 0, R[i].ncol, i});
+}
+
+// The round's per-query scalars, with their arrays carved out of the arena at base.
+void round_queries(const std::vector<BatchQuery> &R, const RoundPlan &P, char *base,
+                   const pc_tables &T, std::vector<pc_query> &Qv)
+{
+    const uint32_t nq = (uint32_t)R.size();
+    const uint64_t S = 1ull << kBatchLog2S;
+    pc_sums *sums = reinterpret_cast<pc_sums *>(base + P.o_sums);
+    Qv.assign(nq, pc_query{});
     for (uint32_t i = 0; i < nq; i++) {
         const BatchQuery &b = R[i];
-        pc_query &Q = sl.Qv[i];
-        size_t o = o_q[i];
-        const size_t o_end = o_q[i] + chunk(b);
+        pc_query &Q = Qv[i];
+        size_t o = P.o_q[i];
+        const size_t o_end = P.o_q[i] + query_chunk(b);
         auto carve = [&](size_t bytes) {
             char *p = base + o;
             o += r256(bytes);
-            if (o > o_end) // the chunk sizes above and these carves must agree
+            if (o > o_end) // query_chunk and these carves must agree
                 fail(PC_EINTERNAL, "batch arena layout");
             return p;
         };
@@ -1100,56 +1165,61 @@ void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
         Q.e_clu = reinterpret_cast<uint4 *>(carve(na * 16));
         Q.cnt = reinterpret_cast<uint32_t *>(carve(b.nseg * b.ncol * 4));
         Q.wgt = reinterpret_cast<int32_t *>(carve(b.nseg * b.ncol * 4));
-        Q.e_total = reinterpret_cast<uint64_t *>(base + o_et) + i;
+        Q.e_total = reinterpret_cast<uint64_t *>(base + P.o_et) + i;
         Q.sums = sums + i;
         Q.carry = nullptr;
         Q.nseg = b.nseg;
         Q.sieve_end = b.nseg * 2 * S;
     }
+}
 
-    // block tables: the query of each block and each query's first block
-    sl.blk_h.clear();
-    auto table = [&](auto nblocks_of, uint32_t *nblocks) {
-        const size_t at = sl.blk_h.size();
-        std::vector<uint32_t> first(nq + 1);
-        uint32_t nbk = 0;
-        for (uint32_t i = 0; i < nq; i++) {
-            first[i] = nbk;
-            nbk += std::max<uint32_t>(1, nblocks_of(R[i]));
-        }
-        first[nq] = nbk;
-        for (uint32_t i = 0; i < nq; i++)
-            for (uint32_t k = first[i]; k < first[i + 1]; k++)
-                sl.blk_h.push_back(i);
-        sl.blk_h.insert(sl.blk_h.end(), first.begin(), first.end());
-        *nblocks = nbk;
-        return at; // q at [at, at + nbk), first at [at + nbk, at + nbk + nq + 1)
-    };
-    uint32_t nb_xb, nb_s1, nb_ez, nb_sc;
-    const size_t t_xb = table(
-        [](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, (b.a + 2 + 255) / 256); },
-        &nb_xb);
-    const size_t t_s1 = table(
-        [](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(64, b.y / 4096 + 1); }, &nb_s1);
-    const size_t t_ez = table(
-        [](const BatchQuery &b) { return (uint32_t)std::min<uint64_t>(1024, b.y / 4096 + 1); },
-        &nb_ez);
-    const size_t t_sc = table([](const BatchQuery &b) { return (b.ncol + 255) / 256; }, &nb_sc);
+// The round's kernels on st: clears, set-up, easy leaves, sieve, carries and
+// combination into the pc_final array of the arena.  qs, tiles and bk hold
+// the uploaded Qv, P.tiles and P.blk.
+void round_launches(const RoundPlan &P, uint32_t nq, char *base, const pc_tables &T,
+                    const pc_query *qs, const pc_tile *tiles, const uint32_t *bk, int32_t *err,
+                    const Knobs &K, hipStream_t st)
+{
+    pc_sums *sums = reinterpret_cast<pc_sums *>(base + P.o_sums);
+    pc_final *fin = reinterpret_cast<pc_final *>(base + P.o_fin);
+    hipck(pc_launch_fill_u64(reinterpret_cast<uint64_t *>(err), 1, 0, st), "fill");
+    hipck(pc_launch_fill_u64(reinterpret_cast<uint64_t *>(sums), nq * sizeof(pc_sums) / 8, 0, st),
+          "fill");
+    hipck(pc_launch_batch_setup(T, qs, bk + P.t_xb, bk + P.t_xb + P.nb_xb, P.nb_xb, bk + P.t_s1,
+                                bk + P.t_s1 + P.nb_s1, P.nb_s1, nq, st),
+          "batch set-up");
+    hipck(pc_launch_batch_easy(T, qs, bk + P.t_ez, bk + P.t_ez + P.nb_ez, P.nb_ez, st),
+          "batch easy");
+    pc_sieve_args A{};
+    A.T = T;
+    A.Qs = qs;
+    A.tiles = tiles;
+    A.ntiles = (uint32_t)P.tiles.size();
+    A.err = err;
+    hipck(pc_launch_sieve(A, kBatchLog2S, kBatchWG, PC_MODE_TALLY | (K.batch ? 0 : 0x100), st),
+          "batch sieve");
+    hipck(pc_launch_batch_finish(qs, bk + P.t_sc, bk + P.t_sc + P.nb_sc, P.nb_sc, nq, fin, st),
+          "batch finish");
+}
 
-    // sieve tiles, largest queries first, each query's low (leaf-dense) segments first
-    std::vector<uint32_t> order(nq);
-    for (uint32_t i = 0; i < nq; i++)
-        order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t u, uint32_t v) { return R[u].bytes() > R[v].bytes(); });
-    sl.tiles_h.clear();
-    for (uint32_t i : order)
-        for (uint64_t sg = 0; sg < R[i].nseg; sg++)
-            sl.tiles_h.push_back(pc_tile{(uint32_t)sg, 0, R[i].ncol, i});
+// Queue one round (sl.R) on the slot's stream: its kernels (as a HIP graph
+// unless use_graph is false), then the copies of the results into pinned
+// memory and the slot's completion event.
+void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
+{
+    const std::vector<BatchQuery> &R = sl.R;
+    const uint32_t nq = (uint32_t)R.size();
+    hipStream_t st = sl.st ? sl.st : g_stream;
+    const pc_tables T = tables_view(kWheelC);
+    RoundPlan &P = sl.plan;
+    plan_round(R, P);
+    slot_ensure(sl, sl.arena, P.arena, "batch arena");
+    char *base = static_cast<char *>(sl.arena.p);
+    round_queries(R, P, base, T, sl.Qv);
 
     slot_ensure(sl, sl.qs, nq * sizeof(pc_query), "batch queries");
-    slot_ensure(sl, sl.tiles, sl.tiles_h.size() * sizeof(pc_tile), "batch tiles");
-    slot_ensure(sl, sl.blk, sl.blk_h.size() * 4, "batch blocks");
+    slot_ensure(sl, sl.tiles, P.tiles.size() * sizeof(pc_tile), "batch tiles");
+    slot_ensure(sl, sl.blk, P.blk.size() * 4, "batch blocks");
     slot_ensure(sl, sl.err, 8, "error flag");
     if (sl.h_fin_cap < nq) {
         if (sl.h_fin)
@@ -1164,33 +1234,14 @@ void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
         hipck(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "hipEventCreate");
     hipck(hipMemcpyAsync(sl.qs.p, sl.Qv.data(), nq * sizeof(pc_query), hipMemcpyHostToDevice, st),
           "H2D");
-    hipck(hipMemcpyAsync(sl.tiles.p, sl.tiles_h.data(), sl.tiles_h.size() * sizeof(pc_tile),
+    hipck(hipMemcpyAsync(sl.tiles.p, P.tiles.data(), P.tiles.size() * sizeof(pc_tile),
                          hipMemcpyHostToDevice, st),
           "H2D");
-    hipck(hipMemcpyAsync(sl.blk.p, sl.blk_h.data(), sl.blk_h.size() * 4, hipMemcpyHostToDevice, st),
+    hipck(hipMemcpyAsync(sl.blk.p, P.blk.data(), P.blk.size() * 4, hipMemcpyHostToDevice, st),
           "H2D");
-    const pc_query *qs = ptr<pc_query>(sl.qs);
-    const uint32_t *bk = ptr<uint32_t>(sl.blk);
-    const uint32_t ntiles = (uint32_t)sl.tiles_h.size();
-
     auto launches = [&]() {
-        hipck(pc_launch_fill_u64(ptr<uint64_t>(sl.err), 1, 0, st), "fill");
-        hipck(pc_launch_fill_u64(reinterpret_cast<uint64_t *>(sums), nq * sizeof(pc_sums) / 8, 0, st),
-              "fill");
-        hipck(pc_launch_batch_setup(T, qs, bk + t_xb, bk + t_xb + nb_xb, nb_xb, bk + t_s1,
-                                    bk + t_s1 + nb_s1, nb_s1, nq, st),
-              "batch set-up");
-        hipck(pc_launch_batch_easy(T, qs, bk + t_ez, bk + t_ez + nb_ez, nb_ez, st), "batch easy");
-        pc_sieve_args A{};
-        A.T = T;
-        A.Qs = qs;
-        A.tiles = ptr<pc_tile>(sl.tiles);
-        A.ntiles = ntiles;
-        A.err = ptr<int32_t>(sl.err);
-        hipck(pc_launch_sieve(A, kBatchLog2S, kBatchWG, PC_MODE_TALLY | (K.batch ? 0 : 0x100), st),
-              "batch sieve");
-        hipck(pc_launch_batch_finish(qs, bk + t_sc, bk + t_sc + nb_sc, nb_sc, nq, fin, st),
-              "batch finish");
+        round_launches(P, nq, base, T, ptr<pc_query>(sl.qs), ptr<pc_tile>(sl.tiles),
+                       ptr<uint32_t>(sl.blk), ptr<int32_t>(sl.err), K, st);
     };
     if (use_graph) {
         hipck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
@@ -1209,6 +1260,7 @@ void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
     } else {
         launches();
     }
+    const pc_final *fin = reinterpret_cast<const pc_final *>(base + P.o_fin);
     hipck(hipMemcpyAsync(sl.h_fin, fin, nq * sizeof(pc_final), hipMemcpyDeviceToHost, st), "D2H");
     hipck(hipMemcpyAsync(sl.h_err, sl.err.p, 4, hipMemcpyDeviceToHost, st), "D2H");
     hipck(hipEventRecord(sl.done, st), "hipEventRecord");
@@ -1322,6 +1374,171 @@ void run_batch(const uint64_t *xs, size_t n, const Knobs &K, double alpha, bool 
         sl.bytes += b.bytes();
     }
     flush();
+}
+
+// ---------------------------------------------------------------------------
+// Batches in caller memory.  The caller's workspace holds, in this order, each
+// round's uploaded arrays (query scalars, tiles, block tables, output
+// positions), the results known on the host ((position, value) pairs: x below
+// the sieve threshold, and queries too large for a round, computed windowed
+// during the call), the error flag, and one round arena that the rounds reuse
+// one after another in stream order.
+// ---------------------------------------------------------------------------
+struct AsyncRound {
+    std::vector<BatchQuery> R;
+    RoundPlan P;
+    size_t o_qs = 0, o_tiles = 0, o_blk = 0, o_pos = 0;
+};
+
+struct AsyncPlan {
+    std::vector<uint64_t> known;       // results of x < kSmallX (by position)
+    std::vector<size_t> known_idx;     // positions answered on the host
+    std::vector<BatchQuery> windowed;  // computed during the call, windowed
+    std::vector<AsyncRound> rounds;
+    size_t o_kv = 0, nkv = 0, o_err = 0, o_arena = 0, total = 0;
+};
+
+void async_plan(const uint64_t *xs, size_t n, const Knobs &K, AsyncPlan &A)
+{
+    A.known.assign(n, 0);
+    const std::vector<BatchQuery> big = plan_queries(xs, n, 0.0, A.known.data());
+    for (size_t i = 0; i < n; i++)
+        if (xs[i] < kSmallX)
+            A.known_idx.push_back(i);
+    // the rounds of the synchronous path: in input order within the carry budget
+    std::vector<BatchQuery> cur;
+    uint64_t bytes = 0;
+    auto flush = [&]() {
+        if (cur.empty())
+            return;
+        A.rounds.emplace_back();
+        A.rounds.back().R.swap(cur);
+        bytes = 0;
+    };
+    for (const BatchQuery &b : big) {
+        if (b.bytes() > K.carry_budget) {
+            A.windowed.push_back(b);
+            continue;
+        }
+        if (bytes + b.bytes() > K.carry_budget || cur.size() >= 65536)
+            flush();
+        cur.push_back(b);
+        bytes += b.bytes();
+    }
+    flush();
+    A.nkv = A.known_idx.size() + A.windowed.size();
+    size_t tot = 0, arena = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = tot;
+        tot += r256(bytes);
+        return o;
+    };
+    for (AsyncRound &r : A.rounds) {
+        plan_round(r.R, r.P);
+        r.o_qs = take(r.R.size() * sizeof(pc_query));
+        r.o_tiles = take(r.P.tiles.size() * sizeof(pc_tile));
+        r.o_blk = take(r.P.blk.size() * 4);
+        r.o_pos = take(r.R.size() * 8);
+        arena = std::max(arena, r.P.arena);
+    }
+    A.o_kv = take(A.nkv * 16);
+    A.o_err = take(8);
+    A.o_arena = take(arena);
+    A.total = A.rounds.empty() ? A.o_err : tot; // no round: no flag, no arena
+}
+
+uint64_t *g_async_host = nullptr; // pinned staging for xs and the upload
+size_t g_async_host_cap = 0;
+
+void *async_staging(size_t bytes)
+{
+    if (g_async_host_cap < bytes) {
+        if (g_async_host)
+            (void)hipHostFree(g_async_host);
+        g_async_host = nullptr;
+        g_async_host_cap = 0;
+        const size_t cap = std::max<size_t>(bytes, 1 << 16);
+        hipck(hipHostMalloc((void **)&g_async_host, cap), "hipHostMalloc");
+        g_async_host_cap = cap;
+    }
+    return g_async_host;
+}
+
+void run_batch_async(const uint64_t *d_xs, size_t n, uint64_t *d_out, void *d_ws, size_t ws_bytes,
+                     hipStream_t st)
+{
+    init_stream();
+    const Knobs K;
+    // the queries, once the stream's earlier work has produced them
+    uint64_t *hx = static_cast<uint64_t *>(async_staging(n * 8));
+    hipck(hipMemcpyAsync(hx, d_xs, n * 8, hipMemcpyDeviceToHost, st), "D2H");
+    hipck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const std::vector<uint64_t> xs(hx, hx + n);
+    AsyncPlan A;
+    async_plan(xs.data(), n, K, A);
+    if (A.total > ws_bytes || (A.total > 0 && !d_ws))
+        fail(PC_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes; these queries need " +
+                            std::to_string(A.total) + " (pc_workspace_bytes)");
+    std::vector<ulonglong2> kv;
+    kv.reserve(A.nkv);
+    for (size_t i : A.known_idx)
+        kv.push_back(ulonglong2{i, A.known[i]});
+    for (const BatchQuery &b : A.windowed) {
+        pc_result r;
+        run_query(b.x, b.y, K, &r);
+        kv.push_back(ulonglong2{b.idx, r.pi});
+    }
+    char *ws = static_cast<char *>(d_ws);
+    char *arena = ws + A.o_arena;
+    const pc_tables T = tables_view(kWheelC);
+    // one upload of everything before the error flag, then the kernels
+    char *img = static_cast<char *>(async_staging(A.o_err));
+    std::vector<pc_query> Qv;
+    for (const AsyncRound &r : A.rounds) {
+        round_queries(r.R, r.P, arena, T, Qv);
+        memcpy(img + r.o_qs, Qv.data(), Qv.size() * sizeof(pc_query));
+        memcpy(img + r.o_tiles, r.P.tiles.data(), r.P.tiles.size() * sizeof(pc_tile));
+        memcpy(img + r.o_blk, r.P.blk.data(), r.P.blk.size() * 4);
+        uint64_t *pos = reinterpret_cast<uint64_t *>(img + r.o_pos);
+        for (size_t i = 0; i < r.R.size(); i++)
+            pos[i] = r.R[i].idx;
+    }
+    if (!kv.empty())
+        memcpy(img + A.o_kv, kv.data(), kv.size() * 16);
+    hipck(hipMemcpyAsync(ws, img, A.o_err, hipMemcpyHostToDevice, st), "H2D");
+    hipck(hipStreamSynchronize(st), "hipStreamSynchronize"); // the staging is free again
+    hipck(pc_launch_scatter_u64(reinterpret_cast<const ulonglong2 *>(ws + A.o_kv), kv.size(),
+                                d_out, st),
+          "results");
+    int32_t *err = reinterpret_cast<int32_t *>(ws + A.o_err);
+    for (const AsyncRound &r : A.rounds) {
+        const uint32_t nq = (uint32_t)r.R.size();
+        round_launches(r.P, nq, arena, T, reinterpret_cast<const pc_query *>(ws + r.o_qs),
+                       reinterpret_cast<const pc_tile *>(ws + r.o_tiles),
+                       reinterpret_cast<const uint32_t *>(ws + r.o_blk), err, K, st);
+        hipck(pc_launch_batch_out(reinterpret_cast<const pc_final *>(arena + r.P.o_fin),
+                                  reinterpret_cast<const uint64_t *>(ws + r.o_pos), nq, err, d_out,
+                                  st),
+              "results");
+    }
+    hipEvent_t e = nullptr;
+    if (!g_async_spare.empty()) {
+        e = g_async_spare.back();
+        g_async_spare.pop_back();
+    } else {
+        hipck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    }
+    g_async_live.push_back(e);
+    hipck(hipEventRecord(e, st), "hipEventRecord");
+    // forget the batches that have finished
+    for (size_t i = 0; i < g_async_live.size();)
+        if (g_async_live[i] != e && hipEventQuery(g_async_live[i]) == hipSuccess) {
+            g_async_spare.push_back(g_async_live[i]);
+            g_async_live[i] = g_async_live.back();
+            g_async_live.pop_back();
+        } else {
+            i++;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -1655,6 +1872,37 @@ pc_status pc_pi_count_batch(const uint64_t *xs, size_t n, uint64_t *pi_out)
     return pc_pi_count_batch_ex(xs, n, nullptr, pi_out);
 }
 
+size_t pc_workspace_bytes(const uint64_t *xs, size_t n)
+{
+    if (n == 0)
+        return 0;
+    if (!xs) {
+        t_err = "xs is null";
+        return SIZE_MAX;
+    }
+    size_t bytes = SIZE_MAX;
+    const pc_status st = guarded([&] {
+        AsyncPlan A;
+        async_plan(xs, n, Knobs{}, A);
+        bytes = A.total;
+    });
+    return st == PC_OK ? bytes : SIZE_MAX;
+}
+
+pc_status pc_pi_count_batch_async(const uint64_t *d_xs, size_t n, uint64_t *d_out, void *d_ws,
+                                  size_t ws_bytes, void *hip_stream)
+{
+    if (n == 0)
+        return PC_OK;
+    if (!d_xs || !d_out) {
+        t_err = "d_xs and d_out must be device pointers";
+        return PC_EINVAL;
+    }
+    return guarded([&] {
+        run_batch_async(d_xs, n, d_out, d_ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
 int pc_wheel_c(void) { return kWheelC; }
 
 const char *pc_status_str(pc_status s)
@@ -1682,7 +1930,15 @@ void pc_shutdown(void)
 {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     slot_release(g_slot);
-    drop_tables();
+    drop_tables(); // waits for the caller-memory batches still queued
+    async_wait_all();
+    for (hipEvent_t e : g_async_spare)
+        (void)hipEventDestroy(e);
+    g_async_spare.clear();
+    if (g_async_host)
+        (void)hipHostFree(g_async_host);
+    g_async_host = nullptr;
+    g_async_host_cap = 0;
     drop_query_bufs();
     if (g_stream2) {
         (void)hipStreamSynchronize(g_stream2);

@@ -163,6 +163,11 @@ hipError_t pc_launch_batch_easy(const pc_tables &T, const pc_query *Qs, const ui
                                 const uint32_t *bf, uint32_t nblocks, hipStream_t s);
 hipError_t pc_launch_batch_finish(const pc_query *Qs, const uint32_t *bq, const uint32_t *bf,
                                   uint32_t nblocks, uint32_t nq, pc_final *out, hipStream_t s);
+// The caller-memory batch path: a round's results, and results known on the
+// host ((position, value) pairs), written into the caller's output array.
+hipError_t pc_launch_batch_out(const pc_final *fin, const uint64_t *pos, uint32_t nq,
+                               const int32_t *err, uint64_t *out, hipStream_t s);
+hipError_t pc_launch_scatter_u64(const ulonglong2 *kv, uint64_t n, uint64_t *out, hipStream_t s);
 
 hipError_t pc_launch_combine(const pc_sums *sums, const pc_query &Q, uint64_t kp2,
                              pc_final *out, hipStream_t s);

@@ -72,3 +72,19 @@ def test_host_arithmetic(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "OK" in r.stdout
+
+
+def test_async_argument_checks_without_device(lib):
+    # the caller-memory batch: n = 0 and null pointers are answered before
+    # any device call
+    lib.pc_workspace_bytes.restype = C.c_size_t
+    lib.pc_workspace_bytes.argtypes = [C.c_void_p, C.c_size_t]
+    lib.pc_pi_count_batch_async.restype = C.c_int
+    lib.pc_pi_count_batch_async.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                            C.c_size_t, C.c_void_p]
+    lib.pc_last_error.restype = C.c_char_p
+    assert lib.pc_workspace_bytes(None, 0) == 0
+    assert lib.pc_workspace_bytes(None, 3) == 2**64 - 1
+    assert b"null" in lib.pc_last_error()
+    assert lib.pc_pi_count_batch_async(None, 0, None, None, 0, None) == 0
+    assert lib.pc_pi_count_batch_async(None, 3, None, None, 0, None) == 1  # PC_EINVAL
