@@ -6,8 +6,15 @@ each half decade of x it times pi(x) at every candidate alpha on this GPU
 best alpha, and writes the winners to csrc/pc_alpha_table.h, the table the
 library reads when alpha = 0 (alpha) and when the caller names no shape.
 
-    python -m paper_1503_01839_amd.autotune            # tune, write the header
-    python -m paper_1503_01839_amd.autotune --dry-run  # tune, print only
+A batch fills the GPU with many queries at once, so what counts there is the
+total work rather than one query's latency: the batch alpha of a half decade
+(up to 10^16; above, a query fills the GPU alone and takes the single-query
+alpha) is the one that runs a batch of queries log-uniform in that half
+decade (seeded) in the least time.
+
+    python -m paper_1503_01839_amd.autotune              # tune, write the header
+    python -m paper_1503_01839_amd.autotune --dry-run    # tune, print only
+    python -m paper_1503_01839_amd.autotune --batch-only # batch alphas; keep the rest
 
 Rebuild the library afterwards (__graft_entry__.build())."""
 from __future__ import annotations
@@ -20,6 +27,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 HEADER = os.path.join(HERE, "csrc", "pc_alpha_table.h")
 ALPHAS = [1, 1.5, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48]
 SHAPES = [(32, 512), (32, 256), (64, 512), (64, 1024)]  # (segment KiB, workgroup threads)
+BATCH_HI = 16.0   # half decades above take the single-query alpha in batches
+BATCH_SEED = 1503
 
 
 def candidates(log10x: float) -> list[float]:
@@ -52,15 +61,66 @@ def tune(lo: float = 7.0, hi: float = 19.0, reps: int = 3, log=print):
             log(f"  log10 x = {d:4.1f} alpha {best[0]:5.1f} {shape}: {t:9.2f} ms", flush=True)
             if t < best[1]:
                 best = (best[0], t, shape)
-        table.append((d, best[0], best[1], best[2]))
+        table.append((d, best[0], best[1], best[2], best[0]))
         log(f"log10 x = {d:4.1f}: alpha {best[0]:5.1f} segment {best[2][0]} KiB "
             f"workgroup {best[2][1]}  {best[1]:9.2f} ms", flush=True)
         d += 0.5
     return table
 
 
+def batch_queries(d: float) -> list[int]:
+    """The batch a half decade is tuned on: x log-uniform in [d - 1/4, d + 1/4),
+    as many as make a few tenths of a second of work."""
+    import numpy as np
+    n = 512 if d < 13 else 256 if d < 15.5 else 128
+    rng = np.random.Generator(np.random.PCG64(BATCH_SEED + int(d * 10)))
+    return [int(10 ** v) for v in rng.uniform(d - 0.25, d + 0.25, n)]
+
+
+def tune_batch(table, reps: int = 2, log=print):
+    """The batch alpha of every half decade in the table (see the module text)."""
+    import time
+    import paper_1503_01839_amd as pc
+    out = []
+    for d, a, t, sh, _ in table:
+        if d > BATCH_HI + 1e-9:
+            out.append((d, a, t, sh, a))
+            continue
+        xs = batch_queries(d)
+        best = None
+        for ab in candidates(d):
+            ref = pc.pi_count_batch(xs, alpha=ab)  # tables sized for this alpha
+            ts = []
+            for _ in range(reps):
+                s = time.perf_counter()
+                r = pc.pi_count_batch(xs, alpha=ab)
+                ts.append((time.perf_counter() - s) * 1e3)
+                if r != ref:
+                    raise RuntimeError("batch results changed between runs")
+            tb = min(ts)
+            log(f"  batch log10 x = {d:4.1f} n = {len(xs)} alpha {ab:5.1f}: {tb:9.2f} ms", flush=True)
+            if best is None or tb < best[1]:
+                best = (ab, tb)
+        log(f"log10 x = {d:4.1f}: batch alpha {best[0]:5.1f}  {best[1]:9.2f} ms", flush=True)
+        out.append((d, a, t, sh, best[0]))
+    return out
+
+
+def read_table(path: str = HEADER):
+    """The entries of an existing header: (log10 x, alpha, ms, shape, batch alpha)."""
+    import re
+    rows = []
+    for m in re.finditer(r"\{([\d.]+), ([\d.]+), (\d+), (\d+)(?:, ([\d.]+))?\}, // ([\d.]+) ms",
+                         open(path).read()):
+        a = float(m.group(2))
+        rows.append((float(m.group(1)), a, float(m.group(6)), (int(m.group(3)), int(m.group(4))),
+                     float(m.group(5)) if m.group(5) else a))
+    return rows
+
+
 def header_text(table) -> str:
-    rows = "\n".join(f"    {{{d:.1f}, {a:g}, {sh[0]}, {sh[1]}}}, // {t:.2f} ms" for d, a, t, sh in table)
+    rows = "\n".join(f"    {{{d:.1f}, {a:g}, {sh[0]}, {sh[1]}, {ab:g}}}, // {t:.2f} ms"
+                     for d, a, t, sh, ab in table)
     return f"""// pc_alpha_table.h -- alpha = y / icbrt(x) and the sieve shape per half decade of x, written by
 // paper_1503_01839_amd/autotune.py from pi(x) timings on MI355X; the entry
 // whose log10 x is nearest is used.  Regenerate with the tuner, do not edit.
@@ -68,9 +128,10 @@ def header_text(table) -> str:
 
 struct pc_alpha_entry {{
     double log10x;
-    double alpha;
-    unsigned seg_kib; // LDS segment, KiB
-    unsigned wg;      // workgroup threads
+    double alpha;       // least time for one query
+    unsigned seg_kib;   // LDS segment, KiB
+    unsigned wg;        // workgroup threads
+    double batch_alpha; // least time for a batch of queries of this size
 }};
 
 static const pc_alpha_entry kAlphaTable[] = {{
@@ -85,8 +146,11 @@ def main():
     ap.add_argument("--lo", type=float, default=7.0)
     ap.add_argument("--hi", type=float, default=19.0)
     ap.add_argument("--out", default=HEADER, help="where to write the header")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="keep the single-query entries of the current header, tune the batch alphas")
     args = ap.parse_args()
-    table = tune(args.lo, args.hi)
+    table = read_table() if args.batch_only else tune(args.lo, args.hi)
+    table = tune_batch(table)
     text = header_text(table)
     if args.dry_run:
         print(text)

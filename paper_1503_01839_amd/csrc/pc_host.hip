@@ -335,6 +335,10 @@ const pc_alpha_entry &tuned_entry(uint64_t x)
 
 double default_alpha(uint64_t x) { return tuned_entry(x).alpha; }
 
+// alpha for a query in a batch round: the least total work rather than the
+// least latency of the query alone
+double default_batch_alpha(uint64_t x) { return tuned_entry(x).batch_alpha; }
+
 uint64_t choose_y(uint64_t x, double alpha)
 {
     uint64_t r = pc_icbrt(x), s = pc_isqrt(x);
@@ -1300,7 +1304,7 @@ std::vector<BatchQuery> plan_queries(const uint64_t *xs, size_t n, double alpha,
     for (size_t i = 0; i < n; i++) {
         if (xs[i] < kSmallX)
             continue;
-        ys[i] = choose_y(xs[i], alpha > 0 ? alpha : default_alpha(xs[i]));
+        ys[i] = choose_y(xs[i], alpha > 0 ? alpha : default_batch_alpha(xs[i]));
         need = std::max<uint64_t>({need, pc_isqrt(xs[i]), ys[i]});
         ymax = std::max(ymax, ys[i]);
     }
