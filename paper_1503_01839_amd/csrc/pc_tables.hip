@@ -52,42 +52,44 @@ __global__ __launch_bounds__(PT_T) void k_sieve_pitab(uint64_t nent, const uint3
                                                     uint32_t nbase, uint2 *tab, uint32_t *cnt)
 {
     __shared__ uint32_t bits[PT_WORDS];
+    __shared__ uint32_t first[PT_T]; // start index of each small prime, computed once
     const uint32_t t = threadIdx.x;
     const uint64_t e0 = (uint64_t)blockIdx.x * PT_WORDS;
     for (uint32_t i = t; i < PT_WORDS; i += PT_T)
         bits[i] = 0xFFFFFFFFu;
-    __syncthreads();
-    const uint64_t nlo = 64 * e0;                   // first integer covered
+    // The table has at most 2^26 entries, so every integer it covers is below
+    // 2^32 and the first multiple of a prime comes from a 32-bit remainder.
+    const uint32_t nlo = (uint32_t)(64 * e0);       // first integer covered
     const uint64_t nhi = 64 * (e0 + PT_WORDS) - 1;  // last integer covered
     const uint32_t NBIT = PT_WORDS * 32;
-    // small primes: all threads share the multiples of one prime at a time
-    uint32_t k = 0;
-    for (; k < nbase; k++) {
-        uint64_t q = base[k];
-        if (q >= 4 * PT_T)
-            break;
-        if (q * q > nhi)
-            break;
-        uint64_t m = (nlo + q - 1) / q * q;
+    // bit index (from nlo) of the first odd multiple of q that is >= nlo and >= q^2
+    auto start = [&](uint32_t q) -> uint32_t {
+        const uint32_t r = nlo % q;
+        uint64_t m = (uint64_t)nlo + (r ? q - r : 0);
         if ((m & 1) == 0)
             m += q;
-        if (m < q * q)
-            m = q * q;
-        uint32_t i0 = (uint32_t)(((m - 1) >> 1) - (nlo >> 1));
-        for (uint32_t i = i0 + t * (uint32_t)q; i < NBIT; i += PT_T * (uint32_t)q)
+        if (m < (uint64_t)q * q)
+            m = (uint64_t)q * q;
+        return (uint32_t)(((m - 1) >> 1) - (nlo >> 1));
+    };
+    // small primes (q < 4 PT_T, q^2 <= nhi: a prefix of base[], at most PT_T
+    // of them): their starts once per workgroup, then all threads share the
+    // multiples of one prime at a time
+    const bool small = t < nbase && base[t] < 4 * PT_T && (uint64_t)base[t] * base[t] <= nhi;
+    if (small)
+        first[t] = start(base[t]);
+    const uint32_t nsm = (uint32_t)__syncthreads_count(small);
+    for (uint32_t k = 0; k < nsm; k++) {
+        const uint32_t q = base[k];
+        for (uint32_t i = first[k] + t * q; i < NBIT; i += PT_T * q)
             atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
     }
     // large primes: one lane per prime
-    for (uint32_t j = k + t; j < nbase; j += PT_T) {
-        uint64_t q = base[j];
-        if (q * q > nhi)
+    for (uint32_t j = nsm + t; j < nbase; j += PT_T) {
+        const uint32_t q = base[j];
+        if ((uint64_t)q * q > nhi)
             continue;
-        uint64_t m = (nlo + q - 1) / q * q;
-        if ((m & 1) == 0)
-            m += q;
-        if (m < q * q)
-            m = q * q;
-        for (uint64_t i = ((m - 1) >> 1) - (nlo >> 1); i < NBIT; i += q)
+        for (uint32_t i = start(q); i < NBIT; i += q)
             atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
     }
     __syncthreads();
@@ -210,6 +212,8 @@ hipError_t pc_launch_pitab(uint64_t nent, const uint32_t *base, uint32_t nbase, 
                            hipStream_t s)
 {
     (void)bits;
+    if (nent > (1ull << 26)) // k_sieve_pitab's 32-bit arithmetic
+        return hipErrorInvalidValue;
     uint32_t nblk = (uint32_t)((nent + PT_WORDS - 1) / PT_WORDS);
     k_sieve_pitab<<<nblk, PT_T, 0, s>>>(nent, base, nbase, pitab, cnts);
     hipError_t e = scan_excl<uint32_t>(cnts, nent, scan_tmp, (uint32_t *)nullptr, s);
@@ -258,32 +262,48 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
     __shared__ uint32_t lpf[MF_N];
     __shared__ uint32_t prod[MF_N];
     __shared__ int32_t mu[MF_N];
+    __shared__ uint32_t f1[MF_T], f2[MF_T]; // first multiples of p and p^2 in the block
     const uint32_t t = threadIdx.x;
-    const uint32_t n0 = blockIdx.x * MF_N;
+    const uint32_t n0 = blockIdx.x * MF_N; // ymax < 2^31: every n fits 32 bits
     for (uint32_t i = t; i < MF_N; i += MF_T) {
         lpf[i] = 0;
         prod[i] = 1;
         mu[i] = 1;
     }
-    __syncthreads();
-    for (uint32_t k = 1; k <= nsmall; k++) {
-        uint32_t p = primes[k];
-        uint32_t first = (n0 + p - 1) / p * p;
-        for (uint32_t m = first + t * p; m < n0 + MF_N; m += MF_T * p) {
-            uint32_t i = m - n0;
-            if (lpf[i] == 0)
-                lpf[i] = p;
-            prod[i] *= p;
-            mu[i] = -mu[i];
-        }
-        uint64_t pp = (uint64_t)p * p;
-        if (pp < (uint64_t)n0 + MF_N) {
-            uint64_t f2 = ((uint64_t)n0 + pp - 1) / pp * pp;
-            for (uint64_t m = f2 + (uint64_t)t * pp; m < (uint64_t)n0 + MF_N; m += MF_T * pp)
-                mu[m - n0] = 0;
+    for (uint32_t k0 = 1; k0 <= nsmall; k0 += MF_T) {
+        // the offsets of the next MF_T primes, one per thread
+        if (k0 + t <= nsmall) {
+            const uint32_t p = primes[k0 + t];
+            const uint32_t r = n0 % p;
+            f1[t] = r ? p - r : 0;
+            const uint64_t pp = (uint64_t)p * p;
+            uint32_t o2 = 0xFFFFFFFFu; // p^2 has no multiple in the block
+            if (pp < (uint64_t)n0 + MF_N) { // then pp < 2^32
+                const uint32_t r2 = n0 % (uint32_t)pp;
+                o2 = r2 ? (uint32_t)pp - r2 : 0;
+            }
+            f2[t] = o2;
         }
         __syncthreads();
+        const uint32_t kend = min(nsmall + 1, k0 + MF_T);
+        for (uint32_t k = k0; k < kend; k++) {
+            const uint32_t p = primes[k];
+            for (uint32_t i = f1[k - k0] + t * p; i < MF_N; i += MF_T * p) {
+                if (lpf[i] == 0)
+                    lpf[i] = p;
+                prod[i] *= p;
+                mu[i] = -mu[i];
+            }
+            const uint32_t o2 = f2[k - k0];
+            if (o2 != 0xFFFFFFFFu) {
+                const uint64_t pp = (uint64_t)p * p;
+                for (uint64_t i = o2 + (uint64_t)t * pp; i < MF_N; i += MF_T * pp)
+                    mu[i] = 0;
+            }
+            __syncthreads();
+        }
     }
+    __syncthreads();
     for (uint32_t i = t; i < MF_N; i += MF_T) {
         uint64_t n = (uint64_t)n0 + i;
         if (n > ymax)
@@ -311,6 +331,8 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
 hipError_t pc_launch_mulpf(const uint32_t *primes, uint32_t nsmall, uint64_t ymax, int32_t *mulpf,
                            hipStream_t s)
 {
+    if (ymax >= (1ull << 31)) // k_mulpf's 32-bit arithmetic
+        return hipErrorInvalidValue;
     uint32_t nblk = (uint32_t)(ymax / MF_N + 1);
     k_mulpf<<<nblk, MF_T, 0, s>>>(primes, nsmall, ymax, mulpf);
     return hipGetLastError();
