@@ -21,13 +21,13 @@ __global__ __launch_bounds__(1024) void k_base_primes(uint32_t *base, uint32_t *
     const uint32_t t = threadIdx.x;
     bits[t] = t == 0 ? 0xFFFFFFFEu : 0xFFFFFFFFu; // 1 is not prime
     __syncthreads();
-    if (t < 127) { // odd q in [3, 255]; composite q only repeats its factors' work
-        uint32_t q = 2 * t + 3;
-        for (uint32_t n = q * q; n < 65536u; n += 2 * q) {
-            uint32_t i = n >> 1;
+    // odd q in [3, 255], the odd multiples from q^2 shared by all threads;
+    // composite q only repeats its factors' work
+    for (uint32_t q = 3; q < 256; q += 2)
+        for (uint32_t n = q * q + 2 * q * t; n < 65536u; n += 2 * q * 1024) {
+            const uint32_t i = n >> 1;
             atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
         }
-    }
     __syncthreads();
     uint32_t w = bits[t], total;
     uint32_t off = pc_block_excl_scan<1024>((uint32_t)__builtin_popcount(w), scr, &total);
