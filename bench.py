@@ -6,6 +6,9 @@ pi up to sqrt x, mu*lpf up to y, wheel), S1, trivial and easy leaves, the
 segmented sieve with hard leaves and P2, the carry scan and the final
 combination.  The input is the single integer x, resident before timing.
 
+--x runs the same step at another size (the other single-query
+configurations, e.g. x = 2^63 + 2^61); the default is the headline, 1e18.
+
 Prints one JSON line.  `value` is special leaves (trivial + easy + hard, the
 whole S2 tree at the chosen alpha) per second of pi(1e18) wall time; the
 alpha-independent pi(x) wall time is `ms_per_step`.
@@ -64,6 +67,16 @@ def kernel_sha256():
     for f in KERNEL_SRC:
         h.update(open(f, "rb").read())
     return h.hexdigest()
+
+
+def icbrt(n: int) -> int:
+    """floor(n^(1/3))."""
+    r = int(round(n ** (1.0 / 3.0)))
+    while r ** 3 > n:
+        r -= 1
+    while (r + 1) ** 3 <= n:
+        r += 1
+    return max(r, 1)
 
 
 def sync():
@@ -163,6 +176,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--x", type=int, default=X,
+                    help="the single query (default 1e18, the headline; other sizes for the "
+                         "other single-query configurations, e.g. 2^63 + 2^61)")
     ap.add_argument("--alpha", type=float, default=0.0, help="0 = library's tuned value")
     ap.add_argument("--segment-kib", type=int, default=0)
     ap.add_argument("--wg", type=int, default=0)
@@ -188,21 +204,25 @@ def main():
 
     flags = 0 if args.keep_tables else pc.FLAG_REBUILD_TABLES
     cfg = dict(alpha=args.alpha, segment_kib=args.segment_kib, wg_size=args.wg, flags=flags)
+    x = args.x
+    if not 0 <= x < 2**64:
+        raise SystemExit("--x must lie in [0, 2^64)")
     for i in range(args.warmup):
-        r = pc.pi_count_ex(X, **cfg)
+        r = pc.pi_count_ex(x, **cfg)
         print(f"warmup {i}: {r.ms_total:.1f} ms", file=sys.stderr, flush=True)
     sync()
     results = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        r = pc.pi_count_ex(X, **cfg)
+        r = pc.pi_count_ex(x, **cfg)
         results.append(r)
         print(f"step {i}: {r.ms_total:.1f} ms (tables {r.ms_tables:.1f}, leaves {r.ms_leaves:.1f}, "
               f"sieve {r.ms_sieve:.1f})", file=sys.stderr, flush=True)
     sync()
     wall = time.perf_counter() - t0
     r = results[-1]
-    ok = all(q.pi == PI_1E18 for q in results)
+    ok = all(q.pi == PI_1E18 for q in results) if x == X else None
+    consistent = len({q.pi for q in results}) == 1
     ms_step = 1e3 * wall / args.steps
     leaves = r.n_trivial + r.n_easy + r.n_hard
     value = leaves / (ms_step / 1e3)
@@ -216,7 +236,8 @@ def main():
     ops_per_launch = ops / max(launches, 1)
     achieved = ops_per_launch / (avg_launch_ms / 1e3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK / 1e12,
-            "unit": "T int-ops/s", "frac": achieved / INT_PEAK, "traffic": traffic_bytes(launches),
+            "unit": "T int-ops/s", "frac": achieved / INT_PEAK,
+            "traffic": traffic_bytes(launches) if x == X else None,
             "kernel": "k_sieve", "launches": launches, "avg_launch_ms": avg_launch_ms,
             "ops_per_launch": ops_per_launch,
             "work": {"crossings": r.crossings, "prime_visits": visits, "hard_leaves": r.n_hard,
@@ -229,11 +250,12 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64/i128",
         "data": "synthetic",
-        "config": {"workload": "pi(x) single query, x = 1e18 (Table 1 row 10^18)", "x": X,
-                   "alpha": r.y / 1e6, "y": r.y, "a": r.a, "c": r.c, "z": r.z, "bmax": r.bmax,
+        "config": {"workload": ("pi(x) single query, x = 1e18 (Table 1 row 10^18)" if x == X
+                                else f"pi(x) single query, x = {x}"), "x": x,
+                   "alpha": r.y / icbrt(x), "y": r.y, "a": r.a, "c": r.c, "z": r.z, "bmax": r.bmax,
                    "segment_bits": r.segment_bits, "segments": r.segments,
                    "windows": r.windows, "tables_rebuilt_each_step": not args.keep_tables},
-        "pi": r.pi, "pi_matches_table1": ok,
+        "pi": r.pi, "pi_matches_table1": ok, "pi_same_every_step": consistent,
         "pi_wall_ms": ms_step,
         "leaves": {"trivial": r.n_trivial, "easy": r.n_easy, "hard": r.n_hard, "s1_terms": r.n_s1,
                    "p2_terms": r.n_p2},
