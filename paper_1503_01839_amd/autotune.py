@@ -15,6 +15,8 @@ decade (seeded) in the least time.
     python -m paper_1503_01839_amd.autotune              # tune, write the header
     python -m paper_1503_01839_amd.autotune --dry-run    # tune, print only
     python -m paper_1503_01839_amd.autotune --batch-only # batch alphas; keep the rest
+    python -m paper_1503_01839_amd.autotune --sweep 16 --alphas 1,2,4,8
+                                            # every alpha x shape at x = 10^16, print only
 
 Rebuild the library afterwards (__graft_entry__.build())."""
 from __future__ import annotations
@@ -140,6 +142,19 @@ static const pc_alpha_entry kAlphaTable[] = {{
 """
 
 
+def sweep(log10x: float, alphas, reps: int = 5, log=print):
+    """pi(10^log10x) at every alpha x shape (median of reps, tables cached)."""
+    import paper_1503_01839_amd as pc
+    x = int(round(10 ** log10x))
+    for a in alphas:
+        for seg, wg in SHAPES:
+            kw = dict(alpha=a, segment_kib=seg, wg_size=wg)
+            r = pc.pi_count_ex(x, **kw)  # tables sized for this alpha
+            t = statistics.median(pc.pi_count_ex(x, **kw).ms_total for _ in range(reps))
+            log(f"  log10 x = {log10x:4.1f} alpha {a:5.1f} segment {seg} KiB workgroup {wg:4d}: "
+                f"{t:9.2f} ms  (y = {r.y}, {r.segments} segments, pi = {r.pi})", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dry-run", action="store_true")
@@ -148,7 +163,14 @@ def main():
     ap.add_argument("--out", default=HEADER, help="where to write the header")
     ap.add_argument("--batch-only", action="store_true",
                     help="keep the single-query entries of the current header, tune the batch alphas")
+    ap.add_argument("--sweep", type=float, default=None, metavar="LOG10X",
+                    help="time every alpha x shape at x = 10^LOG10X and print; writes nothing")
+    ap.add_argument("--alphas", default=None, help="comma-separated alphas for --sweep")
     args = ap.parse_args()
+    if args.sweep is not None:
+        alphas = [float(a) for a in args.alphas.split(",")] if args.alphas else candidates(args.sweep)
+        sweep(args.sweep, alphas)
+        return
     table = read_table() if args.batch_only else tune(args.lo, args.hi)
     table = tune_batch(table)
     text = header_text(table)
