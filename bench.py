@@ -133,27 +133,51 @@ def batch_leg(pc, n):
             "speedup": ts / tb, "match_plain": True}
 
 
-def serve_leg(pc, n):
+def serve_leg(pc, n, modes=("served", "plain"), piece=0):
     """An open-loop Poisson stream served with continuous batching, and by the
-    one-request-at-a-time server; p50/p99 of completion - arrival."""
+    one-request-at-a-time server; p50/p99 of completion - arrival.  piece > 0
+    replays the stream in consecutive pieces of that many requests (each
+    piece's arrival times re-based to its first), one call each, so that a
+    long stream reports progress; the latencies of all pieces are pooled."""
+    import hashlib
     import numpy as np
     from paper_1503_01839_amd import workloads as W
     xs, arr = W.serve_stream(n, rate_per_s=SERVE_RATE)
     pc.pi_count_batch(xs[:16])
     out = {"requests": n, "x": "log-uniform [1e10, 1e18], PCG64(1839)",
            "arrivals": f"Poisson, {SERVE_RATE}/s"}
+    if piece:
+        out["piece_requests"] = piece
+    kwargs = {"served": {}, "plain": dict(max_inflight=1, max_round=1)}
     ref = None
-    for name, kw in (("served", {}), ("plain", dict(max_inflight=1, max_round=1))):
-        pis, lat, st = pc.serve(xs, arr, **kw)
+    for name in modes:
+        step = piece or n
+        pis, lat, wall = [], [], 0.0
+        agg = dict(rounds=0, windowed=0, max_round_size=0, max_inflight_seen=0)
+        for k in range(0, n, step):
+            t0 = arr[k]
+            p_pis, p_lat, st = pc.serve(xs[k:k + step], [t - t0 for t in arr[k:k + step]],
+                                        **kwargs[name])
+            pis += p_pis
+            lat += p_lat
+            wall += st["wall_s"]
+            for f in ("rounds", "windowed"):
+                agg[f] += st[f]
+            for f in ("max_round_size", "max_inflight_seen"):
+                agg[f] = max(agg[f], st[f])
+            if piece:
+                print(f"serve {name}: {min(k + step, n)}/{n} requests", file=sys.stderr, flush=True)
         if ref is None:
             ref = pis
         elif pis != ref:
             raise SystemExit("served results differ from the per-request server")
         lat = np.array(lat) * 1e3
-        out[name] = {"requests_per_s": n / st["wall_s"], "p50_ms": float(np.percentile(lat, 50)),
-                     "p99_ms": float(np.percentile(lat, 99)), "rounds": st["rounds"],
-                     "windowed": st["windowed"], "max_round": st["max_round_size"],
-                     "max_inflight": st["max_inflight_seen"]}
+        out[name] = {"requests_per_s": n / wall, "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "rounds": agg["rounds"],
+                     "windowed": agg["windowed"], "max_round": agg["max_round_size"],
+                     "max_inflight": agg["max_inflight_seen"],
+                     "results_sha256": hashlib.sha256(np.array(pis, dtype=np.uint64).tobytes())
+                     .hexdigest()}
     return out
 
 
@@ -188,6 +212,10 @@ def main():
     ap.add_argument("--batch-queries", type=int, default=BATCH_N, help="0 = skip the batch leg")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the serving leg (the full stream is 20000); 0 = skip")
+    ap.add_argument("--serve-modes", default="served,plain",
+                    help="servers of the serving leg: served (continuous batching), plain")
+    ap.add_argument("--serve-piece", type=int, default=0,
+                    help="replay the stream in pieces of this many requests (0 = one call)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -274,7 +302,10 @@ def main():
     if args.batch_queries:
         out["batch"] = batch_leg(pc, args.batch_queries)
     if args.serve_requests:
-        out["serve"] = serve_leg(pc, args.serve_requests)
+        modes = tuple(m for m in args.serve_modes.split(",") if m)
+        if not modes or any(m not in ("served", "plain") for m in modes):
+            raise SystemExit("--serve-modes takes served and/or plain")
+        out["serve"] = serve_leg(pc, args.serve_requests, modes, args.serve_piece)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
