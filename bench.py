@@ -228,13 +228,17 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    modes = tuple(m for m in args.serve_modes.split(",") if m)
+    if not modes or any(m not in ("served", "plain") for m in modes):
+        raise SystemExit("--serve-modes takes served and/or plain")
+    if args.serve_piece < 0 or not 0 <= args.x < 2**64:
+        raise SystemExit("--serve-piece must be >= 0 and --x in [0, 2^64)")
+
     import paper_1503_01839_amd as pc
 
     flags = 0 if args.keep_tables else pc.FLAG_REBUILD_TABLES
     cfg = dict(alpha=args.alpha, segment_kib=args.segment_kib, wg_size=args.wg, flags=flags)
     x = args.x
-    if not 0 <= x < 2**64:
-        raise SystemExit("--x must lie in [0, 2^64)")
     for i in range(args.warmup):
         r = pc.pi_count_ex(x, **cfg)
         print(f"warmup {i}: {r.ms_total:.1f} ms", file=sys.stderr, flush=True)
@@ -302,9 +306,6 @@ def main():
     if args.batch_queries:
         out["batch"] = batch_leg(pc, args.batch_queries)
     if args.serve_requests:
-        modes = tuple(m for m in args.serve_modes.split(",") if m)
-        if not modes or any(m not in ("served", "plain") for m in modes):
-            raise SystemExit("--serve-modes takes served and/or plain")
         out["serve"] = serve_leg(pc, args.serve_requests, modes, args.serve_piece)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
