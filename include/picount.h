@@ -124,9 +124,13 @@ pc_status pc_p2(uint64_t x, uint64_t y, uint64_t *out);
 /* pi(xs[i]) for i < n; host arrays of n elements.  n = 0 is valid.  Every
  * xs[i] is validated before any work; on error nothing is written and
  * pc_last_error() names the first bad index.  All queries share one set of
- * device tables and one persistent tile queue; alpha per query comes from
- * the tuning table's batch column (the alpha of least total work for a batch
- * of queries of that size, which may differ from a lone query's). */
+ * device tables and run in rounds that fit the round budget (6 GiB of sieve
+ * counts): per round one set-up pass, one easy-leaf pass, one sieve launch
+ * whose (query, segment) tiles cover every query of the round, one carry
+ * pass and one combination, captured as a HIP graph.  A query too large for
+ * a round runs alone, windowed.  alpha per query comes from the tuning
+ * table's batch column (the alpha of least total work for a batch of queries
+ * of that size, which may differ from a lone query's). */
 pc_status pc_pi_count_batch(const uint64_t *xs, size_t n, uint64_t *pi_out);
 
 /* As pc_pi_count_batch with knobs; cfg may be NULL. */
