@@ -1189,6 +1189,11 @@ void round_launches(const RoundPlan &P, uint32_t nq, char *base, const pc_tables
     hipck(pc_launch_fill_u64(reinterpret_cast<uint64_t *>(err), 1, 0, st), "fill");
     hipck(pc_launch_fill_u64(reinterpret_cast<uint64_t *>(sums), nq * sizeof(pc_sums) / 8, 0, st),
           "fill");
+    // results cleared (ok = 0): a read-back that overtook the combination
+    // shows up as an error instead of the arena's previous values
+    static_assert(sizeof(pc_final) % 8 == 0, "pc_final is filled as u64 words");
+    hipck(pc_launch_fill_u64(reinterpret_cast<uint64_t *>(fin), nq * sizeof(pc_final) / 8, 0, st),
+          "fill");
     hipck(pc_launch_batch_setup(T, qs, bk + P.t_xb, bk + P.t_xb + P.nb_xb, P.nb_xb, bk + P.t_s1,
                                 bk + P.t_s1 + P.nb_s1, P.nb_s1, nq, st),
           "batch set-up");
@@ -1234,6 +1239,7 @@ void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
     }
     if (!sl.h_err)
         hipck(hipHostMalloc((void **)&sl.h_err, 8), "hipHostMalloc");
+    memset(sl.h_fin, 0, nq * sizeof(pc_final)); // ok = 0 until this round's copy lands
     if (!sl.done)
         hipck(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming), "hipEventCreate");
     hipck(hipMemcpyAsync(sl.qs.p, sl.Qv.data(), nq * sizeof(pc_query), hipMemcpyHostToDevice, st),
@@ -1285,7 +1291,8 @@ void collect_round(BatchSlot &sl, uint64_t *out)
         fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment (batch)");
     for (size_t i = 0; i < sl.R.size(); i++) {
         if (!sl.h_fin[i].ok)
-            fail(PC_EINTERNAL, "pi(x) outside [0, 2^64) (batch)");
+            fail(PC_EINTERNAL, "pi(x) outside [0, 2^64), or the round's results were not read "
+                               "back in order (batch)");
         out[sl.R[i].idx] = sl.h_fin[i].pi;
     }
 }
