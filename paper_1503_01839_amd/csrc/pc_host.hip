@@ -703,6 +703,11 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     if (const char *tp = std::getenv("PICOUNT_TILE_TRACE"))
         trace_file = std::fopen(tp, "a");
     std::vector<pc_tile> tiles_a, tiles_b;
+    // Each window's tile lists stay unchanged until the final synchronisation:
+    // a copy from pageable memory may read its source only when the stream
+    // reaches it, which under load from other streams can be after the host
+    // has built the next window's lists.
+    std::vector<std::vector<pc_tile>> sent;
     uint64_t ntiles_total = 0;
     uint64_t *cin = ptr<uint64_t>(B.carry_a), *cout = ptr<uint64_t>(B.carry_b);
     const int bflag = K.batch ? 0 : 0x100;
@@ -831,6 +836,10 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
                                    g_stream),
                   "sum");
         }
+        sent.push_back(std::move(tiles_a));
+        sent.push_back(std::move(tiles_b));
+        tiles_a = std::vector<pc_tile>();
+        tiles_b = std::vector<pc_tile>();
         std::swap(cin, cout);
     }
     if (trace_file)
