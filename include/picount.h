@@ -92,6 +92,8 @@ typedef struct {
      * stream concurrently with the sieve. */
     double ms_total, ms_tables, ms_leaves, ms_sieve;
     double ms_k_sieve, ms_k_scan, ms_k_easy, ms_k_s1;  /* kernel time, HIP events     */
+    uint64_t n_easy_items;          /* work items of the easy-leaf kernel: one easy leaf,
+                                       or a run of easy leaves sharing pi(u)     */
 } pc_result;
 
 /* ---------------------------------------------------------------------- */
@@ -206,6 +208,24 @@ typedef struct {
 pc_status pc_serve(const uint64_t *xs, const double *arrival_s, size_t n,
                    const pc_serve_config *cfg, uint64_t *pi_out, double *latency_s_out,
                    pc_serve_stats *stats);
+
+/* Read-out of the shared device tables that every query uses (the primes and
+ * pi(.) of Section 2.1, mu(n) * lpf(n) of Section 2.2), for checking them
+ * against an independent computation.  which selects the table; entries
+ * lo .. lo + n - 1 are copied to the host array out (n elements):
+ *   PC_TABLE_PRIMES  uint32_t: out[i] = p_{lo+i}, the primes 1-based (p_1 = 2);
+ *                    lo >= 1, p_{lo+n-1} < 2^32;
+ *   PC_TABLE_PI      uint64_t: out[i] = pi(lo + i); lo + n - 1 < 2^32;
+ *   PC_TABLE_MULPF   int32_t:  out[i] = mu(v) * lpf(v), v = lo + i: 0 if v = 0
+ *                    or v is not squarefree, INT32_MAX at v = 1;
+ *                    lo + n - 1 <= 2^31 - 2.
+ * The tables are built (or grown) as a query that needs the range would build
+ * them.  n = 0 is valid and touches nothing; out null with n > 0, an unknown
+ * table or a range outside the table's domain gives PC_EINVAL. */
+#define PC_TABLE_PRIMES 1
+#define PC_TABLE_PI 2
+#define PC_TABLE_MULPF 3
+pc_status pc_read_table(int which, uint64_t lo, uint64_t n, void *out);
 
 /* Wheel size c used by the library (c = min(pc_wheel_c(), a)). */
 int pc_wheel_c(void);

@@ -72,8 +72,12 @@ def lib():
         L.or_decompose.argtypes = [u64, u64, u64, C.c_int, C.c_int, C.c_int, u64,
                                    C.POINTER(_Decomp), P, P, P, P, u64]
         L.or_decompose.restype = C.c_int
-        L.or_leaf_sample.argtypes = [u64, u64, u64, u64, u64, u64, C.POINTER(_Decomp)]
+        L.or_leaf_sample.argtypes = [u64, u64, u64, u64, u64, u64, u64, C.POINTER(_Decomp)]
         L.or_leaf_sample.restype = C.c_int
+        L.or_s1_p2.argtypes = [u64, u64, u64, C.POINTER(_Decomp)]
+        L.or_s1_p2.restype = C.c_int
+        L.or_mu_lpf.argtypes = [u64, C.c_void_p, C.c_void_p]
+        L.or_mu_lpf.restype = C.c_int
         L.or_pi_meissel.argtypes = [u64, u64, u64]
         L.or_pi_meissel.restype = u64
         _lib = L
@@ -98,6 +102,17 @@ def primes(n: int) -> list[int]:
     buf = (C.c_uint32 * max(cnt, 1))()
     lib().or_primes(n, buf, cnt)
     return list(buf[:cnt])
+
+
+def mu_lpf(N: int):
+    """(mu, lpf) for 0 <= n <= N as numpy arrays (int8, uint32), by a plain
+    factor sieve; lpf is 0 for n < 2."""
+    import numpy as np
+    mu = np.zeros(N + 1, dtype=np.int8)
+    lpf = np.zeros(N + 1, dtype=np.uint32)
+    if lib().or_mu_lpf(N, mu.ctypes.data, lpf.ctypes.data) != 0:
+        raise ValueError(f"or_mu_lpf({N}) failed")
+    return mu, lpf
 
 
 def phi(u: int, b: int, c: int = 6) -> int:
@@ -190,11 +205,25 @@ def pi_meissel(x: int, y: int | None = None, c: int = 6) -> int:
     return lib().or_pi_meissel(x, y, c)
 
 
-def leaf_sample(x: int, y: int, c: int, b_lo: int, b_hi: int, u_max: int) -> Decomp:
-    """The special leaves with b_lo <= b < b_hi (hard ones only up to u_max):
-    a bounded slice of one (x, y, c) for timing the oracle on large x."""
+def s1_p2(x: int, y: int, c: int = 6) -> Decomp:
+    """S1 and P2 (with their term counts) of one (x, y, c); the leaf fields
+    are zero."""
     D = _Decomp()
-    rc = lib().or_leaf_sample(x, y, c, b_lo, b_hi, u_max, C.byref(D))
+    if lib().or_s1_p2(x, y, c, C.byref(D)) != 0:
+        raise ValueError(f"or_s1_p2({x}, {y}, {c}) failed")
+    vals = {f: getattr(D, f) for f, _ in _Decomp._fields_}
+    for k in ("s1", "s2t", "s2e", "s2h", "p2", "phi"):
+        vals[k] = vals[k].value()
+    return Decomp(**vals)
+
+
+def leaf_sample(x: int, y: int, c: int, b_lo: int, b_hi: int, u_max: int,
+                b_step: int = 1) -> Decomp:
+    """The special leaves with b = b_lo + k b_step < b_hi (hard ones only up
+    to u_max): a bounded slice of one (x, y, c), for timing the oracle on
+    large x or summing it slice by slice."""
+    D = _Decomp()
+    rc = lib().or_leaf_sample(x, y, c, b_lo, b_hi, b_step, u_max, C.byref(D))
     if rc != 0:
         raise ValueError(f"or_leaf_sample failed with code {rc}")
     vals = {f: getattr(D, f) for f, _ in _Decomp._fields_}

@@ -249,6 +249,24 @@ static int ctx_init(ctx_t *C, uint64_t x, uint64_t y, uint64_t pilim)
     return 0;
 }
 
+/* mu(n) and the least prime factor lpf(n) for 0 <= n <= N (§2.2 keeps the
+ * product mu(n) lpf(n) as a table), from the same plain factor sieve as the
+ * context above: mu_out[n] in {-1, 0, 1}, lpf_out[n] the least prime factor
+ * (0 for n < 2).  Returns 0, or -1 if N is too large for one byte array. */
+int or_mu_lpf(uint64_t N, int8_t *mu_out, uint32_t *lpf_out)
+{
+    if (N > (1ull << 32))
+        return -1;
+    ctx_t C;
+    ctx_init(&C, N, N < 2 ? 2 : N, 0);
+    for (uint64_t n = 0; n <= N; n++) {
+        mu_out[n] = n == 0 ? 0 : C.mu[n];
+        lpf_out[n] = n < 2 ? 0 : C.lpf[n];
+    }
+    ctx_free(&C);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* phi(u, b)                                                                 */
 /* ------------------------------------------------------------------------ */
@@ -519,14 +537,16 @@ static void one_leaf(const ctx_t *C, leaves_acc *A, uint64_t b, uint64_t m,
  * the primes in (max(p_b, y/p_b), y] are walked; the trailing run of them with
  * u < p_b is trivial and is counted, not walked. */
 static void special_leaves(const ctx_t *C, leaves_acc *A, int collect, uint64_t b_lo,
-                           uint64_t b_hi)
+                           uint64_t b_hi, uint64_t b_step)
 {
     uint64_t x = C->x, y = C->y;
-    if (b_lo < C->c + 1)
-        b_lo = C->c + 1;
+    if (b_step == 0)
+        b_step = 1;
+    while (b_lo < C->c + 1)
+        b_lo += b_step;
     if (b_hi > C->a)
         b_hi = C->a;
-    for (uint64_t b = b_lo; b < b_hi; b++) {
+    for (uint64_t b = b_lo; b < b_hi; b += b_step) {
         uint64_t p = C->p[b];
         uint64_t mlo = y / p + 1;
         if ((u128)p * p <= y) {
@@ -730,7 +750,7 @@ int or_decompose(uint64_t x, uint64_t y, uint64_t c, int hard_route, int want_ph
     A.per_b_e = pbe;
     A.u_max = UINT64_MAX;
     int collect = hard_route == 1 || hard_route == 3;
-    special_leaves(&C, &A, collect, C.c + 1, C.a);
+    special_leaves(&C, &A, collect, C.c + 1, C.a, 1);
     out->s2t = pack(A.s2t);
     out->s2e = pack(A.s2e);
     out->n_trivial = A.nt;
@@ -792,6 +812,36 @@ int or_decompose(uint64_t x, uint64_t y, uint64_t c, int hard_route, int want_ph
     return 0;
 }
 
+/* Only the ordinary leaves S1 and P2 of one (x, y, c), with their term
+ * counts, by the same routines as or_decompose (the special leaves of a large
+ * x are summed separately, slice by slice, with or_leaf_sample). */
+int or_s1_p2(uint64_t x, uint64_t y, uint64_t c, or_decomp *out)
+{
+    if (y < 1 || (u128)y * y > x || (u128)(y + 1) * (y + 1) * (y + 1) <= x)
+        return 1;
+    ctx_t C;
+    uint64_t z = x / y;
+    uint64_t pilim = or_isqrt(z) + 2;
+    ctx_init(&C, x, y, pilim);
+    C.c = c < C.a ? c : C.a;
+    memset(out, 0, sizeof *out);
+    out->x = x;
+    out->y = y;
+    out->a = C.a;
+    out->c = C.c;
+    out->z = z;
+    out->bmax = C.pi[or_isqrt(z)];
+    s1_acc S = {&C, 0, 0};
+    s1_loops(&S, 1, C.c + 1, 1);
+    out->s1 = pack(S.sum);
+    out->n_s1 = S.terms;
+    uint64_t n2;
+    out->p2 = pack(p2_sum(&C, &n2));
+    out->n_p2 = n2;
+    ctx_free(&C);
+    return 0;
+}
+
 /* pi(x) by Meissel's identity: phi(x, a) by eq. (4.1) plus P2, y given
  * (icbrt(x) <= y <= isqrt(x)).  Small x (< 8) is counted directly. */
 uint64_t or_pi_meissel(uint64_t x, uint64_t y, uint64_t c)
@@ -807,12 +857,13 @@ uint64_t or_pi_meissel(uint64_t x, uint64_t y, uint64_t c)
 }
 
 /* A bounded slice of the special leaves of one (x, y, c): the leaves with
- * b_lo <= b < b_hi, and of the hard ones only those with u <= u_max (their
- * phi from the direct sieve of [1, u_max]).  Used to time the oracle on a
- * sample of a workload too large to run whole.  out->n_* count the leaves
- * of the slice; out->s2t/s2e/s2h are the slice's sums. */
+ * b = b_lo + k b_step < b_hi (k >= 0; b_step 0 means 1; b <= c skipped), and
+ * of the hard ones only those with u <= u_max (their phi from the direct
+ * sieve of [1, u_max]).  Used to time the oracle on a sample of a workload
+ * too large to run whole, and to sum a large one slice by slice.  out->n_*
+ * count the leaves of the slice; out->s2t/s2e/s2h are the slice's sums. */
 int or_leaf_sample(uint64_t x, uint64_t y, uint64_t c, uint64_t b_lo, uint64_t b_hi,
-                   uint64_t u_max, or_decomp *out)
+                   uint64_t b_step, uint64_t u_max, or_decomp *out)
 {
     if (y < 1 || (u128)y * y > x || (u128)(y + 1) * (y + 1) * (y + 1) <= x)
         return 1;
@@ -828,7 +879,7 @@ int or_leaf_sample(uint64_t x, uint64_t y, uint64_t c, uint64_t b_lo, uint64_t b
     leaves_acc A;
     memset(&A, 0, sizeof A);
     A.u_max = u_max;
-    special_leaves(&C, &A, 1, b_lo, b_hi);
+    special_leaves(&C, &A, 1, b_lo, b_hi, b_step);
     out->s2t = pack(A.s2t);
     out->s2e = pack(A.s2e);
     out->n_trivial = A.nt;

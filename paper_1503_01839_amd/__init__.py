@@ -21,10 +21,11 @@ FLAG_REBUILD_TABLES = 4
 FLAG_NO_SMALL_SEGMENTS = 8
 FLAG_NO_GRAPH = 16
 FLAG_BATCH_SEQUENTIAL = 32
+TABLE_PRIMES, TABLE_PI, TABLE_MULPF = 1, 2, 3
 
 EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
            "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_workspace_bytes",
-           "pc_pi_count_batch_async", "pc_serve", "pc_wheel_c",
+           "pc_pi_count_batch_async", "pc_serve", "pc_read_table", "pc_wheel_c",
            "pc_status_str", "pc_last_error", "pc_shutdown"]
 
 
@@ -56,7 +57,8 @@ class _Result(C.Structure):
                                           "small_segments", "crossings", "device_bytes")] + \
                [(n, C.c_uint32) for n in ("sieve_launches", "scan_launches")] + \
                [(n, C.c_double) for n in ("ms_total", "ms_tables", "ms_leaves", "ms_sieve",
-                                          "ms_k_sieve", "ms_k_scan", "ms_k_easy", "ms_k_s1")]
+                                          "ms_k_sieve", "ms_k_scan", "ms_k_easy", "ms_k_s1")] + \
+               [("n_easy_items", C.c_uint64)]
 
 
 @dataclass
@@ -96,6 +98,7 @@ class Result:
     ms_k_scan: float
     ms_k_easy: float
     ms_k_s1: float
+    n_easy_items: int
 
 class ServeConfig(C.Structure):
     _fields_ = [("max_inflight", C.c_uint32), ("max_round", C.c_uint32),
@@ -137,6 +140,8 @@ def lib():
                   "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_pi_count_batch_async",
                   "pc_serve"):
             getattr(L, f).restype = C.c_int
+        L.pc_read_table.argtypes = [C.c_int, u64, u64, C.c_void_p]
+        L.pc_read_table.restype = C.c_int
         L.pc_wheel_c.restype = C.c_int
         L.pc_status_str.argtypes = [C.c_int]
         L.pc_status_str.restype = C.c_char_p
@@ -267,6 +272,18 @@ def serve(xs, arrivals, max_inflight=0, max_round=0, mem_budget=0, alpha=0.0, fl
     _check(lib().pc_serve(xa, ta, n, C.byref(cfg), out, lat, C.byref(st)))
     stats = {f: getattr(st, f) for f, _ in ServeStats._fields_}
     return list(out), list(lat), stats
+
+
+def read_table(which: int, lo: int, n: int):
+    """Entries lo .. lo + n - 1 of a shared device table (TABLE_PRIMES: p_k,
+    TABLE_PI: pi(v), TABLE_MULPF: mu(v) * lpf(v)) as a numpy array."""
+    import numpy as np
+    dt = {TABLE_PRIMES: np.uint32, TABLE_PI: np.uint64, TABLE_MULPF: np.int32}.get(which)
+    if dt is None:
+        raise ValueError(f"unknown table {which}")
+    out = np.zeros(max(n, 1), dtype=dt)
+    _check(lib().pc_read_table(which, lo, n, out.ctypes.data))
+    return out[:n]
 
 
 def wheel_c() -> int:

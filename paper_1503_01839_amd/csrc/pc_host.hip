@@ -120,7 +120,7 @@ struct Tables {
     DevBuf pattern[kWheelC + 1], phitab[kWheelC + 1], wres[kWheelC + 1];
     bool wheel_ok[kWheelC + 1] = {};
     uint32_t pattern_bits[kWheelC + 1] = {}, Qc[kWheelC + 1] = {}, phiQ[kWheelC + 1] = {};
-    DevBuf lk_in, lk_out;
+    DevBuf lk_in, lk_out, chk;
 };
 Tables g_T;
 
@@ -220,6 +220,30 @@ void ensure_recip(uint64_t kmax)
     T.recip_n = k;
 }
 
+// The number of squarefree n <= Y, Q(Y) = sum_{d <= isqrt Y} mu(d) floor(Y / d^2)
+// (inclusion-exclusion over the squares), for checking the device mu*lpf table.
+uint64_t squarefree_count(uint64_t Y)
+{
+    const uint64_t r = pc_isqrt(Y);
+    std::vector<int8_t> mu(r + 1, 1);
+    std::vector<uint8_t> comp(r + 1, 0);
+    for (uint64_t p = 2; p <= r; p++) {
+        if (comp[p])
+            continue;
+        for (uint64_t k = p; k <= r; k += p) {
+            if (k > p)
+                comp[k] = 1;
+            mu[k] = (int8_t)-mu[k];
+        }
+        for (uint64_t k = p * p; k <= r; k += p * p)
+            mu[k] = 0;
+    }
+    int64_t q = 0;
+    for (uint64_t d = 1; d <= r; d++)
+        q += mu[d] * (int64_t)(Y / (d * d));
+    return (uint64_t)q;
+}
+
 void ensure_mulpf(uint64_t y)
 {
     Tables &T = g_T;
@@ -236,6 +260,22 @@ void ensure_mulpf(uint64_t y)
     hipck(pc_launch_mulpf(ptr<uint32_t>(T.primes), (uint32_t)nsmall, Y, ptr<int32_t>(T.mulpf),
                           g_stream),
           "mu*lpf table");
+    // the table must mark exactly Q(Y) integers squarefree
+    ensure(T.chk, 8, "table check");
+    hipck(pc_launch_fill_u64(ptr<uint64_t>(T.chk), 1, 0, g_stream), "fill");
+    hipck(pc_launch_count_nonzero(ptr<int32_t>(T.mulpf), Y, ptr<unsigned long long>(T.chk),
+                                  g_stream),
+          "table check");
+    uint64_t nsq = 0;
+    hipck(hipMemcpyAsync(&nsq, T.chk.p, 8, hipMemcpyDeviceToHost, g_stream), "D2H");
+    hipck(hipStreamSynchronize(g_stream), "sync");
+    if (nsq != squarefree_count(Y)) {
+        dfree(T.mulpf);
+        T.y_limit = 0; // rebuilt by the next call that needs it
+        fail(PC_EINTERNAL, "mu*lpf table: " + std::to_string(nsq) + " squarefree entries up to " +
+                               std::to_string(Y) + ", expected " +
+                               std::to_string(squarefree_count(Y)));
+    }
     T.y_limit = Y;
 }
 
@@ -286,7 +326,7 @@ void drop_tables()
 {
     Tables &T = g_T;
     DevBuf *all[] = {&T.base, &T.nbase_d, &T.pitab, &T.primes, &T.cnt_tmp, &T.scan_tmp, &T.recip,
-                     &T.mulpf, &T.lk_in, &T.lk_out};
+                     &T.mulpf, &T.lk_in, &T.lk_out, &T.chk};
     for (DevBuf *b : all)
         dfree(*b);
     for (int c = 0; c <= kWheelC; c++) {
@@ -850,6 +890,8 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     pc_final fin{};
     pc_sums hs{};
     int32_t err = 0;
+    uint64_t e_items = 0;
+    hipck(hipMemcpyAsync(&e_items, B.e_total.p, 8, hipMemcpyDeviceToHost, g_stream), "D2H");
     hipck(hipMemcpyAsync(&hs, B.sums.p, sizeof hs, hipMemcpyDeviceToHost, g_stream), "D2H");
     hipck(hipMemcpyAsync(&fin, B.fin.p, sizeof fin, hipMemcpyDeviceToHost, g_stream), "D2H");
     hipck(hipMemcpyAsync(&err, B.err.p, 4, hipMemcpyDeviceToHost, g_stream), "D2H");
@@ -882,6 +924,7 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         res->n_s1 = hs.n_s1;
         res->n_easy = hs.n_easy;
         res->n_hard = hs.n_hard;
+        res->n_easy_items = e_items;
         res->crossings = hs.crossings;
         res->segments = nseg;
         res->tiles = ntiles_total;
@@ -1920,6 +1963,59 @@ pc_status pc_pi_count_batch_async(const uint64_t *d_xs, size_t n, uint64_t *d_ou
     }
     return guarded([&] {
         run_batch_async(d_xs, n, d_out, d_ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+pc_status pc_read_table(int which, uint64_t lo, uint64_t n, void *out)
+{
+    if (n == 0)
+        return PC_OK;
+    if (!out) {
+        t_err = "out must not be null";
+        return PC_EINVAL;
+    }
+    return guarded([&] {
+        init_stream();
+        Tables &T = g_T;
+        const uint64_t last = lo + n - 1;
+        if (last < lo)
+            fail(PC_EINVAL, "range wraps around");
+        if (which == PC_TABLE_PRIMES) {
+            if (lo < 1)
+                fail(PC_EINVAL, "primes are numbered from 1");
+            uint64_t lim = 1024;
+            for (;;) { // grow the pi table until it holds p_last
+                ensure_pi(lim);
+                if (T.nprimes >= last)
+                    break;
+                if (T.pi_limit >= 0xFFFFFFFFull)
+                    fail(PC_EINVAL, "p_k beyond 2^32 requested");
+                lim = std::min<uint64_t>(2 * T.pi_limit + 2, 0xFFFFFFFFull);
+            }
+            hipck(hipMemcpyAsync(out, ptr<uint32_t>(T.primes) + lo, n * 4, hipMemcpyDeviceToHost,
+                                 g_stream),
+                  "D2H");
+            hipck(hipStreamSynchronize(g_stream), "sync");
+        } else if (which == PC_TABLE_PI) {
+            if (last > 0xFFFFFFFFull)
+                fail(PC_EINVAL, "pi table ends below 2^32");
+            ensure_pi(std::max<uint64_t>(last, 1024));
+            std::vector<uint64_t> pts(n);
+            for (uint64_t i = 0; i < n; i++)
+                pts[i] = lo + i;
+            const std::vector<uint64_t> v = lookup(pts);
+            memcpy(out, v.data(), n * 8);
+        } else if (which == PC_TABLE_MULPF) {
+            if (last > (1ull << 31) - 2)
+                fail(PC_EINVAL, "mu*lpf table ends at 2^31 - 2");
+            ensure_mulpf(std::max<uint64_t>(last, 1));
+            hipck(hipMemcpyAsync(out, ptr<int32_t>(T.mulpf) + lo, n * 4, hipMemcpyDeviceToHost,
+                                 g_stream),
+                  "D2H");
+            hipck(hipStreamSynchronize(g_stream), "sync");
+        } else {
+            fail(PC_EINVAL, "unknown table");
+        }
     });
 }
 

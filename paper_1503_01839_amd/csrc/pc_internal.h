@@ -91,6 +91,8 @@ hipError_t pc_launch_pitab(uint64_t nentries, const uint32_t *base, uint32_t nba
 hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, uint32_t n, hipStream_t s);
 hipError_t pc_launch_mulpf(const uint32_t *primes, uint32_t nsmall, uint64_t ymax,
                            int32_t *mulpf, hipStream_t s);
+hipError_t pc_launch_count_nonzero(const int32_t *a, uint64_t n, unsigned long long *out,
+                                   hipStream_t s);
 hipError_t pc_launch_wheel(uint32_t c, const uint32_t *primes, uint32_t *pattern,
                            uint32_t pattern_words, uint32_t *phitab, uint32_t *wres,
                            hipStream_t s);

@@ -252,6 +252,15 @@ hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, uint32_t n, 
 // 4096 consecutive n; the primes <= sqrt(ymax) are applied in increasing order
 // (one barrier each) so the first prime to touch n is its least prime factor.
 // A cofactor left above 1 is one prime > sqrt(ymax).
+//
+// Within one prime p, the thread that flips the sign of mu[i] (i a multiple of
+// p) and the thread that marks i as divisible by p^2 are in general different
+// threads, often of different wavefronts, with no barrier between them.  The
+// square marks therefore go to their own array, which nothing reads until the
+// last barrier: each word of lpf, prod and mu has one writer per prime, and sq
+// only ever receives stores of 1.  (A read-modify-write of mu interleaved with
+// a store of 0 to the same word by another wavefront would otherwise leave a
+// non-squarefree n marked squarefree.)
 // ---------------------------------------------------------------------------
 #define MF_N 4096
 #define MF_T 256
@@ -262,6 +271,7 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
     __shared__ uint32_t lpf[MF_N];
     __shared__ uint32_t prod[MF_N];
     __shared__ int32_t mu[MF_N];
+    __shared__ uint8_t sq[MF_N];            // 1: some p^2 divides n
     __shared__ uint32_t f1[MF_T], f2[MF_T]; // first multiples of p and p^2 in the block
     const uint32_t t = threadIdx.x;
     const uint32_t n0 = blockIdx.x * MF_N; // ymax < 2^31: every n fits 32 bits
@@ -269,6 +279,7 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
         lpf[i] = 0;
         prod[i] = 1;
         mu[i] = 1;
+        sq[i] = 0;
     }
     for (uint32_t k0 = 1; k0 <= nsmall; k0 += MF_T) {
         // the offsets of the next MF_T primes, one per thread
@@ -298,7 +309,7 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
             if (o2 != 0xFFFFFFFFu) {
                 const uint64_t pp = (uint64_t)p * p;
                 for (uint64_t i = o2 + (uint64_t)t * pp; i < MF_N; i += MF_T * pp)
-                    mu[i] = 0;
+                    sq[i] = 1;
             }
             __syncthreads();
         }
@@ -314,7 +325,7 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
         } else if (n == 1) {
             v = 0x7FFFFFFF;
         } else {
-            int32_t m = mu[i];
+            int32_t m = sq[i] ? 0 : mu[i];
             uint32_t l = lpf[i];
             if (m != 0 && prod[i] < n) {
                 uint32_t big = (uint32_t)n / prod[i];
@@ -326,6 +337,28 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
         }
         out[n] = v;
     }
+}
+
+// *out += the number of nonzero entries of a[1..n] (a consistency check of the
+// mu*lpf table: those are the squarefree n <= ymax).
+__global__ __launch_bounds__(256) void k_count_nonzero(const int32_t *a, uint64_t n,
+                                                      unsigned long long *out)
+{
+    __shared__ unsigned long long scr[4];
+    unsigned long long c = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = 1 + (uint64_t)blockIdx.x * 256 + threadIdx.x; i <= n; i += stride)
+        c += a[i] != 0 ? 1u : 0u;
+    c = pc_block_sum<256>(c, scr);
+    if (threadIdx.x == 0)
+        atomicAdd(out, c);
+}
+
+hipError_t pc_launch_count_nonzero(const int32_t *a, uint64_t n, unsigned long long *out,
+                                   hipStream_t s)
+{
+    k_count_nonzero<<<1024, 256, 0, s>>>(a, n, out);
+    return hipGetLastError();
 }
 
 hipError_t pc_launch_mulpf(const uint32_t *primes, uint32_t nsmall, uint64_t ymax, int32_t *mulpf,

@@ -8,7 +8,16 @@ Calls nothing but the CPU oracle (``oracle/``) and the paper's Table 1.
 * route "identity" : S1, S2t, S2e and P2 from the oracle; S2h from Meissel's
                      identity with the paper's tabulated pi(x) (Table 1):
                      S2h = pi(x) - a + 1 + P2 - S1 - S2t - S2e.
-Usage: python tests/golden/make_golden.py [--big]   (--big adds 1e16 and 1e18)
+                     --tuned records take S1 and P2 from oracle.s1_p2 and
+                     S2t, S2e as sums of oracle.leaf_sample over slices of b
+                     run in parallel (the same leaf routine as the whole
+                     decomposition; n_hard is then not counted).
+Usage: python tests/golden/make_golden.py [--big] [--tuned]
+  --big   adds 1e16 (alpha 1, 2, 4, 8) and 1e18 (alpha 8, 16)
+  --tuned adds the alphas the library picks by default: 1e16 (16), 1e17 (24),
+          1e18 (24)
+  --only-tuned  skips the small sieve-route records (they are kept from the
+          existing file)
 """
 import json
 import os
@@ -55,13 +64,44 @@ def job(spec):
     return rec
 
 
+def _slice(args):
+    x, y, b0, b1 = args
+    d = O.leaf_sample(x, y, C, b0, b1, 0)
+    return d.s2t, d.s2e, d.n_trivial, d.n_easy
+
+
+def job_sliced(x, alpha, n10, ex, nslices=96):
+    """An identity record with the special leaves summed slice by slice."""
+    r = O.icbrt(x)
+    y = min(alpha * r, O.isqrt(x))
+    base = O.s1_p2(x, y, C)
+    a = base.a
+    cuts = [C + 1 + (a - C - 1) * k // nslices for k in range(nslices + 1)]
+    # small b have the most candidates m: cut them finer
+    cuts = sorted(set([C + 1 + k for k in range(0, 64, 4)] + cuts))
+    parts = list(ex.map(_slice, [(x, y, b0, b1) for b0, b1 in zip(cuts, cuts[1:]) if b0 < b1]))
+    s2t = sum(p[0] for p in parts)
+    s2e = sum(p[1] for p in parts)
+    pi = paper_pow10()[n10]
+    s2h = pi - a + 1 + base.p2 - base.s1 - s2t - s2e
+    rec = dict(x=x, alpha=alpha, y=y, c=base.c, a=a, z=base.z, bmax=base.bmax, s1=base.s1,
+               s2t=s2t, s2e=s2e, s2h=s2h, p2=base.p2, n_s1=base.n_s1,
+               n_trivial=sum(p[2] for p in parts), n_easy=sum(p[3] for p in parts),
+               n_hard=None, n_p2=base.n_p2, route="identity")
+    rec["pi"] = base.s1 + s2t + s2e + s2h + a - 1 - base.p2
+    rec["source"] = f"S2h from Meissel's identity with pi(10^{n10}) of Table 1"
+    print(json.dumps(rec), flush=True)
+    return rec
+
+
 def main():
     specs = []
-    for n in (8, 9, 10, 11, 12):
-        for alpha in (1, 2, 4, 8):
-            specs.append((10**n, alpha, "sieve", n))
-    specs.append((10**13, 1, "sieve", 13))
-    specs.append((2**40, 3, "sieve", None))
+    if "--only-tuned" not in sys.argv:
+        for n in (8, 9, 10, 11, 12):
+            for alpha in (1, 2, 4, 8):
+                specs.append((10**n, alpha, "sieve", n))
+        specs.append((10**13, 1, "sieve", 13))
+        specs.append((2**40, 3, "sieve", None))
     if "--big" in sys.argv:
         for alpha in (1, 2, 4, 8):
             specs.append((10**16, alpha, "identity", 16))
@@ -71,6 +111,9 @@ def main():
     specs.sort(key=lambda s: -s[0] / s[1])
     with ProcessPoolExecutor(max_workers=int(os.environ.get("GOLDEN_JOBS", "6"))) as ex:
         recs = list(ex.map(job, specs))
+        if "--tuned" in sys.argv:
+            for x, alpha, n10 in ((10**16, 16, 16), (10**17, 24, 17), (10**18, 24, 18)):
+                recs.append(job_sliced(x, alpha, n10, ex))
     recs.sort(key=lambda r: (r["x"], r["alpha"]))
     pw = paper_pow10()
     for r in recs:  # every record must reproduce the paper where the paper has a value

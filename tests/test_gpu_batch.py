@@ -3,11 +3,15 @@ run alone (the plain per-query path, itself pinned to the oracle and to the
 paper's tables), whether the batch runs as a HIP graph, phase by phase, or one
 query after another.  Inputs: x log-uniform from a fixed seed, plus edge
 values (tiny x, duplicates, Table 1 and Table 2 entries)."""
+import json
+import os
 import random
 
 import pytest
 
 pytestmark = pytest.mark.gpu
+
+MIXES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_pi_mixes.json")
 
 
 def say(*a):
@@ -58,3 +62,18 @@ def test_batch_alpha_invariance(pc):
     ref = pc.pi_count_batch(xs)
     for alpha in (1, 3):
         assert pc.pi_count_batch(xs, alpha=alpha) == ref, alpha
+
+
+def test_batch_workload_vs_oracle(pc):
+    # the 4096-query batch workload: every member the oracle finished (every
+    # x <= 1e13 and 64 above) equals the oracle's pi(x)
+    from paper_1503_01839_amd import workloads as W
+    with open(MIXES) as f:
+        want = dict(map(tuple, json.load(f)["batch_4096"]))
+    xs = W.batch_queries(4096)
+    say("case: batch workload vs oracle", len(want))
+    got = dict(zip(xs, pc.pi_count_batch(xs)))
+    bad = [(x, got[x], v) for x, v in want.items() if got[x] != v]
+    assert not bad, bad[:5]
+    assert len(want) > 2000
+

@@ -56,17 +56,34 @@ def test_decompose_small_vs_oracle(pc):
         assert r.pi == O.pi_brute(x), (x, y)
 
 
+def check_record(r, rec, what=""):
+    assert (r.a, r.bmax) == (rec["a"], rec["bmax"]), (rec["x"], rec["y"], what)
+    for got, key in ((r.s1, "s1"), (r.s2_trivial, "s2t"), (r.s2_easy, "s2e"),
+                     (r.s2_hard, "s2h"), (r.p2, "p2"), (r.pi, "pi")):
+        assert got == rec[key], (rec["x"], rec["y"], key, what)
+    assert (r.n_trivial, r.n_easy, r.n_s1) == (rec["n_trivial"], rec["n_easy"], rec["n_s1"])
+    if rec["n_hard"] is not None:
+        assert r.n_hard == rec["n_hard"], (rec["x"], rec["y"], "n_hard", what)
+
+
 def test_golden_records(pc):
+    # every record, 1e8 to 1e18: the sieve route up to 1e13, Meissel's identity
+    # with Table 1 above (Section 5)
     for rec in golden():
-        if rec["x"] > 10**13:
-            continue
-        say("case: golden", rec["x"], rec["y"])
-        r = pc.decompose(rec["x"], rec["y"])
-        assert (r.a, r.bmax) == (rec["a"], rec["bmax"])
-        assert (r.s1, r.s2_trivial, r.s2_easy, r.s2_hard, r.p2) == \
-            (rec["s1"], rec["s2t"], rec["s2e"], rec["s2h"], rec["p2"]), rec["x"]
-        assert r.pi == rec["pi"]
-        assert r.n_trivial == rec["n_trivial"]
+        say("case: golden", rec["x"], rec["y"], rec["route"])
+        check_record(pc.decompose(rec["x"], rec["y"]), rec)
+
+
+@pytest.mark.parametrize("seg,wg", [(32, 256), (32, 512), (64, 512), (64, 1024)])
+def test_1e16_alpha_shape_grid(pc, seg, wg):
+    # x = 1e16 with alpha in {1, 2, 4, 8} on every sieve shape, each component
+    # against the oracle's record (S2h pinned to Table 1 by Meissel's identity)
+    recs = {r["alpha"]: r for r in golden() if r["x"] == 10**16}
+    for alpha in (1, 2, 4, 8):
+        rec = recs[alpha]
+        say("case: 1e16 grid", alpha, seg, wg)
+        check_record(pc.decompose(10**16, rec["y"], segment_kib=seg, wg_size=wg), rec,
+                     (alpha, seg, wg))
 
 
 @pytest.mark.parametrize("seg,wg", [(32, 256), (32, 512), (64, 512), (64, 1024)])
@@ -94,13 +111,15 @@ def test_windows(pc):
 
 
 def test_paper_powers_of_ten(pc, paper_pow10):
-    for n in range(1, 16):
+    # Table 1 up to 10^19, the largest power of ten below 2^64
+    for n in range(1, 20):
         say("case: pi(10^%d)" % n)
         assert pc.pi_count(10**n) == paper_pow10[n], n
 
 
 def test_paper_powers_of_two(pc, paper_pow2):
-    for m in range(1, 51):
+    # Table 2 up to 2^63, the largest power of two below 2^64
+    for m in range(1, 64):
         say("case: pi(2^%d)" % m)
         assert pc.pi_count(2**m) == paper_pow2[m], m
 

@@ -3,9 +3,14 @@ as the request run alone, whether requests are batched as they arrive, served
 one at a time (the plain per-query server), or sent to the windowed path;
 latencies are non-negative.  Inputs: x log-uniform and Poisson arrivals from
 fixed seeds."""
+import json
+import os
+
 import pytest
 
 from paper_1503_01839_amd import workloads as W
+
+MIXES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_pi_mixes.json")
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +34,10 @@ def test_serve_equals_solo(pc):
     assert pis1 == solo and st1["rounds"] == sum(1 for x in xs if x >= 2**20)
     pis2, _, _ = pc.serve(xs, t, flags=pc.FLAG_NO_GRAPH, max_inflight=2, max_round=16)
     assert pis2 == solo
+    # and every answer equals the oracle's pi(x)
+    with open(MIXES) as f:
+        want = dict(map(tuple, json.load(f)["serve_test"]))
+    assert [want[x] for x in xs] == pis
 
 
 def test_serve_windowed_requests(pc):

@@ -246,3 +246,72 @@ def test_survey_worked_values():
     assert (d.phi, d.p2, d.s2t, d.s2e, d.s1, d.s2h) == (102753, 24300, 271, 4092, 75754, 22636)
     d = O.decompose(10**11, 4641, 6, hard=O.HARD_SIEVE)
     assert (d.s1, d.s2h, d.n_hard, d.p2, d.bmax) == (1469551610, 5219697028, 192435, 2571194450, 626)
+
+
+# ------------------------------------------------ tables and leaf slices ---
+def test_mu_lpf_vs_factoring():
+    N = 20000
+    m, l = O.mu_lpf(N)
+    for n in range(N + 1):
+        if n < 2:
+            assert l[n] == 0 and m[n] == (1 if n == 1 else 0), n
+            continue
+        assert m[n] == mu(n), n
+        assert l[n] == factor(n)[0], n
+
+
+def test_leaf_sample_vs_per_b_sums():
+    # a slice of b with every hard leaf (u_max = z) equals the per-prime sums
+    # of the whole decomposition over the same b
+    for x, y in [(10**8, 928), (10**9, 4000), (10**9 + 7, 31622)]:
+        d = O.decompose(x, y, 6, hard=O.HARD_SIEVE, per_b=True)
+        for b0, b1 in [(0, d.a), (7, 9), (10, 60), (d.a // 3, d.a // 2), (d.a - 5, d.a)]:
+            s = O.leaf_sample(x, y, 6, b0, b1, d.z)
+            lo = max(b0, 7)
+            assert s.s2t == sum(d.per_b_trivial[lo:b1]), (x, y, b0, b1)
+            assert s.s2e == sum(d.per_b_easy[lo:b1]), (x, y, b0, b1)
+            assert s.s2h == sum(d.per_b_hard[lo:b1]), (x, y, b0, b1)
+        s = O.leaf_sample(x, y, 6, 0, d.a, d.z)
+        assert (s.n_trivial, s.n_easy, s.n_hard) == (d.n_trivial, d.n_easy, d.n_hard)
+        # every b_step-th prime from b_lo on
+        for b0, step in [(7, 5), (9, 64), (0, 3)]:
+            s = O.leaf_sample(x, y, 6, b0, d.a, d.z, b_step=step)
+            bs = [b for b in range(b0, d.a, step) if b >= 7]
+            assert s.s2t == sum(d.per_b_trivial[b] for b in bs), (x, y, b0, step)
+            assert s.s2e == sum(d.per_b_easy[b] for b in bs), (x, y, b0, step)
+            assert s.s2h == sum(d.per_b_hard[b] for b in bs), (x, y, b0, step)
+
+
+def test_leaf_sample_u_bound_vs_definition():
+    # hard leaves only up to u_max: brute force by definition (gcd-count phi)
+    P = py_primes(1000)
+    for x, y, c, b0, b1, umax in [(10**4, 21, 2, 0, 99, 300), (40000, 100, 6, 7, 20, 2000),
+                                  (30030, 31, 1, 2, 9, 500)]:
+        s = O.leaf_sample(x, y, c, b0, b1, umax)
+        a = sum(1 for p in P if p <= y)
+        cc = min(c, a)
+        nt = st = ne = se = nh = sh = 0
+        pi_tab = [0] * (y + 1)
+        for n in range(2, y + 1):
+            pi_tab[n] = pi_tab[n - 1] + is_prime(n)
+        for b in range(max(b0, cc + 1), min(b1, a)):
+            p = P[b - 1]
+            for m in range(1, y + 1):
+                if m * p <= y or mu(m) == 0 or lpf(m) <= p:
+                    continue
+                u, w = x // (m * p), -mu(m)
+                if u < p:
+                    nt, st = nt + 1, st + w
+                elif u < p * p and u <= y:
+                    ne, se = ne + 1, se + w * (pi_tab[u] - b + 2)
+                elif u <= umax:
+                    nh, sh = nh + 1, sh + w * phi_gcd(u, b - 1, P)
+        assert (s.n_trivial, s.s2t, s.n_easy, s.s2e, s.n_hard, s.s2h) == (nt, st, ne, se, nh, sh)
+
+
+def test_s1_p2_vs_decompose():
+    for x, y in [(10**9, 1000), (10**10 + 3, 9000), (2**36, 4096)]:
+        d = O.decompose(x, y, 6, hard=O.HARD_NONE)
+        e = O.s1_p2(x, y, 6)
+        assert (e.s1, e.n_s1, e.p2, e.n_p2, e.a, e.bmax) == (d.s1, d.n_s1, d.p2, d.n_p2, d.a, d.bmax)
+
