@@ -176,6 +176,32 @@ size_t pc_workspace_bytes(const uint64_t *xs, size_t n);
 pc_status pc_pi_count_batch_async(const uint64_t *d_xs, size_t n, uint64_t *d_out, void *d_ws,
                                   size_t ws_bytes, void *hip_stream);
 
+/* The caller-memory batch without any allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  d_out[i] = pi(d_xs[i]) for i < n, as
+ * pc_pi_count_batch_async computes it, with the same device arrays d_xs and
+ * d_out (n elements each) and stream; no workspace argument: the workspace is
+ * a fixed device array of the library, PC_NOALLOC_SCRATCH_BYTES on each
+ * device the library runs on, held until the process ends.  The call makes no
+ * device or pinned-host allocation and builds no table: the shared tables
+ * must already cover the queries, as after pc_workspace_bytes(xs, n) or any
+ * batch of the same queries.  It returns once d_out is complete (it waits for
+ * the stream).  Every call on one device shares that device's array and
+ * keeps the last call's contents; calls are serialised and each waits for its
+ * own work, so calls through this library never overlap, but kernels of
+ * another copy of the library in the same process would race on it.
+ * Errors: n = 0 is valid and touches nothing; d_xs or d_out null with n > 0
+ * -> PC_EINVAL; tables not built or too small for these x, or an x whose
+ * sieve counts exceed half the array (x of a few times 10^15 and above)
+ * -> PC_ERANGE; more than PC_NOALLOC_SCRATCH_BYTES / 48 queries or a
+ * workspace beyond the array -> PC_ENOMEM; these write nothing.  An
+ * inconsistency found on the device -> PC_EINTERNAL, with all ones in d_out
+ * for the queries of the round where it was found (pi(x) < 2^63 for every
+ * x < 2^64, so no count has that value). */
+#define PC_NOALLOC_SCRATCH_BYTES (128ull << 20)
+pc_status pc_pi_count_batch_noalloc(const uint64_t *d_xs, size_t n, uint64_t *d_out,
+                                    void *hip_stream);
+
 /* Serving: an open-loop stream of pi(x) requests replayed in real time, with
  * continuous batching.  Request i (x = xs[i]) arrives arrival_s[i] seconds
  * after the call starts (non-decreasing, finite, >= 0).  Arrived requests wait

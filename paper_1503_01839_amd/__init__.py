@@ -25,7 +25,8 @@ TABLE_PRIMES, TABLE_PI, TABLE_MULPF = 1, 2, 3
 
 EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
            "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_workspace_bytes",
-           "pc_pi_count_batch_async", "pc_serve", "pc_read_table", "pc_wheel_c",
+           "pc_pi_count_batch_async", "pc_pi_count_batch_noalloc", "pc_serve", "pc_read_table",
+           "pc_wheel_c",
            "pc_status_str", "pc_last_error", "pc_shutdown"]
 
 
@@ -136,9 +137,10 @@ def lib():
         L.pc_workspace_bytes.restype = C.c_size_t
         L.pc_pi_count_batch_async.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                               C.c_size_t, C.c_void_p]
+        L.pc_pi_count_batch_noalloc.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
         for f in ("pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
                   "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_pi_count_batch_async",
-                  "pc_serve"):
+                  "pc_pi_count_batch_noalloc", "pc_serve"):
             getattr(L, f).restype = C.c_int
         L.pc_read_table.argtypes = [C.c_int, u64, u64, C.c_void_p]
         L.pc_read_table.restype = C.c_int
@@ -250,6 +252,14 @@ def pi_count_batch_async(d_xs, n: int, d_out, d_ws, ws_bytes: int, stream=None) 
     stream."""
     _check(lib().pc_pi_count_batch_async(_addr(d_xs), n, _addr(d_out), _addr(d_ws), ws_bytes,
                                          _addr(stream)))
+
+
+def pi_count_batch_noalloc(d_xs, n: int, d_out, stream=None) -> None:
+    """out[i] = pi(xs[i]) in caller device memory with no allocation (the
+    library's fixed scratch array as workspace; the tables must already cover
+    these x); returns once out is complete.  Pointer arguments as in
+    pi_count_batch_async."""
+    _check(lib().pc_pi_count_batch_noalloc(_addr(d_xs), n, _addr(d_out), _addr(stream)))
 
 
 def serve(xs, arrivals, max_inflight=0, max_round=0, mem_budget=0, alpha=0.0, flags=0):

@@ -1351,33 +1351,50 @@ void collect_round(BatchSlot &sl, uint64_t *out)
 
 BatchSlot g_slot; // the synchronous batch path's slot, on the library stream
 
-// Parameters of every query x >= kSmallX (small x are answered into out),
-// with the tables all of them need.
-std::vector<BatchQuery> plan_queries(const uint64_t *xs, size_t n, double alpha, uint64_t *out)
+// y of every query x >= kSmallX, and the pi-table limit and largest y they need.
+struct QueryYs {
+    std::vector<uint64_t> ys;
+    uint64_t need = kSmallX, ymax = 0;
+};
+
+QueryYs query_ys(const uint64_t *xs, size_t n, double alpha)
 {
     if (std::isnan(alpha) || alpha < 0)
         fail(PC_EINVAL, "alpha must be >= 0 (0 = tuned)");
-    init_stream();
-    std::vector<uint64_t> ys(n, 0);
-    uint64_t need = kSmallX, ymax = 0;
+    QueryYs Y;
+    Y.ys.assign(n, 0);
     for (size_t i = 0; i < n; i++) {
         if (xs[i] < kSmallX)
             continue;
-        ys[i] = choose_y(xs[i], alpha > 0 ? alpha : default_batch_alpha(xs[i]));
-        need = std::max<uint64_t>({need, pc_isqrt(xs[i]), ys[i]});
-        ymax = std::max(ymax, ys[i]);
+        Y.ys[i] = choose_y(xs[i], alpha > 0 ? alpha : default_batch_alpha(xs[i]));
+        Y.need = std::max<uint64_t>({Y.need, pc_isqrt(xs[i]), Y.ys[i]});
+        Y.ymax = std::max(Y.ymax, Y.ys[i]);
     }
-    ensure_pi(std::max<uint64_t>(need, 1024) + 1);
+    return Y;
+}
+
+// The points whose pi the planner needs: per query y, isqrt x, isqrt(x / y)
+// (x itself for x < kSmallX, whose pi is the answer).
+std::vector<uint64_t> query_points(const uint64_t *xs, size_t n, const QueryYs &Y)
+{
     std::vector<uint64_t> pts;
     pts.reserve(3 * n);
     for (size_t i = 0; i < n; i++) {
         const bool small = xs[i] < kSmallX;
-        pts.push_back(small ? xs[i] : ys[i]);
+        pts.push_back(small ? xs[i] : Y.ys[i]);
         pts.push_back(small ? 0 : pc_isqrt(xs[i]));
-        pts.push_back(small ? 0 : pc_isqrt(xs[i] / ys[i]));
+        pts.push_back(small ? 0 : pc_isqrt(xs[i] / Y.ys[i]));
     }
-    const std::vector<uint64_t> lk = lookup(pts);
-    uint64_t amax = 0;
+    return pts;
+}
+
+// Parameters of every query x >= kSmallX from the looked-up pi values (small x
+// are answered into out); *amax = the largest a.
+std::vector<BatchQuery> query_params(const uint64_t *xs, size_t n, const QueryYs &Y,
+                                     const std::vector<uint64_t> &lk, uint64_t *out,
+                                     uint64_t *amax)
+{
+    *amax = 0;
     std::vector<BatchQuery> big;
     for (size_t i = 0; i < n; i++) {
         if (xs[i] < kSmallX) {
@@ -1386,21 +1403,34 @@ std::vector<BatchQuery> plan_queries(const uint64_t *xs, size_t n, double alpha,
         }
         BatchQuery b{};
         b.x = xs[i];
-        b.y = ys[i];
+        b.y = Y.ys[i];
         b.a = lk[3 * i];
         b.kx = lk[3 * i + 1];
         b.bmax = lk[3 * i + 2];
-        b.z = xs[i] / ys[i];
+        b.z = xs[i] / Y.ys[i];
         b.c = (uint32_t)std::min<uint64_t>(kWheelC, b.a);
         b.nb = b.bmax > b.c ? (uint32_t)(b.bmax - b.c) : 0;
         b.ncol = b.nb + 1;
         b.nseg = b.z / (2ull << kBatchLog2S) + 1;
         b.idx = i;
-        amax = std::max(amax, b.a);
+        *amax = std::max(*amax, b.a);
         big.push_back(b);
     }
+    return big;
+}
+
+// Parameters of every query x >= kSmallX (small x are answered into out),
+// with the tables all of them need.
+std::vector<BatchQuery> plan_queries(const uint64_t *xs, size_t n, double alpha, uint64_t *out)
+{
+    const QueryYs Y = query_ys(xs, n, alpha);
+    init_stream();
+    ensure_pi(std::max<uint64_t>(Y.need, 1024) + 1);
+    uint64_t amax = 0;
+    std::vector<BatchQuery> big = query_params(xs, n, Y, lookup(query_points(xs, n, Y)), out,
+                                               &amax);
     if (!big.empty()) {
-        ensure_mulpf(ymax);
+        ensure_mulpf(Y.ymax);
         ensure_recip(amax + 1);
         ensure_wheel(kWheelC);
         hipck(hipStreamSynchronize(g_stream), "sync");
@@ -1461,10 +1491,21 @@ struct AsyncPlan {
     size_t o_kv = 0, nkv = 0, o_err = 0, o_arena = 0, total = 0;
 };
 
+// The rounds and the workspace layout of a caller-memory batch, from the
+// planned queries (A.known holds the answers of x < kSmallX).
+void async_layout(const uint64_t *xs, size_t n, const std::vector<BatchQuery> &big,
+                  const Knobs &K, AsyncPlan &A);
+
 void async_plan(const uint64_t *xs, size_t n, const Knobs &K, AsyncPlan &A)
 {
     A.known.assign(n, 0);
     const std::vector<BatchQuery> big = plan_queries(xs, n, 0.0, A.known.data());
+    async_layout(xs, n, big, K, A);
+}
+
+void async_layout(const uint64_t *xs, size_t n, const std::vector<BatchQuery> &big,
+                  const Knobs &K, AsyncPlan &A)
+{
     for (size_t i = 0; i < n; i++)
         if (xs[i] < kSmallX)
             A.known_idx.push_back(i);
@@ -1527,6 +1568,9 @@ void *async_staging(size_t bytes)
     return g_async_host;
 }
 
+void async_queue(const AsyncPlan &A, const std::vector<ulonglong2> &kv, char *img, char *ws,
+                 uint64_t *d_out, const Knobs &K, hipStream_t st);
+
 void run_batch_async(const uint64_t *d_xs, size_t n, uint64_t *d_out, void *d_ws, size_t ws_bytes,
                      hipStream_t st)
 {
@@ -1551,11 +1595,37 @@ void run_batch_async(const uint64_t *d_xs, size_t n, uint64_t *d_out, void *d_ws
         run_query(b.x, b.y, K, &r);
         kv.push_back(ulonglong2{b.idx, r.pi});
     }
-    char *ws = static_cast<char *>(d_ws);
+    async_queue(A, kv, static_cast<char *>(async_staging(A.o_err)), static_cast<char *>(d_ws),
+                d_out, K, st);
+    hipEvent_t e = nullptr;
+    if (!g_async_spare.empty()) {
+        e = g_async_spare.back();
+        g_async_spare.pop_back();
+    } else {
+        hipck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    }
+    g_async_live.push_back(e);
+    hipck(hipEventRecord(e, st), "hipEventRecord");
+    // forget the batches that have finished
+    for (size_t i = 0; i < g_async_live.size();)
+        if (g_async_live[i] != e && hipEventQuery(g_async_live[i]) == hipSuccess) {
+            g_async_spare.push_back(g_async_live[i]);
+            g_async_live[i] = g_async_live.back();
+            g_async_live.pop_back();
+        } else {
+            i++;
+        }
+}
+
+// Queue the rounds of plan A on st with the workspace ws: one upload of
+// everything before the error flag, staged in img (host, A.o_err bytes; free
+// again when this returns, since the upload is waited for), the results known
+// on the host (kv), then each round's kernels and its results into d_out.
+void async_queue(const AsyncPlan &A, const std::vector<ulonglong2> &kv, char *img, char *ws,
+                 uint64_t *d_out, const Knobs &K, hipStream_t st)
+{
     char *arena = ws + A.o_arena;
     const pc_tables T = tables_view(kWheelC);
-    // one upload of everything before the error flag, then the kernels
-    char *img = static_cast<char *>(async_staging(A.o_err));
     std::vector<pc_query> Qv;
     for (const AsyncRound &r : A.rounds) {
         round_queries(r.R, r.P, arena, T, Qv);
@@ -1584,24 +1654,91 @@ void run_batch_async(const uint64_t *d_xs, size_t n, uint64_t *d_out, void *d_ws
                                   st),
               "results");
     }
-    hipEvent_t e = nullptr;
-    if (!g_async_spare.empty()) {
-        e = g_async_spare.back();
-        g_async_spare.pop_back();
-    } else {
-        hipck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+}
+
+// ---------------------------------------------------------------------------
+// The caller-memory batch without any allocation.  The workspace is one fixed
+// device array of the library (every device it runs on holds its own copy
+// until the process ends), and the shared device tables must already cover
+// the queries: the call never builds or grows them.  The array's name is a
+// host-side stand-in; its device address comes from hipGetSymbolAddress once
+// per device, and only that address is used.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = PC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::vector<void *> g_scratch; // device address of scratch, by device ordinal
+
+char *scratch_ptr()
+{
+    int dev = 0;
+    hipck(hipGetDevice(&dev), "hipGetDevice");
+    if ((size_t)dev >= g_scratch.size())
+        g_scratch.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        hipck(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = p;
     }
-    g_async_live.push_back(e);
-    hipck(hipEventRecord(e, st), "hipEventRecord");
-    // forget the batches that have finished
-    for (size_t i = 0; i < g_async_live.size();)
-        if (g_async_live[i] != e && hipEventQuery(g_async_live[i]) == hipSuccess) {
-            g_async_spare.push_back(g_async_live[i]);
-            g_async_live[i] = g_async_live.back();
-            g_async_live.pop_back();
-        } else {
-            i++;
-        }
+    return static_cast<char *>(g_scratch[dev]);
+}
+
+void run_batch_noalloc(const uint64_t *d_xs, size_t n, uint64_t *d_out, hipStream_t st)
+{
+    Tables &T = g_T;
+    if (!g_stream || !T.base_ok || !T.wheel_ok[kWheelC])
+        fail(PC_ERANGE, "the device tables are not built: call pc_workspace_bytes (or any "
+                        "batch) with these queries first");
+    if (n > kScratchBytes / 48)
+        fail(PC_ENOMEM, "more queries than the scratch array holds (" +
+                            std::to_string(kScratchBytes / 48) + ")");
+    char *ws = scratch_ptr();
+    std::vector<uint64_t> xs(n);
+    hipck(hipMemcpyAsync(xs.data(), d_xs, n * 8, hipMemcpyDeviceToHost, st), "D2H");
+    hipck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const QueryYs Y = query_ys(xs.data(), n, 0.0);
+    if (T.pi_limit < std::max<uint64_t>(Y.need, 1024) + 1 || T.y_limit < Y.ymax)
+        fail(PC_ERANGE, "the device tables do not cover these queries: call "
+                        "pc_workspace_bytes (or any batch) with them first");
+    // pi at the planning points, staged in the scratch array
+    const std::vector<uint64_t> pts = query_points(xs.data(), n, Y);
+    uint64_t *d_in = reinterpret_cast<uint64_t *>(ws), *d_lk = d_in + pts.size();
+    std::vector<uint64_t> lk(pts.size());
+    hipck(hipMemcpyAsync(d_in, pts.data(), pts.size() * 8, hipMemcpyHostToDevice, st), "H2D");
+    hipck(pc_launch_lookup(ptr<uint2>(T.pitab), d_in, (uint32_t)pts.size(), d_lk, st), "lookup");
+    hipck(hipMemcpyAsync(lk.data(), d_lk, lk.size() * 8, hipMemcpyDeviceToHost, st), "D2H");
+    hipck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    AsyncPlan A;
+    A.known.assign(n, 0);
+    uint64_t amax = 0;
+    const std::vector<BatchQuery> big = query_params(xs.data(), n, Y, lk, A.known.data(), &amax);
+    if (!big.empty() && T.recip_n < amax + 1)
+        fail(PC_ERANGE, "the device tables do not cover these queries: call "
+                        "pc_workspace_bytes (or any batch) with them first");
+    Knobs K;
+    K.carry_budget = kScratchBytes / 2; // one round's counts and weights
+    async_layout(xs.data(), n, big, K, A);
+    if (!A.windowed.empty())
+        fail(PC_ERANGE, "x = " + std::to_string(A.windowed[0].x) + " needs " +
+                            std::to_string(A.windowed[0].bytes()) +
+                            " bytes of sieve counts, more than a round of the scratch array");
+    if (A.total > kScratchBytes)
+        fail(PC_ENOMEM, "these queries need " + std::to_string(A.total) +
+                            " bytes of workspace; the scratch array has " +
+                            std::to_string(kScratchBytes));
+    std::vector<ulonglong2> kv;
+    kv.reserve(A.nkv);
+    for (size_t i : A.known_idx)
+        kv.push_back(ulonglong2{i, A.known[i]});
+    std::vector<char> img(A.o_err);
+    async_queue(A, kv, img.data(), ws, d_out, K, st);
+    // wait: the next call reuses the array, and the tables must outlive the kernels
+    int32_t err = 0;
+    if (!A.rounds.empty())
+        hipck(hipMemcpyAsync(&err, ws + A.o_err, 4, hipMemcpyDeviceToHost, st), "D2H");
+    hipck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (err)
+        fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment (batch)");
 }
 
 // ---------------------------------------------------------------------------
@@ -1950,6 +2087,19 @@ size_t pc_workspace_bytes(const uint64_t *xs, size_t n)
         bytes = A.total;
     });
     return st == PC_OK ? bytes : SIZE_MAX;
+}
+
+pc_status pc_pi_count_batch_noalloc(const uint64_t *d_xs, size_t n, uint64_t *d_out,
+                                    void *hip_stream)
+{
+    if (n == 0)
+        return PC_OK;
+    if (!d_xs || !d_out) {
+        t_err = "d_xs and d_out must be device pointers";
+        return PC_EINVAL;
+    }
+    return guarded(
+        [&] { run_batch_noalloc(d_xs, n, d_out, static_cast<hipStream_t>(hip_stream)); });
 }
 
 pc_status pc_pi_count_batch_async(const uint64_t *d_xs, size_t n, uint64_t *d_out, void *d_ws,
