@@ -127,19 +127,22 @@ __global__ __launch_bounds__(BT) void k_scan_rows_b(const pc_query *Qs, pc_blk B
     const pc_query &Q = Qs[q];
     const uint32_t col = cb * BT + threadIdx.x;
     pc_s128 dh = 0, dp = 0;
-    if (col < Q.ncol) {
-        uint64_t carry = 0;
-        const uint64_t nrows = Q.nseg, ncol = Q.ncol;
+    const uint64_t nrows = Q.nseg, nb = Q.nb;
+    uint64_t carry = 0;
+    if (col < nb) { // a sieving column: row r holds it at r nb + col
         for (uint64_t r = 0; r < nrows; r++) {
-            const uint64_t idx = r * ncol + col;
+            const uint64_t idx = r * nb + col;
             const int32_t w = Q.wgt[idx];
-            if (w) {
-                if (col == Q.nb)
-                    dp += (pc_s128)w * (pc_s128)carry;
-                else
-                    dh += (pc_s128)w * (pc_s128)carry;
-            }
+            if (w)
+                dh += (pc_s128)w * (pc_s128)carry;
             carry += Q.cnt[idx];
+        }
+    } else if (col == nb) { // the P2 column
+        for (uint64_t r = 0; r < nrows; r++) {
+            const int32_t w = Q.wP[r];
+            if (w)
+                dp += (pc_s128)w * (pc_s128)carry;
+            carry += Q.cntP[r];
         }
     }
     dh = pc_block_sum128<BT>(dh, scr);

@@ -129,6 +129,7 @@ struct QueryBufs {
     DevBuf work, hot, bounds, tiles_a, trace;
     DevBuf tiles, cnt, wgt, carry_rows, carry_a, carry_b, status, ticket, part_tile_h,
         part_tile_p, part_scan_h, part_scan_p, err;
+    DevBuf row_off, blkoff, cntP, wP, carryP;
 };
 QueryBufs g_Q;
 
@@ -345,7 +346,8 @@ void drop_query_bufs()
     DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.e_start, &B.e_count, &B.e_off, &B.e_tmp, &B.e_total, &B.e_clu, &B.part,
                      &B.sums, &B.fin, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
                      &B.carry_a, &B.carry_b, &B.status, &B.ticket, &B.part_tile_h,
-                     &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err, &B.qdev};
+                     &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err, &B.qdev,
+                     &B.row_off, &B.blkoff, &B.cntP, &B.wP, &B.carryP};
     for (DevBuf *b : all)
         dfree(*b);
 }
@@ -709,31 +711,81 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     // --- the sieve of [1, z] in windows of segments ---
     auto t2 = clk::now();
     std::vector<size_t> ev_sieve, ev_scan;
-    const uint64_t per_entry = K.two_pass ? 12 : 8;
-    uint64_t rows_w = std::max<uint64_t>(1, K.carry_budget / (per_entry * Q.ncol));
-    rows_w = std::min(rows_w, nseg);
-    const uint64_t nwin = (nseg + rows_w - 1) / rows_w;
-    const uint32_t ncb = (Q.ncol + 255) / 256;
-    uint32_t R = (uint32_t)std::clamp<uint64_t>(rows_w / 64, 16, 1024);
-    const uint64_t nchunk_max = (rows_w + R - 1) / R;
+    // Row lengths of the count staircase: a hard leaf of p_b has u < x / p_b^2,
+    // so row r (first integer lo_r) stores the columns of the primes
+    // p_b <= isqrt(x / lo_r), and the first row stores every column.
+    std::vector<uint32_t> rowlen(nseg, Q.nb);
+    if (nseg > 1) {
+        std::vector<uint64_t> pts(nseg - 1);
+        for (uint64_t r = 1; r < nseg; r++) {
+            const uint64_t lo_r = r < nA ? r * 2 * SA : baseB + (r - nA) * 2 * S;
+            pts[r - 1] = pc_isqrt(x / lo_r);
+        }
+        const std::vector<uint64_t> pv = lookup(pts);
+        for (uint64_t r = 1; r < nseg; r++)
+            rowlen[r] = (uint32_t)std::min<uint64_t>(Q.nb, pv[r - 1] > c ? pv[r - 1] - c : 0);
+    }
+    // windows of rows within the carry budget (cells of cnt and w, or of cnt
+    // and the carries, plus the P2 column's per-row words)
+    const uint64_t per_cell = K.two_pass ? 12 : 8, per_row = K.two_pass ? 12 : 8;
+    std::vector<uint64_t> win_start{0};
+    uint64_t max_rows = 0, max_cells = 0, cells_total = 0;
+    {
+        uint64_t cells = 0, rows = 0;
+        for (uint64_t r = 0; r < nseg; r++) {
+            if (rows && (cells + rowlen[r]) * per_cell + (rows + 1) * per_row > K.carry_budget) {
+                win_start.push_back(r);
+                cells = rows = 0;
+            }
+            cells += rowlen[r];
+            rows++;
+            max_rows = std::max(max_rows, rows);
+            max_cells = std::max(max_cells, cells);
+            cells_total += rowlen[r];
+        }
+        win_start.push_back(nseg);
+    }
+    const uint64_t nwin = win_start.size() - 1;
+    const uint32_t R = (uint32_t)std::clamp<uint64_t>(max_rows / 256, 16, 1024);
+    uint64_t max_chunks = (max_rows + R - 1) / R, max_tickets = 0;
+    // the scan's tickets per window: blocks of 256 columns of each chunk's first row
+    std::vector<std::vector<uint32_t>> blkoffs(nwin);
+    for (uint64_t w = 0; w < nwin; w++) {
+        std::vector<uint32_t> &bo = blkoffs[w];
+        bo.push_back(0);
+        for (uint64_t r = win_start[w]; r < win_start[w + 1]; r += R)
+            bo.push_back(bo.back() + (rowlen[r] + 255) / 256);
+        max_tickets = std::max<uint64_t>(max_tickets, bo.back());
+    }
 
-    ensure(B.cnt, rows_w * Q.ncol * 4, "counts");
+    ensure(B.cnt, max_cells * 4, "counts");
     if (!K.two_pass)
-        ensure(B.wgt, rows_w * Q.ncol * 4, "leaf weights");
+        ensure(B.wgt, max_cells * 4, "leaf weights");
     else
-        ensure(B.carry_rows, rows_w * Q.ncol * 8, "carries");
+        ensure(B.carry_rows, max_cells * 8, "carries");
+    ensure(B.cntP, max_rows * 4, "P2 counts");
+    if (!K.two_pass)
+        ensure(B.wP, max_rows * 4, "P2 weights");
+    else
+        ensure(B.carryP, max_rows * 8, "P2 carries");
+    ensure(B.row_off, (max_rows + 1) * 8, "row offsets");
+    ensure(B.blkoff, (max_chunks + 1) * 4, "scan blocks");
     ensure(B.carry_a, (size_t)Q.ncol * 8, "carry");
     ensure(B.carry_b, (size_t)Q.ncol * 8, "carry");
-    ensure(B.status, nchunk_max * Q.ncol * 8 + 8, "look-back status");
+    ensure(B.status, max_tickets * 256 * 8 + 8, "look-back status");
     ensure(B.ticket, 8, "ticket");
-    ensure(B.part_scan_h, nchunk_max * ncb * 16, "scan partials");
-    ensure(B.part_scan_p, nchunk_max * ncb * 16, "scan partials");
+    ensure(B.part_scan_h, max_tickets * 16 + 16, "scan partials");
+    ensure(B.part_scan_p, 16, "scan partials");
     ensure(B.err, 8, "error flag");
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.carry_a), Q.ncol, 0, g_stream), "fill");
     // the query as the sieve reads it: one entry of a device array
+    Q.row_off = ptr<uint64_t>(B.row_off);
     Q.cnt = ptr<uint32_t>(B.cnt);
     Q.wgt = ptr<int32_t>(B.wgt);
     Q.carry = ptr<uint64_t>(B.carry_rows);
+    Q.cntP = ptr<uint32_t>(B.cntP);
+    Q.wP = ptr<int32_t>(B.wP);
+    Q.carryP = ptr<uint64_t>(B.carryP);
     ensure(B.qdev, sizeof(pc_query), "query");
     hipck(hipMemcpyAsync(B.qdev.p, &Q, sizeof Q, hipMemcpyHostToDevice, g_stream), "H2D");
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.err), 1, 0, g_stream), "fill");
@@ -748,12 +800,24 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     // reaches it, which under load from other streams can be after the host
     // has built the next window's lists.
     std::vector<std::vector<pc_tile>> sent;
+    std::vector<std::vector<uint64_t>> sent_off; // the same for the row offsets
     uint64_t ntiles_total = 0;
     uint64_t *cin = ptr<uint64_t>(B.carry_a), *cout = ptr<uint64_t>(B.carry_b);
     const int bflag = K.batch ? 0 : 0x100;
     for (uint64_t w = 0; w < nwin; w++) {
-        const uint64_t r0 = w * rows_w;
-        const uint64_t rows = std::min(rows_w, nseg - r0), r1 = r0 + rows;
+        const uint64_t r0 = win_start[w], r1 = win_start[w + 1], rows = r1 - r0;
+        {
+            std::vector<uint64_t> off(rows + 1, 0);
+            for (uint64_t r = 0; r < rows; r++)
+                off[r + 1] = off[r] + rowlen[r0 + r];
+            hipck(hipMemcpyAsync(B.row_off.p, off.data(), off.size() * 8, hipMemcpyHostToDevice,
+                                 g_stream),
+                  "row offsets");
+            hipck(hipMemcpyAsync(B.blkoff.p, blkoffs[w].data(), blkoffs[w].size() * 4,
+                                 hipMemcpyHostToDevice, g_stream),
+                  "scan blocks");
+            sent_off.push_back(std::move(off));
+        }
         // rows [r0, min(r1, nA)) are small segments, the rest workgroup segments
         tiles_a.clear();
         for (uint64_t r = r0; r < std::min(r1, nA); r++)
@@ -843,7 +907,12 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         pc_scan_args SA{};
         SA.cnt = ptr<uint32_t>(B.cnt);
         SA.wgt = ptr<int32_t>(B.wgt);
+        SA.row_off = ptr<uint64_t>(B.row_off);
+        SA.blkoff = ptr<uint32_t>(B.blkoff);
         SA.carry_rows = ptr<uint64_t>(B.carry_rows);
+        SA.cntP = ptr<uint32_t>(B.cntP);
+        SA.wP = ptr<int32_t>(B.wP);
+        SA.carryP = ptr<uint64_t>(B.carryP);
         SA.carry_in = cin;
         SA.carry_out = cout;
         SA.status = ptr<uint64_t>(B.status);
@@ -852,12 +921,11 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         SA.part_p2 = ptr<pc_s128>(B.part_scan_p);
         SA.err = ptr<int32_t>(B.err);
         SA.nrows = rows;
-        SA.ncol = Q.ncol;
         SA.nb = Q.nb;
         SA.rows_per_chunk = R;
         SA.nchunk = (uint32_t)((rows + R - 1) / R);
-        SA.ncb = ncb;
-        hipck(pc_launch_fill_u64(ptr<uint64_t>(B.status), (uint64_t)SA.nchunk * Q.ncol, 0,
+        SA.nticket = blkoffs[w].back();
+        hipck(pc_launch_fill_u64(ptr<uint64_t>(B.status), (uint64_t)SA.nticket * 256, 0,
                                  g_stream),
               "fill");
         hipck(pc_launch_fill_u64(ptr<uint64_t>(B.ticket), 1, 0, g_stream), "fill");
@@ -869,11 +937,10 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
             sieve(true, PC_MODE_LEAVES);
             sieve(false, PC_MODE_LEAVES);
         } else {
-            hipck(pc_launch_sum128(ptr<pc_s128>(B.part_scan_h), SA.nchunk * ncb,
-                                   &sums->hard_dot, g_stream),
-                  "sum");
-            hipck(pc_launch_sum128(ptr<pc_s128>(B.part_scan_p), SA.nchunk * ncb, &sums->p2_dot,
+            hipck(pc_launch_sum128(ptr<pc_s128>(B.part_scan_h), SA.nticket, &sums->hard_dot,
                                    g_stream),
+                  "sum");
+            hipck(pc_launch_sum128(ptr<pc_s128>(B.part_scan_p), 1, &sums->p2_dot, g_stream),
                   "sum");
         }
         sent.push_back(std::move(tiles_a));
@@ -899,6 +966,8 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     const double ms_sieve = ms_since(t2);
     if (err & 1)
         fail(PC_EINTERNAL, "look-back scan did not complete");
+    if (err & 8)
+        fail(PC_EINTERNAL, "a sieving column before the cut lay outside its row's stored range");
     if (err)
         fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment");
     if (!fin.ok)
@@ -1039,8 +1108,9 @@ size_t r256(size_t v) { return (v + 255) & ~(size_t)255; }
 // takes them.
 size_t query_chunk(const BatchQuery &b)
 {
-    const size_t na = b.a + 2, cells = b.nseg * b.ncol;
-    return r256(na * 8) + 2 * r256(na * 16) + 3 * r256(na * 8) + 2 * r256(cells * 4);
+    const size_t na = b.a + 2, cells = b.nseg * b.nb;
+    return r256(na * 8) + 2 * r256(na * 16) + 3 * r256(na * 8) + 2 * r256(cells * 4) +
+           2 * r256(b.nseg * 4);
 }
 
 // What the host builds for one round: the arena layout (sums, easy totals,
@@ -1219,8 +1289,12 @@ void round_queries(const std::vector<BatchQuery> &R, const RoundPlan &P, char *b
         Q.e_count = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_off = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_clu = reinterpret_cast<uint4 *>(carve(na * 16));
-        Q.cnt = reinterpret_cast<uint32_t *>(carve(b.nseg * b.ncol * 4));
-        Q.wgt = reinterpret_cast<int32_t *>(carve(b.nseg * b.ncol * 4));
+        Q.row_off = nullptr; // every row holds all nb sieving columns
+        Q.cnt = reinterpret_cast<uint32_t *>(carve(b.nseg * b.nb * 4));
+        Q.wgt = reinterpret_cast<int32_t *>(carve(b.nseg * b.nb * 4));
+        Q.cntP = reinterpret_cast<uint32_t *>(carve(b.nseg * 4));
+        Q.wP = reinterpret_cast<int32_t *>(carve(b.nseg * 4));
+        Q.carryP = nullptr;
         Q.e_total = reinterpret_cast<uint64_t *>(base + P.o_et) + i;
         Q.sums = sums + i;
         Q.carry = nullptr;

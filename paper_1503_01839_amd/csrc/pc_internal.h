@@ -50,9 +50,18 @@ struct pc_query {
     const ulonglong2 *Ub;   // Ub[b].x <= u of every hard leaf of b <= Ub[b].y, and Ub[b].y is
                             // also >= that bound for every later sieving prime (x > y: none)
     pc_sums *sums;          // device accumulators of this query
-    uint32_t *cnt;          // sieve counts [row * ncol + col], row = seg - seg0
-    int32_t *wgt;           // leaf weights, same layout
+    // Sieve counts and leaf weights of the sieving columns j < nb, stored as a
+    // staircase: row r (= seg - seg0) holds columns [0, row_off[r+1] -
+    // row_off[r]) from row_off[r] on, a bound on the columns that still have
+    // a hard leaf at or above the row's first integer (it never grows with r);
+    // row_off null: every row holds all nb columns, row r from r nb on.
+    const uint64_t *row_off;
+    uint32_t *cnt;          // unsieved count before p_b is crossed
+    int32_t *wgt;           // sum of -mu(m) over the leaves of the column in the row
     const uint64_t *carry;  // PC_MODE_LEAVES: exclusive carries, same layout
+    uint32_t *cntP;         // per row: the count after the last crossing (P2 column)
+    int32_t *wP;            // per row: the P2 terms landing in the row
+    const uint64_t *carryP; // PC_MODE_LEAVES: exclusive carries of cntP
     uint64_t *e_start;      // easy leaves per b: first item, count (bit 63: candidate m),
     uint64_t *e_count;      //   exclusive prefix of the counts and their total
     uint64_t *e_off;
@@ -125,21 +134,32 @@ hipError_t pc_launch_seg_split(const pc_tables &T, const pc_query &Q, uint32_t s
 // Sieve and carry scan.
 hipError_t pc_launch_sieve(const pc_sieve_args &A, uint32_t seg_log2, uint32_t wg, int mode,
                            hipStream_t s);
+// The carries of one window: per sieving column an exclusive scan of the
+// staircase rows (decoupled look-back over chunks of rows), and the same for
+// the P2 column (cntP, one workgroup).  Workgroup tickets run chunk by chunk;
+// chunk k has blkoff[k+1] - blkoff[k] blocks of 256 columns (those below the
+// chunk's first row length).
 struct pc_scan_args {
     const uint32_t *cnt;
     const int32_t *wgt;
-    uint64_t *carry_rows;     // PC_MODE_COUNT: exclusive carries per (row, col)
-    const uint64_t *carry_in; // per col, from earlier windows
-    uint64_t *carry_out;      // per col
-    uint64_t *status;         // [nchunk * ncol] look-back words, zeroed
+    const uint64_t *row_off;  // nrows + 1 (staircase, as pc_query)
+    const uint32_t *blkoff;   // nchunk + 1: first ticket of each chunk
+    uint64_t *carry_rows;     // PC_MODE_COUNT: exclusive carries, staircase layout
+    const uint32_t *cntP;
+    const int32_t *wP;
+    uint64_t *carryP;         // PC_MODE_COUNT: exclusive carries of cntP
+    const uint64_t *carry_in; // per column (nb + 1, the last one P2), from earlier windows
+    uint64_t *carry_out;      // per column, for the next window
+    uint64_t *status;         // [blkoff[nchunk] * 256] look-back words, zeroed
     uint32_t *ticket;         // zeroed
-    pc_s128 *part_hard;       // per workgroup
-    pc_s128 *part_p2;
+    pc_s128 *part_hard;       // per ticket
+    pc_s128 *part_p2;         // one
     int32_t *err;
     uint64_t nrows;
-    uint32_t ncol, nb;
-    uint32_t rows_per_chunk;
-    uint32_t nchunk, ncb;
+    uint32_t nb;
+    uint32_t rows_per_chunk;  // at most 1024
+    uint32_t nchunk;          // ceil(nrows / rows_per_chunk)
+    uint32_t nticket;         // blkoff[nchunk]
 };
 hipError_t pc_launch_scan(const pc_scan_args &A, int mode, hipStream_t s);
 

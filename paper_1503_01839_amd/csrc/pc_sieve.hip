@@ -147,6 +147,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     const uint64_t hi = lo + (2ull << LOG2_S);
     const uint64_t row = seg - A.seg0;
     const pc_query &Q = A.Qs[tile.q];
+    // this row's cells of cnt / wgt: columns [0, r_len) from r_off on (a
+    // bound on the columns that still have hard leaves at or above lo)
+    const uint64_t r_off = Q.row_off ? pc_uniform64(Q.row_off[row]) : row * Q.nb;
+    const uint32_t r_len =
+        Q.row_off ? pc_uniform((uint32_t)(Q.row_off[row + 1] - Q.row_off[row])) : Q.nb;
     const uint32_t qc = pc_uniform(Q.c);
     const uint64_t *const Xb1 = pc_uniform_ptr(Q.Xb) + qc + 1; // X_b of column j of chunk cb: Xb1[cb + j]
     const pc_tables &TB = A.T;
@@ -950,19 +955,21 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             const uint32_t v = tid < jend ? c_new[tid] : 0;
             uint32_t tot;
             const uint32_t ex = pc_block_excl_scan<T>(v, scr32, &tot);
-            if (tid < jall) {
-                const uint32_t col = cb + tid;
-                const bool cut = tid >= jend; // a count no leaf reads: 0
-                if (col >= col_lo && col < col_hi) {
-                    const uint64_t idx = row * ncol + col;
-                    if (MODE != PC_MODE_LEAVES)
-                        Q.cnt[idx] = cut ? 0u : total - ex;
-                    if (MODE == PC_MODE_TALLY)
-                        Q.wgt[idx] = cut ? 0 : c_w[tid];
-                    if (MODE == PC_MODE_LEAVES && !cut && c_w[tid] != 0)
-                        acc_carry += (pc_s128)c_w[tid] * (pc_s128)Q.carry[idx];
-                }
+            const uint32_t col = cb + tid;
+            // columns at or past the cut hold no leaf here or below: 0 (if stored)
+            if (tid < jall && col < r_len && col >= col_lo && col < col_hi) {
+                const bool cut = tid >= jend;
+                const uint64_t idx = r_off + col;
+                if (MODE != PC_MODE_LEAVES)
+                    Q.cnt[idx] = cut ? 0u : total - ex;
+                if (MODE == PC_MODE_TALLY)
+                    Q.wgt[idx] = cut ? 0 : c_w[tid];
+                if (MODE == PC_MODE_LEAVES && !cut && c_w[tid] != 0)
+                    acc_carry += (pc_s128)c_w[tid] * (pc_s128)Q.carry[idx];
             }
+            // every column before the cut must be stored: the row's bound holds
+            if (tid < jend && col >= r_len && col >= col_lo && col < col_hi)
+                atomicOr(A.err, 8);
             total -= tot;
         }
         PC_PH(7);
@@ -970,7 +977,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             // Every column from cb + jend on is past its last hard leaf: its
             // count is read by no leaf and it removes nothing a later leaf of
             // this segment counts, so its multiples are only cleared, in any
-            // order, one thread per column.  Its counts are written as 0.
+            // order, one thread per column.  Its stored counts are 0.
             for (uint32_t col = cb + jend + tid; col < ncross; col += T) {
                 const uint32_t b = qc + 1 + col;
                 const uint64_t p = TB.primes[b];
@@ -986,11 +993,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                     for (uint32_t bit = (uint32_t)((first - lo - 1) >> 1); bit < S; bit += (uint32_t)p)
                         __hip_atomic_fetch_and(&BW(bit >> 5), ~(1u << (bit & 31)), __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (MODE != PC_MODE_LEAVES && col >= cb + jall && col >= col_lo && col < col_hi) {
-                    const uint64_t idx = row * ncol + col;
-                    Q.cnt[idx] = 0;
+                if (MODE != PC_MODE_LEAVES && col >= cb + jall && col < r_len && col >= col_lo &&
+                    col < col_hi) {
+                    Q.cnt[r_off + col] = 0;
                     if (MODE == PC_MODE_TALLY)
-                        Q.wgt[idx] = 0;
+                        Q.wgt[r_off + col] = 0;
                 }
             }
             PC_PH(5);
@@ -1027,14 +1034,13 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             }
         }
         if (tid == 0) {
-            const uint64_t idx = row * ncol + Q.nb;
             const uint32_t np = k2 >= k1 ? k2 - k1 + 1 : 0;
             if (MODE != PC_MODE_LEAVES)
-                Q.cnt[idx] = total;
+                Q.cntP[row] = total;
             if (MODE == PC_MODE_TALLY)
-                Q.wgt[idx] = (int32_t)np;
+                Q.wP[row] = (int32_t)np;
             if (MODE == PC_MODE_LEAVES)
-                extra_p2 = (pc_s128)np * (pc_s128)Q.carry[idx];
+                extra_p2 = (pc_s128)np * (pc_s128)Q.carryP[row];
         }
     }
 #undef BW
@@ -1084,10 +1090,14 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
 
 // ---------------------------------------------------------------------------
 // Look-back scan over the segments of a window, independently per column:
-// carry[s][col] = carry_in[col] + sum_{s' < s} cnt[s'][col].  Workgroups take
-// tickets in order; a workgroup owns rows_per_chunk rows of 256 columns,
-// publishes its column sums, and looks back through earlier chunks until one
-// has published an inclusive prefix (decoupled look-back).
+// carry[s][col] = carry_in[col] + sum_{s' < s} cnt[s'][col], over the rows
+// that store the column (a prefix of the window's rows: row lengths never
+// grow).  Workgroups take tickets in order; ticket t is block t - blkoff[k]
+// of chunk k (256 columns by rows_per_chunk rows).  A workgroup publishes
+// its column sums and looks back through earlier chunks until one has
+// published an inclusive prefix (decoupled look-back); a column stored in a
+// chunk's first row is stored in every earlier chunk, so every look-back
+// finds its words.
 //
 // PC_MODE_TALLY needs only sum w * carry, which splits over a chunk as
 //   sum_r w_r (P + l_r) = P * sum_r w_r + sum_r w_r l_r,
@@ -1098,39 +1108,65 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
 // ---------------------------------------------------------------------------
 #define SCAN_T 256
 #define SCAN_U 8
+#define SCAN_RMAX 1024
 #define LB_A (1ull << 62)
 #define LB_P (2ull << 62)
 #define LB_V ((1ull << 62) - 1)
 
 template <int MODE> __global__ __launch_bounds__(SCAN_T) void k_scan(pc_scan_args A)
 {
-    __shared__ uint32_t s_ticket;
+    __shared__ uint32_t s_ticket, s_chunk;
+    __shared__ uint64_t s_off[SCAN_RMAX + 1];
     __shared__ pc_s128 scr[SCAN_T / 64];
-    if (threadIdx.x == 0)
-        s_ticket = atomicAdd(A.ticket, 1u);
+    if (threadIdx.x == 0) {
+        const uint32_t t = atomicAdd(A.ticket, 1u);
+        uint32_t lo = 0, hi = A.nchunk - 1; // the chunk k with blkoff[k] <= t < blkoff[k+1]
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (A.blkoff[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        s_ticket = t;
+        s_chunk = lo;
+    }
     __syncthreads();
-    const uint32_t tk = s_ticket;
-    const uint32_t rc = tk / A.ncb, cb = tk % A.ncb;
-    const uint32_t col = cb * SCAN_T + threadIdx.x;
-    const bool act = col < A.ncol;
+    const uint32_t tk = s_ticket, rc = s_chunk;
+    const uint32_t cb = tk - A.blkoff[rc];
     const uint64_t r0 = (uint64_t)rc * A.rows_per_chunk;
-    const uint64_t r1 = min(r0 + A.rows_per_chunk, A.nrows);
-    const uint64_t ncol = A.ncol;
+    const uint32_t nr = (uint32_t)min<uint64_t>(A.rows_per_chunk, A.nrows - r0);
+    for (uint32_t i = threadIdx.x; i <= nr; i += SCAN_T)
+        s_off[i] = A.row_off[r0 + i];
+    __syncthreads();
+    const uint32_t col = cb * SCAN_T + threadIdx.x;
+    // rows of the chunk that store the column: a prefix [0, na)
+    uint32_t na = 0;
+    {
+        uint32_t lo = 0, hi = nr; // the first row whose length is <= col
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid + 1] - s_off[mid] > col)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        na = lo;
+    }
+    const bool act = na > 0;
     uint64_t agg = 0, pre = 0;
     int64_t wsum = 0;   // PC_MODE_TALLY: sum of w over the chunk
     pc_s128 wl = 0;     //                sum of w * (counts of the chunk above the row)
     if (act) {
         if (MODE == PC_MODE_TALLY) {
-            const uint32_t *cp = A.cnt + r0 * ncol + col;
-            const int32_t *wp = A.wgt + r0 * ncol + col;
-            uint64_t r = r0;
-            for (; r + SCAN_U <= r1; r += SCAN_U, cp += SCAN_U * ncol, wp += SCAN_U * ncol) {
+            uint32_t i = 0;
+            for (; i + SCAN_U <= na; i += SCAN_U) {
                 uint32_t c[SCAN_U];
                 int32_t w[SCAN_U];
 #pragma unroll
                 for (uint32_t u = 0; u < SCAN_U; u++) {
-                    c[u] = cp[u * ncol];
-                    w[u] = wp[u * ncol];
+                    c[u] = A.cnt[s_off[i + u] + col];
+                    w[u] = A.wgt[s_off[i + u] + col];
                 }
 #pragma unroll
                 for (uint32_t u = 0; u < SCAN_U; u++) {
@@ -1141,19 +1177,21 @@ template <int MODE> __global__ __launch_bounds__(SCAN_T) void k_scan(pc_scan_arg
                     agg += c[u];
                 }
             }
-            for (; r < r1; r++, cp += ncol, wp += ncol) {
-                const int32_t w = *wp;
+            for (; i < na; i++) {
+                const int32_t w = A.wgt[s_off[i] + col];
                 if (w) {
                     wsum += w;
                     wl += (pc_s128)((int64_t)w * (int64_t)agg);
                 }
-                agg += *cp;
+                agg += A.cnt[s_off[i] + col];
             }
         } else {
-            for (uint64_t r = r0; r < r1; r++)
-                agg += A.cnt[r * ncol + col];
+            for (uint32_t i = 0; i < na; i++)
+                agg += A.cnt[s_off[i] + col];
         }
-        uint64_t *st = A.status + (uint64_t)rc * ncol + col;
+        // look-back words: one per (ticket, thread); chunk rc - 1 holds this
+        // column in its block cb
+        uint64_t *st = A.status + (uint64_t)tk * SCAN_T + threadIdx.x;
         if (rc == 0) {
             __hip_atomic_store(st, LB_P | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -1161,8 +1199,9 @@ template <int MODE> __global__ __launch_bounds__(SCAN_T) void k_scan(pc_scan_arg
             int64_t jc = (int64_t)rc - 1;
             uint32_t spins = 0;
             while (jc >= 0) {
-                const uint64_t v = __hip_atomic_load(A.status + (uint64_t)jc * ncol + col,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t w = ((uint64_t)A.blkoff[jc] + cb) * SCAN_T + threadIdx.x;
+                const uint64_t v =
+                    __hip_atomic_load(A.status + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint64_t f = v >> 62;
                 if (f == 0) {
                     if (++spins > (1u << 26)) { // never expected: earlier tickets always run
@@ -1181,43 +1220,80 @@ template <int MODE> __global__ __launch_bounds__(SCAN_T) void k_scan(pc_scan_arg
                                __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    pc_s128 dh = 0, dp = 0;
+    pc_s128 dh = 0;
     if (act) {
         const uint64_t P = A.carry_in[col] + pre; // carry at the chunk's first row
         if (MODE == PC_MODE_TALLY) {
-            const pc_s128 d = (pc_s128)wsum * (pc_s128)P + wl;
-            if (col == A.nb)
-                dp = d;
-            else
-                dh = d;
+            dh = (pc_s128)wsum * (pc_s128)P + wl;
         } else {
             uint64_t carry = P;
-            for (uint64_t r = r0; r < r1; r++) {
-                const uint64_t idx = r * ncol + col;
-                A.carry_rows[idx] = carry;
-                carry += A.cnt[idx];
+            for (uint32_t i = 0; i < na; i++) {
+                A.carry_rows[s_off[i] + col] = carry;
+                carry += A.cnt[s_off[i] + col];
             }
         }
-        if (rc == A.nchunk - 1)
+        // a column stored through the window's last row continues in the next window
+        if (rc == A.nchunk - 1 && na == nr)
             A.carry_out[col] = P + agg;
     }
     if (MODE == PC_MODE_TALLY) {
         dh = pc_block_sum128<SCAN_T>(dh, scr);
-        dp = pc_block_sum128<SCAN_T>(dp, scr);
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0)
             A.part_hard[tk] = dh;
-            A.part_p2[tk] = dp;
+    }
+}
+
+// The P2 column: carry = carry_in + sum of cntP over the rows above, and
+// sum wP * carry (PC_MODE_TALLY) or every carry (PC_MODE_COUNT); one
+// workgroup, each thread a run of consecutive rows.
+#define SCANP_T 1024
+template <int MODE> __global__ __launch_bounds__(SCANP_T) void k_scan_p2(pc_scan_args A)
+{
+    __shared__ uint64_t scr[SCANP_T / 64];
+    __shared__ pc_s128 scr128[SCANP_T / 64];
+    const uint64_t per = (A.nrows + SCANP_T - 1) / SCANP_T;
+    const uint64_t r0 = min<uint64_t>(A.nrows, threadIdx.x * per), r1 = min(A.nrows, r0 + per);
+    uint64_t agg = 0;
+    for (uint64_t r = r0; r < r1; r++)
+        agg += A.cntP[r];
+    uint64_t tot;
+    uint64_t carry = A.carry_in[A.nb] + pc_block_excl_scan<SCANP_T>(agg, scr, &tot);
+    pc_s128 acc = 0;
+    for (uint64_t r = r0; r < r1; r++) {
+        if (MODE == PC_MODE_TALLY) {
+            const int32_t w = A.wP[r];
+            if (w)
+                acc += (pc_s128)w * (pc_s128)carry;
+        } else {
+            A.carryP[r] = carry;
         }
+        carry += A.cntP[r];
+    }
+    if (threadIdx.x == 0)
+        A.carry_out[A.nb] = A.carry_in[A.nb] + tot;
+    if (MODE == PC_MODE_TALLY) {
+        acc = pc_block_sum128<SCANP_T>(acc, scr128);
+        if (threadIdx.x == 0)
+            *A.part_p2 = acc;
     }
 }
 
 hipError_t pc_launch_scan(const pc_scan_args &A, int mode, hipStream_t s)
 {
-    const uint32_t nwg = A.nchunk * A.ncb;
-    if (mode == PC_MODE_TALLY)
-        k_scan<PC_MODE_TALLY><<<nwg, SCAN_T, 0, s>>>(A);
-    else
-        k_scan<PC_MODE_COUNT><<<nwg, SCAN_T, 0, s>>>(A);
+    if (A.nrows == 0)
+        return hipSuccess;
+    if (A.rows_per_chunk == 0 || A.rows_per_chunk > SCAN_RMAX ||
+        (uint64_t)A.nchunk * A.rows_per_chunk < A.nrows)
+        return hipErrorInvalidValue;
+    if (mode == PC_MODE_TALLY) {
+        if (A.nticket)
+            k_scan<PC_MODE_TALLY><<<A.nticket, SCAN_T, 0, s>>>(A);
+        k_scan_p2<PC_MODE_TALLY><<<1, SCANP_T, 0, s>>>(A);
+    } else {
+        if (A.nticket)
+            k_scan<PC_MODE_COUNT><<<A.nticket, SCAN_T, 0, s>>>(A);
+        k_scan_p2<PC_MODE_COUNT><<<1, SCANP_T, 0, s>>>(A);
+    }
     return hipGetLastError();
 }
 

@@ -101,9 +101,10 @@ def test_config_invariance(pc, seg, wg):
 
 def test_windows(pc):
     # a tiny carry budget forces many windows; carries must chain across them
+    # (the stored counts of 1e12 at y = 1e4 take about 64 KiB in all)
     x, y = 10**12, 10**4
     o = O.decompose(x, y, 6, hard=O.HARD_SIEVE)
-    for budget in (1 << 16, 1 << 18, 1 << 20):
+    for budget in (1 << 12, 1 << 14, 1 << 15):
         say("case: windows", budget)
         r = pc.decompose(x, y, carry_budget=budget)
         assert r.windows > 1
