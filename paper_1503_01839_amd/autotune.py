@@ -18,6 +18,15 @@ decade (seeded) in the least time.
     python -m paper_1503_01839_amd.autotune --sweep 16 --alphas 1,2,4,8
                                             # every alpha x shape at x = 10^16, print only
 
+Every candidate's result is checked before its time counts: pi(x) must be the
+same at every alpha and shape of a half decade (the paper's own check of its
+values, Section 5), must equal Table 1 where x is a power of ten, and a
+batch must return the same values at every alpha it is timed at; any
+disagreement stops the tuner.  Segments of 128 KiB are not among the shapes:
+the library builds 32 and 64 KiB segments only (the 64 KiB ones already run
+30-55% slower than 32 KiB at 1e16 and 1e18, and 128 KiB would leave one
+workgroup per CU).
+
 Rebuild the library afterwards (__graft_entry__.build())."""
 from __future__ import annotations
 
@@ -33,6 +42,23 @@ BATCH_HI = 16.0   # half decades above take the single-query alpha in batches
 BATCH_SEED = 1503
 
 
+def table1() -> dict[int, int]:
+    """pi(10^n) of the paper's Table 1 (tests/golden/paper_pi_pow10.txt)."""
+    path = os.path.join(os.path.dirname(HERE), "tests", "golden", "paper_pi_pow10.txt")
+    out = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                n, v = line.split()
+                out[10 ** int(n)] = int(v)
+    return out
+
+
+class ResultMismatch(RuntimeError):
+    """A tuning candidate returned a different pi(x)."""
+
+
 def candidates(log10x: float) -> list[float]:
     """alpha values worth timing at this size (small alpha at large x means a
     sieve too long to be competitive, and minutes of tuning)."""
@@ -42,16 +68,24 @@ def candidates(log10x: float) -> list[float]:
 
 def tune(lo: float = 7.0, hi: float = 19.0, reps: int = 3, log=print):
     import paper_1503_01839_amd as pc
+    tab1 = table1()
     table = []
     d = lo
     while d <= hi + 1e-9:
         x = int(10 ** d)
         n = reps if d < 17 else 2
+        want = [tab1.get(x)]  # pi(x): Table 1's, else the first candidate's
 
         def time(a, seg, wg):
             kw = dict(alpha=a, segment_kib=seg, wg_size=wg)
-            pc.pi_count_ex(x, **kw)  # tables sized for this alpha
-            return statistics.median(pc.pi_count_ex(x, **kw).ms_total for _ in range(n))
+            rs = [pc.pi_count_ex(x, **kw) for _ in range(n + 1)]  # the first sizes the tables
+            for r in rs:
+                if want[0] is None:
+                    want[0] = r.pi
+                if r.pi != want[0]:
+                    raise ResultMismatch(f"pi({x}) = {r.pi} at alpha {a}, shape ({seg}, {wg}); "
+                                         f"expected {want[0]}")
+            return statistics.median(r.ms_total for r in rs[1:])
         best = None
         for a in candidates(d):
             t = time(a, *SHAPES[0])
@@ -90,15 +124,21 @@ def tune_batch(table, reps: int = 2, log=print):
             continue
         xs = batch_queries(d)
         best = None
+        first = None
         for ab in candidates(d):
             ref = pc.pi_count_batch(xs, alpha=ab)  # tables sized for this alpha
+            if first is None:
+                first = ref
+            if ref != first:
+                raise ResultMismatch(f"batch results at alpha {ab} differ from the first alpha's "
+                                     f"(log10 x = {d})")
             ts = []
             for _ in range(reps):
                 s = time.perf_counter()
                 r = pc.pi_count_batch(xs, alpha=ab)
                 ts.append((time.perf_counter() - s) * 1e3)
                 if r != ref:
-                    raise RuntimeError("batch results changed between runs")
+                    raise ResultMismatch("batch results changed between runs")
             tb = min(ts)
             log(f"  batch log10 x = {d:4.1f} n = {len(xs)} alpha {ab:5.1f}: {tb:9.2f} ms", flush=True)
             if best is None or tb < best[1]:
@@ -146,11 +186,17 @@ def sweep(log10x: float, alphas, reps: int = 5, log=print):
     """pi(10^log10x) at every alpha x shape (median of reps, tables cached)."""
     import paper_1503_01839_amd as pc
     x = int(round(10 ** log10x))
+    want = table1().get(x)
     for a in alphas:
         for seg, wg in SHAPES:
             kw = dict(alpha=a, segment_kib=seg, wg_size=wg)
             r = pc.pi_count_ex(x, **kw)  # tables sized for this alpha
-            t = statistics.median(pc.pi_count_ex(x, **kw).ms_total for _ in range(reps))
+            if want is None:
+                want = r.pi
+            rs = [pc.pi_count_ex(x, **kw) for _ in range(reps)]
+            if any(q.pi != r.pi for q in rs) or (want is not None and r.pi != want):
+                raise ResultMismatch(f"pi({x}) differs at alpha {a}, shape ({seg}, {wg})")
+            t = statistics.median(q.ms_total for q in rs)
             log(f"  log10 x = {log10x:4.1f} alpha {a:5.1f} segment {seg} KiB workgroup {wg:4d}: "
                 f"{t:9.2f} ms  (y = {r.y}, {r.segments} segments, pi = {r.pi})", flush=True)
 

@@ -117,8 +117,9 @@ __global__ __launch_bounds__(BT) void k_easy_b(pc_tables T, const pc_query *Qs, 
 }
 
 // Carries of whole queries (every row of a query in one pass): block i scans
-// the columns [256 cb, 256 cb + 256) of query q down the rows in order,
-// carry = sum of the counts above, and adds sum w * carry to the query.
+// the columns [256 cb, 256 cb + 256) of query q down the rows that store them
+// (a prefix of the rows: row lengths never grow), carry = sum of the counts
+// above, and adds sum w * carry to the query.
 __global__ __launch_bounds__(BT) void k_scan_rows_b(const pc_query *Qs, pc_blk B)
 {
     __shared__ pc_s128 scr[BT / 64];
@@ -129,13 +130,15 @@ __global__ __launch_bounds__(BT) void k_scan_rows_b(const pc_query *Qs, pc_blk B
     pc_s128 dh = 0, dp = 0;
     const uint64_t nrows = Q.nseg, nb = Q.nb;
     uint64_t carry = 0;
-    if (col < nb) { // a sieving column: row r holds it at r nb + col
+    if (col < nb) { // a sieving column: row r holds it at row_off[r] + col
         for (uint64_t r = 0; r < nrows; r++) {
-            const uint64_t idx = r * nb + col;
-            const int32_t w = Q.wgt[idx];
+            const uint64_t o = Q.row_off[r];
+            if (col >= Q.row_off[r + 1] - o)
+                break;
+            const int32_t w = Q.wgt[o + col];
             if (w)
                 dh += (pc_s128)w * (pc_s128)carry;
-            carry += Q.cnt[idx];
+            carry += Q.cnt[o + col];
         }
     } else if (col == nb) { // the P2 column
         for (uint64_t r = 0; r < nrows; r++) {

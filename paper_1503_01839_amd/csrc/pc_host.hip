@@ -121,6 +121,11 @@ struct Tables {
     bool wheel_ok[kWheelC + 1] = {};
     uint32_t pattern_bits[kWheelC + 1] = {}, Qc[kWheelC + 1] = {}, phiQ[kWheelC + 1] = {};
     DevBuf lk_in, lk_out, chk;
+    // the first entries of the device pi table, read back for planning the
+    // count staircase on the host (pi at isqrt(x / lo) < 2^24: x < 2^64 and
+    // every segment but the first starts at lo >= 2^16)
+    std::vector<uint2> pi_host;
+    uint64_t pi_host_max = 0; // pi_host answers n <= pi_host_max
 };
 Tables g_T;
 
@@ -207,6 +212,27 @@ void ensure_pi(uint64_t need)
     T.pi_limit = covered;
     T.nprimes = lookup({covered})[0];
     T.recip_n = 0; // the primes array was rebuilt
+    const uint64_t nh = std::min<uint64_t>(nent, (1ull << 24) / 64);
+    T.pi_host.resize(nh);
+    hipck(hipMemcpyAsync(T.pi_host.data(), T.pitab.p, nh * 8, hipMemcpyDeviceToHost, g_stream),
+          "D2H");
+    hipck(hipStreamSynchronize(g_stream), "sync");
+    T.pi_host_max = 64 * nh - 1;
+}
+
+// Row lengths of the count staircase of a query (x, c, nb): a hard leaf of
+// p_b has u < x / p_b^2, so the row whose first integer is lo > 0 keeps the
+// columns of the primes p_b <= isqrt(x / lo); the first row keeps all nb.
+uint32_t row_len(uint64_t x, uint32_t c, uint32_t nb, uint64_t lo)
+{
+    if (lo == 0)
+        return nb;
+    const uint64_t v = pc_isqrt(x / lo);
+    const Tables &T = g_T;
+    if (v > T.pi_host_max)
+        fail(PC_EINTERNAL, "row length beyond the host copy of the pi table");
+    const uint64_t pv = pc_pi_lookup(T.pi_host.data(), v);
+    return (uint32_t)std::min<uint64_t>(nb, pv > c ? pv - c : 0);
 }
 
 void ensure_recip(uint64_t kmax)
@@ -338,6 +364,8 @@ void drop_tables()
     }
     T.base_ok = false;
     T.pi_limit = T.nprimes = T.recip_n = T.y_limit = 0;
+    T.pi_host.clear();
+    T.pi_host_max = 0;
 }
 
 void drop_query_bufs()
@@ -714,17 +742,9 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     // Row lengths of the count staircase: a hard leaf of p_b has u < x / p_b^2,
     // so row r (first integer lo_r) stores the columns of the primes
     // p_b <= isqrt(x / lo_r), and the first row stores every column.
-    std::vector<uint32_t> rowlen(nseg, Q.nb);
-    if (nseg > 1) {
-        std::vector<uint64_t> pts(nseg - 1);
-        for (uint64_t r = 1; r < nseg; r++) {
-            const uint64_t lo_r = r < nA ? r * 2 * SA : baseB + (r - nA) * 2 * S;
-            pts[r - 1] = pc_isqrt(x / lo_r);
-        }
-        const std::vector<uint64_t> pv = lookup(pts);
-        for (uint64_t r = 1; r < nseg; r++)
-            rowlen[r] = (uint32_t)std::min<uint64_t>(Q.nb, pv[r - 1] > c ? pv[r - 1] - c : 0);
-    }
+    std::vector<uint32_t> rowlen(nseg);
+    for (uint64_t r = 0; r < nseg; r++)
+        rowlen[r] = row_len(x, c, Q.nb, r < nA ? r * 2 * SA : baseB + (r - nA) * 2 * S);
     // windows of rows within the carry budget (cells of cnt and w, or of cnt
     // and the carries, plus the P2 column's per-row words)
     const uint64_t per_cell = K.two_pass ? 12 : 8, per_row = K.two_pass ? 12 : 8;
@@ -1104,11 +1124,12 @@ constexpr uint32_t kBatchWG = 512;
 size_t r256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // A query's chunk of a round arena: X_b, Ub, three easy arrays, e_clu,
-// counts, weights, each rounded up to 256 bytes exactly as round_queries
-// takes them.
-size_t query_chunk(const BatchQuery &b)
+// counts and weights (cells of the count staircase), the P2 column's counts
+// and weights, each rounded up to 256 bytes exactly as round_queries takes
+// them.
+size_t query_chunk(const BatchQuery &b, uint64_t cells)
 {
-    const size_t na = b.a + 2, cells = b.nseg * b.nb;
+    const size_t na = b.a + 2;
     return r256(na * 8) + 2 * r256(na * 16) + 3 * r256(na * 8) + 2 * r256(cells * 4) +
            2 * r256(b.nseg * 4);
 }
@@ -1119,6 +1140,9 @@ size_t query_chunk(const BatchQuery &b)
 struct RoundPlan {
     size_t arena = 0, o_sums = 0, o_et = 0, o_fin = 0;
     std::vector<size_t> o_q;
+    std::vector<uint64_t> roff;   // every query's row offsets (nseg + 1 each), uploaded
+    std::vector<size_t> o_roff;   // where each query's offsets start in roff
+    std::vector<uint64_t> cells;  // stored cells of each query's staircase
     std::vector<pc_tile> tiles;
     std::vector<uint32_t> blk;
     size_t t_xb = 0, t_s1 = 0, t_ez = 0, t_sc = 0;
@@ -1130,7 +1154,7 @@ struct RoundPlan {
 // its copies read from.
 struct BatchSlot {
     hipStream_t st = nullptr;
-    DevBuf arena, qs, tiles, blk, err;
+    DevBuf arena, qs, tiles, blk, roff, err;
     pc_final *h_fin = nullptr; // pinned
     size_t h_fin_cap = 0;
     int32_t *h_err = nullptr;  // pinned
@@ -1172,7 +1196,7 @@ void slot_release(BatchSlot &sl)
 {
     if (sl.st)
         (void)hipStreamSynchronize(sl.st);
-    for (DevBuf *b : {&sl.arena, &sl.qs, &sl.tiles, &sl.blk, &sl.err})
+    for (DevBuf *b : {&sl.arena, &sl.qs, &sl.tiles, &sl.blk, &sl.roff, &sl.err})
         if (b->p) {
             (void)hipFree(b->p);
             g_dev_bytes -= b->cap;
@@ -1203,9 +1227,24 @@ void plan_round(const std::vector<BatchQuery> &R, RoundPlan &P)
     P.o_sums = take(nq * sizeof(pc_sums));
     P.o_et = take(nq * 8);
     P.o_fin = take(nq * sizeof(pc_final));
+    // each query's count staircase (rows of 2S integers from 0)
+    P.roff.clear();
+    P.o_roff.resize(nq);
+    P.cells.resize(nq);
+    for (uint32_t i = 0; i < nq; i++) {
+        const BatchQuery &b = R[i];
+        P.o_roff[i] = P.roff.size();
+        uint64_t off = 0;
+        P.roff.push_back(0);
+        for (uint64_t r = 0; r < b.nseg; r++) {
+            off += row_len(b.x, b.c, b.nb, r * (2ull << kBatchLog2S));
+            P.roff.push_back(off);
+        }
+        P.cells[i] = off;
+    }
     P.o_q.resize(nq);
     for (uint32_t i = 0; i < nq; i++)
-        P.o_q[i] = take(query_chunk(R[i]));
+        P.o_q[i] = take(query_chunk(R[i], P.cells[i]));
 
     P.blk.clear();
     auto table = [&](auto nblocks_of, uint32_t *nblocks) {
@@ -1247,9 +1286,10 @@ void plan_round(const std::vector<BatchQuery> &R, RoundPlan &P)
             P.tiles.push_back(pc_tile{(uint32_t)sg, 0, R[i].ncol, i});
 }
 
-// The round's per-query scalars, with their arrays carved out of the arena at base.
+// The round's per-query scalars, with their arrays carved out of the arena at
+// base; roff: the device copy of P.roff.
 void round_queries(const std::vector<BatchQuery> &R, const RoundPlan &P, char *base,
-                   const pc_tables &T, std::vector<pc_query> &Qv)
+                   const uint64_t *roff, const pc_tables &T, std::vector<pc_query> &Qv)
 {
     const uint32_t nq = (uint32_t)R.size();
     const uint64_t S = 1ull << kBatchLog2S;
@@ -1259,7 +1299,7 @@ void round_queries(const std::vector<BatchQuery> &R, const RoundPlan &P, char *b
         const BatchQuery &b = R[i];
         pc_query &Q = Qv[i];
         size_t o = P.o_q[i];
-        const size_t o_end = P.o_q[i] + query_chunk(b);
+        const size_t o_end = P.o_q[i] + query_chunk(b, P.cells[i]);
         auto carve = [&](size_t bytes) {
             char *p = base + o;
             o += r256(bytes);
@@ -1289,9 +1329,9 @@ void round_queries(const std::vector<BatchQuery> &R, const RoundPlan &P, char *b
         Q.e_count = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_off = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_clu = reinterpret_cast<uint4 *>(carve(na * 16));
-        Q.row_off = nullptr; // every row holds all nb sieving columns
-        Q.cnt = reinterpret_cast<uint32_t *>(carve(b.nseg * b.nb * 4));
-        Q.wgt = reinterpret_cast<int32_t *>(carve(b.nseg * b.nb * 4));
+        Q.row_off = roff + P.o_roff[i];
+        Q.cnt = reinterpret_cast<uint32_t *>(carve(P.cells[i] * 4));
+        Q.wgt = reinterpret_cast<int32_t *>(carve(P.cells[i] * 4));
         Q.cntP = reinterpret_cast<uint32_t *>(carve(b.nseg * 4));
         Q.wP = reinterpret_cast<int32_t *>(carve(b.nseg * 4));
         Q.carryP = nullptr;
@@ -1349,8 +1389,9 @@ void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
     RoundPlan &P = sl.plan;
     plan_round(R, P);
     slot_ensure(sl, sl.arena, P.arena, "batch arena");
+    slot_ensure(sl, sl.roff, P.roff.size() * 8, "batch row offsets");
     char *base = static_cast<char *>(sl.arena.p);
-    round_queries(R, P, base, T, sl.Qv);
+    round_queries(R, P, base, ptr<uint64_t>(sl.roff), T, sl.Qv);
 
     slot_ensure(sl, sl.qs, nq * sizeof(pc_query), "batch queries");
     slot_ensure(sl, sl.tiles, P.tiles.size() * sizeof(pc_tile), "batch tiles");
@@ -1374,6 +1415,8 @@ void submit_round(BatchSlot &sl, const Knobs &K, bool use_graph)
                          hipMemcpyHostToDevice, st),
           "H2D");
     hipck(hipMemcpyAsync(sl.blk.p, P.blk.data(), P.blk.size() * 4, hipMemcpyHostToDevice, st),
+          "H2D");
+    hipck(hipMemcpyAsync(sl.roff.p, P.roff.data(), P.roff.size() * 8, hipMemcpyHostToDevice, st),
           "H2D");
     auto launches = [&]() {
         round_launches(P, nq, base, T, ptr<pc_query>(sl.qs), ptr<pc_tile>(sl.tiles),
@@ -1554,7 +1597,7 @@ void run_batch(const uint64_t *xs, size_t n, const Knobs &K, double alpha, bool 
 struct AsyncRound {
     std::vector<BatchQuery> R;
     RoundPlan P;
-    size_t o_qs = 0, o_tiles = 0, o_blk = 0, o_pos = 0;
+    size_t o_qs = 0, o_tiles = 0, o_blk = 0, o_pos = 0, o_roff = 0;
 };
 
 struct AsyncPlan {
@@ -1617,6 +1660,7 @@ void async_layout(const uint64_t *xs, size_t n, const std::vector<BatchQuery> &b
         r.o_tiles = take(r.P.tiles.size() * sizeof(pc_tile));
         r.o_blk = take(r.P.blk.size() * 4);
         r.o_pos = take(r.R.size() * 8);
+        r.o_roff = take(r.P.roff.size() * 8);
         arena = std::max(arena, r.P.arena);
     }
     A.o_kv = take(A.nkv * 16);
@@ -1702,7 +1746,8 @@ void async_queue(const AsyncPlan &A, const std::vector<ulonglong2> &kv, char *im
     const pc_tables T = tables_view(kWheelC);
     std::vector<pc_query> Qv;
     for (const AsyncRound &r : A.rounds) {
-        round_queries(r.R, r.P, arena, T, Qv);
+        round_queries(r.R, r.P, arena, reinterpret_cast<const uint64_t *>(ws + r.o_roff), T, Qv);
+        memcpy(img + r.o_roff, r.P.roff.data(), r.P.roff.size() * 8);
         memcpy(img + r.o_qs, Qv.data(), Qv.size() * sizeof(pc_query));
         memcpy(img + r.o_tiles, r.P.tiles.data(), r.P.tiles.size() * sizeof(pc_tile));
         memcpy(img + r.o_blk, r.P.blk.data(), r.P.blk.size() * 4);

@@ -249,37 +249,35 @@ hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, uint32_t n, 
 
 // ---------------------------------------------------------------------------
 // mu(n)*lpf(n) for n <= ymax by a segmented factor sieve.  Each workgroup owns
-// 4096 consecutive n; the primes <= sqrt(ymax) are applied in increasing order
-// (one barrier each) so the first prime to touch n is its least prime factor.
-// A cofactor left above 1 is one prime > sqrt(ymax).
+// 4096 consecutive n; the primes <= sqrt(ymax) (all below 2^16) are applied in
+// increasing order (one barrier each), so the first prime to touch n is its
+// least prime factor.  A cofactor left above 1 is one prime > sqrt(ymax).
 //
-// Within one prime p, the thread that flips the sign of mu[i] (i a multiple of
-// p) and the thread that marks i as divisible by p^2 are in general different
-// threads, often of different wavefronts, with no barrier between them.  The
-// square marks therefore go to their own array, which nothing reads until the
-// last barrier: each word of lpf, prod and mu has one writer per prime, and sq
-// only ever receives stores of 1.  (A read-modify-write of mu interleaved with
-// a store of 0 to the same word by another wavefront would otherwise leave a
-// non-squarefree n marked squarefree.)
-// ---------------------------------------------------------------------------
+// Per n one state word: bits 0-15 the least prime factor, bit 16 the sign of
+// mu, bit 17 set once some p^2 divides n.  Within one prime p, the thread that
+// records p for a multiple of p and the thread that marks a multiple of p^2
+// are in general different threads, often of different wavefronts, with no
+// barrier between them; both update the word with LDS atomics (xor, or), so
+// neither update can be lost.  (A plain read-modify-write interleaved with
+// the other thread's update would lose it, and a non-squarefree n would be
+// taken as squarefree.)  The product of n's small prime factors has one
+// writer per prime.
 #define MF_N 4096
 #define MF_T 256
+#define MF_SIGN (1u << 16)
+#define MF_SQ (1u << 17)
 
 __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t nsmall,
                                                uint64_t ymax, int32_t *out)
 {
-    __shared__ uint32_t lpf[MF_N];
+    __shared__ uint32_t st[MF_N];
     __shared__ uint32_t prod[MF_N];
-    __shared__ int32_t mu[MF_N];
-    __shared__ uint8_t sq[MF_N];            // 1: some p^2 divides n
     __shared__ uint32_t f1[MF_T], f2[MF_T]; // first multiples of p and p^2 in the block
     const uint32_t t = threadIdx.x;
     const uint32_t n0 = blockIdx.x * MF_N; // ymax < 2^31: every n fits 32 bits
     for (uint32_t i = t; i < MF_N; i += MF_T) {
-        lpf[i] = 0;
+        st[i] = 0;
         prod[i] = 1;
-        mu[i] = 1;
-        sq[i] = 0;
     }
     for (uint32_t k0 = 1; k0 <= nsmall; k0 += MF_T) {
         // the offsets of the next MF_T primes, one per thread
@@ -300,16 +298,16 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
         for (uint32_t k = k0; k < kend; k++) {
             const uint32_t p = primes[k];
             for (uint32_t i = f1[k - k0] + t * p; i < MF_N; i += MF_T * p) {
-                if (lpf[i] == 0)
-                    lpf[i] = p;
+                // bits 0-15 change only here, by this thread, while p is applied
+                const uint32_t lp = (st[i] & 0xFFFFu) ? 0u : p;
+                atomicXor(&st[i], MF_SIGN | lp);
                 prod[i] *= p;
-                mu[i] = -mu[i];
             }
             const uint32_t o2 = f2[k - k0];
             if (o2 != 0xFFFFFFFFu) {
                 const uint64_t pp = (uint64_t)p * p;
                 for (uint64_t i = o2 + (uint64_t)t * pp; i < MF_N; i += MF_T * pp)
-                    sq[i] = 1;
+                    atomicOr(&st[i], MF_SQ);
             }
             __syncthreads();
         }
@@ -325,8 +323,9 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
         } else if (n == 1) {
             v = 0x7FFFFFFF;
         } else {
-            int32_t m = sq[i] ? 0 : mu[i];
-            uint32_t l = lpf[i];
+            const uint32_t w = st[i];
+            int32_t m = (w & MF_SQ) ? 0 : ((w & MF_SIGN) ? -1 : 1);
+            uint32_t l = w & 0xFFFFu;
             if (m != 0 && prod[i] < n) {
                 uint32_t big = (uint32_t)n / prod[i];
                 m = -m;
