@@ -74,26 +74,41 @@ __global__ __launch_bounds__(BT) void k_leaf_setup_b(pc_tables T, const pc_query
     }
 }
 
-// e_off = exclusive prefix of the easy item counts of b = 0..a, one workgroup
-// per query, in chunks of BT entries; then the suffix maxima of the hard-leaf
-// u ranges (pc_ub_suffix).
-__global__ __launch_bounds__(BT) void k_escan_b(const pc_query *Qs)
+// Exclusive prefix of the counts cnt[0..n) (mode bit stripped) into off
+// (which may be cnt itself), the total into *total; the calling workgroup does
+// one query in chunks of BT.
+__device__ __forceinline__ void pc_escan(const pc_query &Q, const uint64_t *cnt, uint64_t *off,
+                                         uint32_t n, uint64_t *total, uint64_t *scr)
+{
+    uint64_t run = 0;
+    for (uint32_t i0 = 0; i0 < n; i0 += BT) {
+        const uint32_t i = i0 + threadIdx.x;
+        const uint64_t v = i < n ? cnt[i] & ~PC_MODEBIT : 0;
+        uint64_t tot;
+        const uint64_t ex = pc_block_excl_scan<BT>(v, scr, &tot);
+        if (i < n)
+            off[i] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0)
+        *total = run;
+}
+
+// The easy leaves' offsets (candidates: e_off, e_total[0]) and bands
+// (singles and groups: e_bk, e_boff, e_total[1], e_total[2]), one workgroup
+// per query; then the suffix maxima of the hard-leaf u ranges (pc_ub_suffix).
+__global__ __launch_bounds__(BT) void k_escan_b(pc_tables T, const pc_query *Qs)
 {
     __shared__ uint64_t scr[BT / 64];
     __shared__ uint64_t sh[BT];
     const pc_query &Q = Qs[blockIdx.x];
-    uint64_t run = 0;
-    for (uint32_t b0 = 0; b0 <= Q.a; b0 += BT) {
-        const uint32_t b = b0 + threadIdx.x;
-        const uint64_t v = b <= Q.a ? Q.e_count[b] & ~PC_MODEBIT : 0;
-        uint64_t tot;
-        const uint64_t ex = pc_block_excl_scan<BT>(v, scr, &tot);
-        if (b <= Q.a)
-            Q.e_off[b] = run + ex;
-        run += tot;
-    }
-    if (threadIdx.x == 0)
-        *Q.e_total = run;
+    pc_escan(Q, Q.e_count, Q.e_off, Q.a + 1, Q.e_total, scr);
+    const uint32_t nband = Q.a / PC_EZ_BAND + 1;
+    for (uint32_t g = threadIdx.x; g < nband; g += BT)
+        pc_easy_band_item(T, Q, g);
+    __syncthreads();
+    pc_escan(Q, Q.e_boff, Q.e_boff, nband, Q.e_total + 1, scr);
+    pc_escan(Q, Q.e_boff + nband, Q.e_boff + nband, nband, Q.e_total + 2, scr);
     pc_ub_suffix<BT>(Q, sh);
 }
 
@@ -101,13 +116,15 @@ __global__ __launch_bounds__(BT) void k_easy_b(pc_tables T, const pc_query *Qs, 
 {
     __shared__ pc_s128 scr[BT / 64];
     __shared__ unsigned long long scr64[BT / 64];
-    __shared__ uint32_t s_b0;
+    __shared__ uint32_t s_b0, s_g[2];
     uint32_t q, lb, nlb;
     pc_blk_of(B, &q, &lb, &nlb);
     const pc_query &Q = Qs[q];
     unsigned long long nleaf = 0;
     int64_t acc = 0;
     pc_easy_tiles<BT, BEZ_PER>(T, Q, lb, nlb, &s_b0, &acc, &nleaf);
+    pc_easy_bands<BT, false>(T, Q, lb, nlb, &s_g[0], &acc);
+    pc_easy_bands<BT, true>(T, Q, lb, nlb, &s_g[1], &acc);
     const pc_s128 s = pc_block_sum128<BT>((pc_s128)acc, scr);
     nleaf = pc_block_sum<BT>(nleaf, scr64);
     if (threadIdx.x == 0) {
@@ -190,7 +207,7 @@ hipError_t pc_launch_batch_setup(const pc_tables &T, const pc_query *Qs, const u
     k_xb_b<<<nb_xb, BT, 0, s>>>(T, Qs, pc_blk{bq_xb, bf_xb});
     k_s1_b<<<nb_s1, BT, 0, s>>>(T, Qs, pc_blk{bq_s1, bf_s1});
     k_leaf_setup_b<<<nb_xb, BT, 0, s>>>(T, Qs, pc_blk{bq_xb, bf_xb});
-    k_escan_b<<<nq, BT, 0, s>>>(Qs);
+    k_escan_b<<<nq, BT, 0, s>>>(T, Qs);
     return hipGetLastError();
 }
 

@@ -78,6 +78,25 @@ __device__ __forceinline__ uint32_t pc_quot32(uint64_t n, double nd, uint32_t d)
     return q - (rem < 0 ? 1u : 0u);
 }
 
+// pc_quot32 for divisors d < 2^31, with rd = 1/d correctly rounded (a table
+// entry): the estimate's error is then below 2^-19, well under the same 2^-10
+// margin, and the remainder n - q d of the estimate q lies in [-d, d), so its
+// low 32 bits read as a signed number are its value.
+__device__ __forceinline__ uint32_t pc_quot31r(uint64_t n, double nd, uint32_t d, double rd)
+{
+    const uint32_t q = (uint32_t)__builtin_fma(nd, rd, 0x1p-10);
+    const int32_t rem = (int32_t)((uint32_t)n - q * d);
+    return q - (rem < 0 ? 1u : 0u);
+}
+
+// pc_quot31r with 1/d from pc_rcp_f64.
+__device__ __forceinline__ uint32_t pc_quot31(uint64_t n, double nd, uint32_t d)
+{
+    const uint32_t q = (uint32_t)__builtin_fma(nd, pc_rcp_f64(d), 0x1p-10);
+    const int32_t rem = (int32_t)((uint32_t)n - q * d);
+    return q - (rem < 0 ? 1u : 0u);
+}
+
 // floor(n / d) - base for 1 <= d < 2^32, base < 2^47, n/d < 2^47:
 // returns false if the quotient lies outside [base, base + span), span <
 // 2^30, else true with *off = the quotient - base.  nd = (double)n.

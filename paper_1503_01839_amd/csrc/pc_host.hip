@@ -113,7 +113,7 @@ struct Tables {
     DevBuf pitab, primes, cnt_tmp, scan_tmp;
     uint64_t pi_limit = 0; // pi table and primes cover n <= pi_limit
     uint64_t nprimes = 0;
-    DevBuf recip;
+    DevBuf recip, rcpd;
     uint64_t recip_n = 0;
     DevBuf mulpf;
     uint64_t y_limit = 0;
@@ -130,7 +130,8 @@ struct Tables {
 Tables g_T;
 
 struct QueryBufs {
-    DevBuf Ub, Xb, e_start, e_count, e_off, e_tmp, e_total, e_clu, part, sums, fin, qdev;
+    DevBuf Ub, Xb, Xd, e_start, e_count, e_off, e_scount, e_bk, e_boff, e_tmp, e_total, e_clu,
+        part, sums, fin, qdev;
     DevBuf work, hot, bounds, tiles_a, trace;
     DevBuf tiles, cnt, wgt, carry_rows, carry_a, carry_b, status, ticket, part_tile_h,
         part_tile_p, part_scan_h, part_scan_p, err;
@@ -242,7 +243,9 @@ void ensure_recip(uint64_t kmax)
         return;
     uint64_t k = std::min<uint64_t>(T.nprimes, std::max<uint64_t>(kmax, 2 * T.recip_n));
     ensure(T.recip, (k + 1) * 8, "reciprocals");
-    hipck(pc_launch_recip(ptr<uint32_t>(T.primes), ptr<uint64_t>(T.recip), (uint32_t)k, g_stream),
+    ensure(T.rcpd, (k + 1) * 8, "reciprocals");
+    hipck(pc_launch_recip(ptr<uint32_t>(T.primes), ptr<uint64_t>(T.recip), ptr<double>(T.rcpd),
+                          (uint32_t)k, g_stream),
           "reciprocals");
     T.recip_n = k;
 }
@@ -337,6 +340,7 @@ pc_tables tables_view(uint32_t c)
     pc_tables v{};
     v.primes = ptr<uint32_t>(T.primes);
     v.recip = ptr<uint64_t>(T.recip);
+    v.rcpd = ptr<double>(T.rcpd);
     v.pitab = ptr<uint2>(T.pitab);
     v.mulpf = ptr<int32_t>(T.mulpf);
     v.pattern = ptr<uint32_t>(T.pattern[c]);
@@ -353,7 +357,7 @@ void drop_tables()
 {
     Tables &T = g_T;
     DevBuf *all[] = {&T.base, &T.nbase_d, &T.pitab, &T.primes, &T.cnt_tmp, &T.scan_tmp, &T.recip,
-                     &T.mulpf, &T.lk_in, &T.lk_out, &T.chk};
+                     &T.rcpd, &T.mulpf, &T.lk_in, &T.lk_out, &T.chk};
     for (DevBuf *b : all)
         dfree(*b);
     for (int c = 0; c <= kWheelC; c++) {
@@ -371,7 +375,7 @@ void drop_tables()
 void drop_query_bufs()
 {
     QueryBufs &B = g_Q;
-    DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.e_start, &B.e_count, &B.e_off, &B.e_tmp, &B.e_total, &B.e_clu, &B.part,
+    DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.Xd, &B.e_start, &B.e_count, &B.e_off, &B.e_scount, &B.e_bk, &B.e_boff, &B.e_tmp, &B.e_total, &B.e_clu, &B.part,
                      &B.sums, &B.fin, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
                      &B.carry_a, &B.carry_b, &B.status, &B.ticket, &B.part_tile_h,
                      &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err, &B.qdev,
@@ -679,7 +683,7 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
 
     ensure(B.sums, sizeof(pc_sums), "sums");
     ensure(B.fin, sizeof(pc_final), "final");
-    ensure(B.e_total, 16, "easy total");
+    ensure(B.e_total, 32, "easy total");
     hipck(pc_launch_fill_u64(ptr<uint64_t>(B.sums), sizeof(pc_sums) / 8, 0, g_stream), "fill");
     pc_sums *sums = ptr<pc_sums>(B.sums);
     Q.sums = sums;
@@ -696,6 +700,11 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     ensure(B.e_start, (a + 2) * 8, "easy ranges");
     ensure(B.e_count, (a + 2) * 8, "easy ranges");
     ensure(B.e_off, (a + 2) * 8, "easy offsets");
+    ensure(B.e_scount, (a + 2) * 8, "easy ranges");
+    const uint64_t nband = a / PC_EZ_BAND + 1;
+    ensure(B.e_bk, 2 * nband * 4, "easy bands");
+    ensure(B.e_boff, 2 * nband * 8, "easy bands");
+    ensure(B.Xd, (a + 2) * 8, "easy bands");
     ensure(B.e_clu, (a + 2) * 16, "easy clusters");
     ensure(B.e_tmp, ((a + 2) / 4096 + 2) * 8, "scan");
     ensure(B.Ub, (a + 2) * 16, "hard-leaf u ranges");
@@ -703,6 +712,10 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     Q.e_start = ptr<uint64_t>(B.e_start);
     Q.e_count = ptr<uint64_t>(B.e_count);
     Q.e_off = ptr<uint64_t>(B.e_off);
+    Q.e_scount = ptr<uint64_t>(B.e_scount);
+    Q.e_bk = ptr<uint32_t>(B.e_bk);
+    Q.e_boff = ptr<uint64_t>(B.e_boff);
+    Q.Xd = ptr<double>(B.Xd);
     Q.e_total = ptr<uint64_t>(B.e_total);
     Q.e_clu = ptr<uint4>(B.e_clu);
     hipck(pc_launch_leaf_setup(T, Q, ptr<pc_s128>(B.part), ls_blocks, g_stream), "leaf setup");
@@ -712,6 +725,12 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     hipck(pc_launch_scan_u64(ptr<uint64_t>(B.e_off), a + 1, ptr<uint64_t>(B.e_tmp),
                              ptr<uint64_t>(B.e_total), g_stream),
           "easy scan");
+    hipck(pc_launch_easy_bands(T, Q, g_stream), "easy bands");
+    for (int kind = 0; kind < 2; kind++)
+        hipck(pc_launch_scan_u64(ptr<uint64_t>(B.e_boff) + kind * nband, nband,
+                                 ptr<uint64_t>(B.e_tmp), ptr<uint64_t>(B.e_total) + 1 + kind,
+                                 g_stream),
+              "easy scan");
     // The easy leaves touch nothing the sieve writes: they run on the second
     // stream once the last sieve window is queued, and rejoin before the
     // combination.  Both kernels keep every CU busy, so running them side by
@@ -727,6 +746,10 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         hipck(hipStreamWaitEvent(g_stream2, g_fork, 0), "hipStreamWaitEvent");
         ev_easy = timed(
             [&] {
+                hipck(pc_launch_easy_band(T, Q, ptr<pc_s128>(B.part), ez_blocks, g_stream2),
+                      "easy");
+                hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ez_blocks, &sums->s2e, g_stream2),
+                      "S2e sum");
                 hipck(pc_launch_easy(T, Q, ptr<pc_s128>(B.part), ez_blocks, g_stream2), "easy");
             },
             g_stream2);
@@ -1013,7 +1036,7 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
         res->n_s1 = hs.n_s1;
         res->n_easy = hs.n_easy;
         res->n_hard = hs.n_hard;
-        res->n_easy_items = e_items;
+        res->n_easy_items = e_items + hs.n_easy_terms;
         res->crossings = hs.crossings;
         res->segments = nseg;
         res->tiles = ntiles_total;
@@ -1123,15 +1146,16 @@ constexpr uint32_t kBatchWG = 512;
 
 size_t r256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// A query's chunk of a round arena: X_b, Ub, three easy arrays, e_clu,
+// A query's chunk of a round arena: X_b, Ub, four easy arrays, e_clu, Xd, bands,
 // counts and weights (cells of the count staircase), the P2 column's counts
 // and weights, each rounded up to 256 bytes exactly as round_queries takes
 // them.
 size_t query_chunk(const BatchQuery &b, uint64_t cells)
 {
     const size_t na = b.a + 2;
-    return r256(na * 8) + 2 * r256(na * 16) + 3 * r256(na * 8) + 2 * r256(cells * 4) +
-           2 * r256(b.nseg * 4);
+    const size_t nband = b.a / PC_EZ_BAND + 1;
+    return 6 * r256(na * 8) + 2 * r256(na * 16) + r256(2 * nband * 4) + r256(2 * nband * 8) +
+           2 * r256(cells * 4) + 2 * r256(b.nseg * 4);
 }
 
 // What the host builds for one round: the arena layout (sums, easy totals,
@@ -1225,7 +1249,7 @@ void plan_round(const std::vector<BatchQuery> &R, RoundPlan &P)
         return o;
     };
     P.o_sums = take(nq * sizeof(pc_sums));
-    P.o_et = take(nq * 8);
+    P.o_et = take(nq * 32);
     P.o_fin = take(nq * sizeof(pc_final));
     // each query's count staircase (rows of 2S integers from 0)
     P.roff.clear();
@@ -1328,14 +1352,19 @@ void round_queries(const std::vector<BatchQuery> &R, const RoundPlan &P, char *b
         Q.e_start = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_count = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_off = reinterpret_cast<uint64_t *>(carve(na * 8));
+        Q.e_scount = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_clu = reinterpret_cast<uint4 *>(carve(na * 16));
+        Q.Xd = reinterpret_cast<double *>(carve(na * 8));
+        const size_t nband = b.a / PC_EZ_BAND + 1;
+        Q.e_bk = reinterpret_cast<uint32_t *>(carve(2 * nband * 4));
+        Q.e_boff = reinterpret_cast<uint64_t *>(carve(2 * nband * 8));
         Q.row_off = roff + P.o_roff[i];
         Q.cnt = reinterpret_cast<uint32_t *>(carve(P.cells[i] * 4));
         Q.wgt = reinterpret_cast<int32_t *>(carve(P.cells[i] * 4));
         Q.cntP = reinterpret_cast<uint32_t *>(carve(b.nseg * 4));
         Q.wP = reinterpret_cast<int32_t *>(carve(b.nseg * 4));
         Q.carryP = nullptr;
-        Q.e_total = reinterpret_cast<uint64_t *>(base + P.o_et) + i;
+        Q.e_total = reinterpret_cast<uint64_t *>(base + P.o_et) + 4 * i;
         Q.sums = sums + i;
         Q.carry = nullptr;
         Q.nseg = b.nseg;

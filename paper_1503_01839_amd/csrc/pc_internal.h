@@ -22,6 +22,7 @@ struct pc_tile {
 struct pc_tables {
     const uint32_t *primes; // primes[k] = p_k, 1-based (primes[1] = 2)
     const uint64_t *recip;  // recip[k] = floor((2^64-1)/p_k) for k <= n_recip
+    const double *rcpd;     // rcpd[k] = 1/p_k correctly rounded, k <= n_recip
     const uint2 *pitab;     // pi table, see pc_pi_lookup
     const int32_t *mulpf;   // mu(n)*lpf(n) for n <= ymax; INT32_MAX at n = 1; 0 if mu = 0
     const uint32_t *pattern; // odd-only pre-sieve bits for p_2..p_c, period pattern_bits (+64 bits)
@@ -62,16 +63,38 @@ struct pc_query {
     uint32_t *cntP;         // per row: the count after the last crossing (P2 column)
     int32_t *wP;            // per row: the P2 terms landing in the row
     const uint64_t *carryP; // PC_MODE_LEAVES: exclusive carries of cntP
-    uint64_t *e_start;      // easy leaves per b: first item, count (bit 63: candidate m),
-    uint64_t *e_count;      //   exclusive prefix of the counts and their total
+    // Easy leaves per b (pc_leaf_setup_item), in three kinds:
+    //   candidates (p_b^2 <= y): m = e_start[b] .. + e_count[b] - 1 (bit 63
+    //     of e_count set), e_off the exclusive prefix of e_count over b and
+    //     e_total[0] its total;
+    //   singles (p_b^2 > y): primes p_k, k = e_start[b] .. + e_scount[b] - 1;
+    //   groups (p_b^2 > y): e_clu[b] = {nk, klo, z, w}, K = klo .. klo + nk
+    //     (none when nk = 0).
+    // Singles and groups are dealt out in bands of PC_EZ_BAND consecutive b:
+    // unit j of band g is the 256 prime indices from e_bk[g] + 256 j on, each
+    // taken against every b of the band.  e_bk[g] / e_boff[g] (g < nband):
+    // first k and exclusive prefix of the units of the singles; at nband + g
+    // the same for the groups; e_total[1] / e_total[2] the units.  Xd[b] =
+    // (double)Xb[b].
+    uint64_t *e_start;
+    uint64_t *e_count;
     uint64_t *e_off;
+    uint64_t *e_scount;
+    uint4 *e_clu;
+    uint32_t *e_bk;
+    uint64_t *e_boff;
+    double *Xd;
     uint64_t *e_total;
-    uint4 *e_clu;           // prime-item b: {single-m items, first K, m split, last m}
     ulonglong2 *Ub_w;       // writable view of Ub (set-up kernels)
     uint64_t *Xb_w;         // writable view of Xb (set-up kernels)
 };
 
 enum { PC_MODE_TALLY = 0, PC_MODE_COUNT = 1, PC_MODE_LEAVES = 2 };
+
+// b per band of the singles and groups of the easy leaves; bands of a query:
+// a / PC_EZ_BAND + 1.
+#define PC_EZ_BAND 64
+#define PC_EZ_UNIT 256
 
 // per-tile trace record: 0 ticks (100 MHz), 1 hard leaves, 2 candidates read,
 // 3 leafy columns, 4 of them with p^3 < segment end, 5.. phase ticks
@@ -97,7 +120,8 @@ hipError_t pc_launch_base_primes(uint32_t *base, uint32_t *nbase, hipStream_t s)
 hipError_t pc_launch_pitab(uint64_t nentries, const uint32_t *base, uint32_t nbase,
                            uint32_t *bits, uint32_t *cnts, uint2 *pitab, uint32_t *primes,
                            uint32_t *scan_tmp, hipStream_t s);
-hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, uint32_t n, hipStream_t s);
+hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, double *rcpd, uint32_t n,
+                           hipStream_t s);
 hipError_t pc_launch_mulpf(const uint32_t *primes, uint32_t nsmall, uint64_t ymax,
                            int32_t *mulpf, hipStream_t s);
 hipError_t pc_launch_count_nonzero(const int32_t *a, uint64_t n, unsigned long long *out,
@@ -120,6 +144,9 @@ hipError_t pc_launch_scan_u64(uint64_t *data, uint64_t n, uint64_t *tmp, uint64_
                               hipStream_t s);
 hipError_t pc_launch_easy(const pc_tables &T, const pc_query &Q, pc_s128 *part, uint32_t nblocks,
                           hipStream_t s);
+hipError_t pc_launch_easy_bands(const pc_tables &T, const pc_query &Q, hipStream_t s);
+hipError_t pc_launch_easy_band(const pc_tables &T, const pc_query &Q, pc_s128 *part,
+                               uint32_t nblocks, hipStream_t s);
 hipError_t pc_launch_sum128(const pc_s128 *part, uint32_t n, pc_s128 *acc, hipStream_t s);
 hipError_t pc_launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 
@@ -166,7 +193,8 @@ hipError_t pc_launch_scan(const pc_scan_args &A, int mode, hipStream_t s);
 // Final combination of the partial sums into pi(x) and its parts.
 struct pc_sums {
     pc_s128 s1, s2t, s2e, hard_local, hard_dot, p2_local, p2_dot;
-    unsigned long long n_s1, n_easy, n_hard, crossings, n_trivial, pad;
+    unsigned long long n_s1, n_easy, n_hard, crossings, n_trivial;
+    unsigned long long n_easy_terms; // singles and group terms of the easy leaves
 };
 struct pc_final {
     pc_s128 s1, s2t, s2e, s2h, p2, phi;

@@ -46,12 +46,13 @@ __device__ __forceinline__ bool pc_s1_item(const pc_tables &T, const pc_query &Q
 //                   H_b = max(x/p_b^3, x/(p_b (y+1)));
 // for p_b^2 > y every m in the range is prime, so the range is stored as
 // prime indices; otherwise as candidate m (bit 63 of the count).  A prime
-// range is cut at s = 1.5 isqrt(x/p_b): each m <= s is one item; above s,
-// where u = x/(m p_b) < m and consecutive m share pi(u), the items are the
-// values K = pi(u) instead, each standing for the primes m with
-// x/(p_b p_{K+1}) < m <= x/(p_b p_K), all with phi(u, b-1) = K - b + 2.  For a
-// sieving prime it also records the u range of its hard leaves (Ub) and the
-// odd multiples below the sieve end (*cross).
+// range is cut at s = 1.5 isqrt(x/p_b): each prime m <= s is a "single"
+// (e_start, e_scount); above s, where u = x/(m p_b) < m and consecutive m
+// share pi(u), the primes m are taken by the value K = pi(u) instead: those
+// with x/(p_b p_{K+1}) < m <= x/(p_b p_K), all with phi(u, b-1) = K - b + 2
+// (e_clu; pc_easy_group_term).  For a sieving prime it also records the u
+// range of its hard leaves (Ub) and the odd multiples below the sieve end
+// (*cross).
 __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_query &Q,
                                                    uint32_t b, uint64_t *triv, uint64_t *cross)
 {
@@ -80,7 +81,7 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
         Q.Ub_w[b] = ub;
     }
     if (b <= Q.a) {
-        uint64_t st = 0, cn = 0;
+        uint64_t st = 0, cn = 0, sn = 0;
         uint4 clu = make_uint4(0, 0, 0, 0);
         if (b > Q.c && b < Q.a) {
             const uint64_t p = T.primes[b], rp = T.recip[b];
@@ -109,11 +110,9 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
                         klo = pc_pi_lookup(T.pitab, pc_div_any(X, (uint32_t)e2));
                         nk = pc_pi_lookup(T.pitab, pc_div_any(X, (uint32_t)(s + 1))) + 1 - klo;
                     }
-                    if (ns + nk) {
-                        st = k1;
-                        cn = ns + nk;
-                        clu = make_uint4((uint32_t)ns, (uint32_t)klo, (uint32_t)s, (uint32_t)e2);
-                    }
+                    st = k1;
+                    sn = ns;
+                    clu = make_uint4((uint32_t)nk, (uint32_t)klo, (uint32_t)s, (uint32_t)e2);
                 }
                 // trivial: m prime, m > max(m1 - 1, tp), m <= y
                 uint64_t t0 = tp > m1 - 1 ? tp : m1 - 1;
@@ -126,6 +125,7 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
         }
         Q.e_start[b] = st;
         Q.e_count[b] = cn;
+        Q.e_scount[b] = sn;
         Q.e_clu[b] = clu;
     }
 }
@@ -160,128 +160,207 @@ template <int NT> __device__ __forceinline__ void pc_ub_suffix(const pc_query &Q
     }
 }
 
-// Item o of a prime-item b (cl = its e_clu entry, st its first prime index,
-// bm2 = b - 2, Xd = (double)X_b): the prime m = p_{st+o} for o < cl.x, else
-// K = cl.y + o - cl.x and the primes m in (max(X_b / p_{K+1}, cl.z),
-// min(X_b / p_K, cl.w)].  Adds the item's part of S2e to *acc and its
-// leaves to *nl.  Every quotient is at most y < 2^32 - 1.
-__device__ __forceinline__ void pc_easy_prime_item(const pc_tables &T, uint4 cl, uint32_t st,
-                                                   uint64_t X, double Xd, uint32_t bm2, uint32_t o,
-                                                   int64_t *acc, uint32_t *nl)
+// The group terms of a prime-item b (cl = its e_clu entry: nk, klo, z = s,
+// w = e2; bm2 = b - 2).  With C(v) = min(max(v, z), w) and
+// V_K = pi(C(X_b / p_K)), the primes m in (max(X_b / p_{K+1}, z),
+// min(X_b / p_K, w)] number V_K - V_{K+1} (also when that range is empty, as
+// C is monotone), so the part of S2e over K = klo .. khi = klo + nk - 1 is
+//   sum_K (V_K - V_{K+1}) (K - bm2)
+//     = sum_{klo <= K <= khi + 1} V_K
+//       + V_klo (klo - bm2 - 1) - V_{khi+1} (khi + 1 - bm2),
+// and its leaves number V_klo - V_{khi+1}.  The sum of the V_K is taken in
+// bands (pc_easy_bands), the two end terms once per b (pc_easy_band_item).
+// Every quotient is at most y < 2^31 - 1, every p_K < 2^31.
+__device__ __forceinline__ int64_t pc_easy_group_v(const pc_tables &T, uint4 cl, uint64_t X,
+                                                   double Xd, uint32_t K)
 {
-    if (o < cl.x) {
-        const uint32_t u = pc_quot32(X, Xd, T.primes[st + o]); // p_b <= u <= y
-        *acc += pc_pi_lookup32(T.pitab, u) - bm2;              // phi(u, b-1) = pi(u) - b + 2
-        (*nl)++;
-    } else {
-        const uint32_t K = cl.y + (o - cl.x);
-        const uint32_t hi = min(pc_quot32(X, Xd, T.primes[K]), cl.w);
-        const uint32_t lo = max(pc_quot32(X, Xd, T.primes[K + 1]), cl.z);
-        if (hi > lo) {
-            const uint32_t n = pc_pi_lookup32(T.pitab, hi) - pc_pi_lookup32(T.pitab, lo);
-            *acc += (int64_t)n * (int64_t)(K - bm2);
-            *nl += n;
-        }
-    }
+    return pc_pi_lookup32(T.pitab,
+                          min(max(pc_quot31r(X, Xd, T.primes[K], T.rcpd[K]), cl.z), cl.w));
 }
 
-// Easy leaves, items laid end to end over b (e_off = exclusive prefix of the
-// counts, e_total their sum).  The calling workgroup (NT threads; every thread
-// calls) takes tiles lb, lb + nlb, ... of NT * PER consecutive items; one
-// search finds the b of a tile's first item, then thread t takes items
-// i0 + t, i0 + t + NT, ... so neighbouring lanes read neighbouring primes m
-// and neighbouring pi(u) entries.  u = x/(m p_b) <= y < 2^32 - 1, so the
-// reciprocal estimate quotient is exact after its remainder check.  The
-// candidate-m items (p_b^2 <= y) all precede the prime items (p_b^2 > y), so a
-// tile that starts in a prime range has only prime items (single primes m,
-// -mu(m) = 1, or groups of them sharing K = pi(u); pc_easy_prime_item), and
-// its loop needs no filter.
+// b in [c+1, a-1] with off[b] <= i0 < off[b+1] (off = an exclusive prefix of
+// item counts; the last such b, so b has items).
+__device__ __forceinline__ uint32_t pc_item_owner(const pc_query &Q, const uint64_t *off,
+                                                  uint64_t i0)
+{
+    uint32_t lo_b = Q.c + 1, hi_b = Q.a - 1;
+    while (lo_b < hi_b) {
+        const uint32_t mid = (lo_b + hi_b + 1) >> 1;
+        if (off[mid] <= i0)
+            lo_b = mid;
+        else
+            hi_b = mid - 1;
+    }
+    return lo_b;
+}
+
+// The candidate easy leaves (p_b^2 <= y), items laid end to end over b
+// (e_off = exclusive prefix of the counts, e_total[0] their sum).  The calling
+// workgroup (NT threads; every thread calls) takes tiles lb, lb + nlb, ... of
+// NT * PER consecutive items; one search finds the b of a tile's first item,
+// then thread t takes items i0 + t, i0 + t + NT, ... so neighbouring lanes
+// read neighbouring entries.  u = x/(m p_b) <= y < 2^31 - 1, so the
+// reciprocal estimate quotient is exact after its remainder check.
 template <int NT, int PER>
 __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query &Q, uint64_t lb,
                                               uint64_t nlb, uint32_t *s_b0, int64_t *acc,
                                               unsigned long long *nleaf)
 {
     constexpr uint64_t TILE = (uint64_t)NT * PER;
-    const uint64_t E = *Q.e_total;
+    const uint64_t E = Q.e_total[0];
     const uint64_t *e_off = Q.e_off, *e_count = Q.e_count, *e_start = Q.e_start;
     for (uint64_t i0 = lb * TILE; i0 < E; i0 += nlb * TILE) {
-        if (threadIdx.x == 0) { // b with e_off[b] <= i0 < e_off[b+1], b in [c+1, a-1]
-            uint32_t lo_b = Q.c + 1, hi_b = Q.a - 1;
-            while (lo_b < hi_b) {
-                const uint32_t mid = (lo_b + hi_b + 1) >> 1;
-                if (e_off[mid] <= i0)
-                    lo_b = mid;
-                else
-                    hi_b = mid - 1;
-            }
-            *s_b0 = lo_b;
-        }
+        if (threadIdx.x == 0)
+            *s_b0 = pc_item_owner(Q, e_off, i0);
         __syncthreads();
         uint32_t b = *s_b0;
         const uint32_t n = (uint32_t)(i0 + TILE < E ? TILE : E - i0); // items of the tile
-        uint64_t cn = e_count[b];
-        if (!(cn & PC_MODEBIT)) {
-            // prime items only; item t of the tile is item t - rs of its b
-            int64_t rs = (int64_t)(e_off[b] - i0), re = rs + (int64_t)cn;
-            uint32_t st = (uint32_t)e_start[b], bm2 = b - 2;
-            uint4 cl = Q.e_clu[b];
-            uint64_t X = Q.Xb[b];
-            double Xd = (double)X;
-            int64_t a = 0;
-            uint32_t nl = 0;
-            for (uint32_t t = threadIdx.x; t < n; t += NT) {
-                while ((int64_t)t >= re) {
-                    b++;
-                    rs = re;
-                    re = rs + (int64_t)e_count[b];
-                    st = (uint32_t)e_start[b];
-                    cl = Q.e_clu[b];
-                    bm2 = b - 2;
-                    X = Q.Xb[b];
-                    Xd = (double)X;
-                }
-                pc_easy_prime_item(T, cl, st, X, Xd, bm2, (uint32_t)((int64_t)t - rs), &a, &nl);
+        uint64_t off = e_off[b], cn = e_count[b] & ~PC_MODEBIT, st = e_start[b], X = Q.Xb[b];
+        double Xd = (double)X;
+        uint32_t p = T.primes[b];
+        const uint64_t iend = i0 + n;
+        for (uint64_t i = i0 + threadIdx.x; i < iend; i += NT) {
+            while (i >= off + cn) {
+                b++;
+                off = e_off[b];
+                cn = e_count[b] & ~PC_MODEBIT;
+                st = e_start[b];
+                X = Q.Xb[b];
+                Xd = (double)X;
+                p = T.primes[b];
             }
-            *acc += a;
-            *nleaf += nl;
-        } else {
-            uint64_t off = e_off[b], st = e_start[b], X = Q.Xb[b];
-            double Xd = (double)X;
-            uint32_t p = T.primes[b];
-            const uint64_t iend = i0 + n;
-            for (uint64_t i = i0 + threadIdx.x; i < iend; i += NT) {
-                while (i >= off + (cn & ~PC_MODEBIT)) {
-                    b++;
-                    off = e_off[b];
-                    cn = e_count[b];
-                    st = e_start[b];
-                    X = Q.Xb[b];
-                    Xd = (double)X;
-                    p = T.primes[b];
-                }
-                const uint64_t o = i - off;
-                if (!(cn & PC_MODEBIT)) { // a prime-item b past the tile's start
-                    int64_t a = 0;
-                    uint32_t nl = 0;
-                    pc_easy_prime_item(T, Q.e_clu[b], (uint32_t)st, X, Xd, b - 2, (uint32_t)o, &a,
-                                       &nl);
-                    *acc += a;
-                    *nleaf += nl;
-                    continue;
-                }
-                const uint32_t m = (uint32_t)(st + o);
-                const int32_t v = T.mulpf[m];
-                const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
-                if (l <= p) // mu(m) = 0 or lpf(m) <= p_b
-                    continue;
-                const uint32_t u = pc_quot32(X, Xd, m); // u <= y < 2^32 - 1
-                const int64_t phi = (int64_t)pc_pi_lookup32(T.pitab, u) - (int64_t)b + 2;
-                *acc += v > 0 ? -phi : phi; // -mu(m) phi(u, b-1)
-                (*nleaf)++;
-            }
+            const uint32_t m = (uint32_t)(st + (i - off));
+            const int32_t v = T.mulpf[m];
+            const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
+            if (l <= p) // mu(m) = 0 or lpf(m) <= p_b
+                continue;
+            const uint32_t u = pc_quot31(X, Xd, m); // u <= y < 2^31 - 1
+            const int64_t phi = (int64_t)pc_pi_lookup32(T.pitab, u) - (int64_t)b + 2;
+            *acc += v > 0 ? -phi : phi; // -mu(m) phi(u, b-1)
+            (*nleaf)++;
         }
         __syncthreads();
     }
+}
+
+// The bands of the singles and groups (layout in pc_query): for band g, the
+// first and one past the last prime index of each kind over the band's b, and
+// its units; also Xd[b] for the band's b, and the parts of S2e and of the
+// leaf count that the bands' sums leave out: -(b - 2) for each single
+// (pc_easy_bands adds pi(u) alone), the two end terms of each b's groups
+// (pc_easy_group_v), and every single and group leaf.
+__device__ __forceinline__ void pc_easy_band_item(const pc_tables &T, const pc_query &Q,
+                                                  uint32_t g)
+{
+    const uint32_t nband = Q.a / PC_EZ_BAND + 1;
+    if (g >= nband)
+        return;
+    const uint32_t b0 = g * PC_EZ_BAND, b1 = min(b0 + PC_EZ_BAND, Q.a + 1);
+    uint32_t s_lo = UINT32_MAX, s_hi = 0, g_lo = UINT32_MAX, g_hi = 0;
+    pc_s128 cst = 0;
+    int64_t leaves = 0;
+    unsigned long long terms = 0;
+    for (uint32_t b = b0; b < b1; b++) {
+        const uint64_t X = Q.Xb[b];
+        const double Xd = (double)X;
+        Q.Xd[b] = Xd;
+        const uint32_t ns = (uint32_t)Q.e_scount[b];
+        if (ns) {
+            const uint32_t k1 = (uint32_t)Q.e_start[b];
+            s_lo = min(s_lo, k1);
+            s_hi = max(s_hi, k1 + ns);
+            cst -= (pc_s128)ns * (b - 2);
+            leaves += ns;
+            terms += ns;
+        }
+        const uint4 cl = Q.e_clu[b];
+        if (cl.x) {
+            const uint32_t klo = cl.y, khi1 = cl.y + cl.x; // K = klo .. khi1
+            g_lo = min(g_lo, klo);
+            g_hi = max(g_hi, khi1 + 1);
+            const int64_t v0 = pc_easy_group_v(T, cl, X, Xd, klo);
+            const int64_t v1 = pc_easy_group_v(T, cl, X, Xd, khi1);
+            cst += (pc_s128)v0 * (int64_t)(klo - b + 1) - (pc_s128)v1 * (int64_t)(khi1 + 2 - b);
+            leaves += v0 - v1;
+            terms += cl.x + 1;
+        }
+    }
+    if (cst != 0)
+        pc_atomic_add128(&Q.sums->s2e, cst);
+    if (leaves)
+        atomicAdd(&Q.sums->n_easy, (unsigned long long)leaves);
+    if (terms)
+        atomicAdd(&Q.sums->n_easy_terms, terms);
+    Q.e_bk[g] = s_lo;
+    Q.e_boff[g] = s_hi > s_lo ? (s_hi - s_lo + PC_EZ_UNIT - 1) / PC_EZ_UNIT : 0;
+    Q.e_bk[nband + g] = g_lo;
+    Q.e_boff[nband + g] = g_hi > g_lo ? (g_hi - g_lo + PC_EZ_UNIT - 1) / PC_EZ_UNIT : 0;
+}
+
+// Singles (GRP false) or groups (GRP true) of the easy leaves, in units of
+// PC_EZ_UNIT prime indices k (one per thread; NT = PC_EZ_UNIT) against the
+// PC_EZ_BAND b of a band (layout in pc_query).  The calling workgroup takes the
+// contiguous units [U lb / nlb, U (lb + 1) / nlb).  A thread loads p_k and 1/p_k
+// once per unit; for each b of the band that has k in its range it adds
+//   singles: pi(u), u = X_b / p_k;
+//   groups:  V_k = pi(C(X_b / p_k)) (pc_easy_group_v);
+// the rest of each term is added once per b (pc_easy_band_item).  Every
+// thread takes every b (a lane outside the b's range looks up pi(2) and drops
+// it), so the loop has no branches; band data are uniform over the workgroup.
+template <int NT, bool GRP>
+__device__ __forceinline__ void pc_easy_bands(const pc_tables &T, const pc_query &Q, uint64_t lb,
+                                              uint64_t nlb, uint32_t *s_g, int64_t *acc)
+{
+    static_assert(NT == PC_EZ_UNIT, "one thread per prime index of a unit");
+    const uint32_t nband = Q.a / PC_EZ_BAND + 1;
+    const uint64_t *boff = Q.e_boff + (GRP ? nband : 0);
+    const uint32_t *bk = Q.e_bk + (GRP ? nband : 0);
+    const uint64_t U = Q.e_total[GRP ? 2 : 1];
+    const uint64_t u0 = U * lb / nlb, u1 = U * (lb + 1) / nlb;
+    if (u0 >= u1)
+        return;
+    if (threadIdx.x == 0) { // the band of unit u0: last g with boff[g] <= u0
+        uint32_t lo = 0, hi = nband - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (boff[mid] <= u0)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        *s_g = lo;
+    }
+    __syncthreads();
+    uint32_t g = __builtin_amdgcn_readfirstlane(*s_g);
+    uint64_t gend = g + 1 < nband ? boff[g + 1] : U;
+    int64_t a = 0;
+    const uint32_t kcap = Q.a + 1; // p_k and 1/p_k exist for k <= a + 1
+    for (uint64_t u = u0; u < u1; u++) {
+        while (u >= gend) {
+            g++;
+            gend = g + 1 < nband ? boff[g + 1] : U;
+        }
+        const uint32_t k = bk[g] + (uint32_t)(u - boff[g]) * PC_EZ_UNIT + threadIdx.x;
+        const uint32_t kk = min(k, kcap);
+        const uint32_t m = T.primes[kk];
+        const double rm = T.rcpd[kk];
+        const uint32_t b1 = min(g * PC_EZ_BAND + PC_EZ_BAND, Q.a + 1);
+#pragma unroll 4
+        for (uint32_t b = g * PC_EZ_BAND; b < b1; b++) {
+            bool in;
+            uint32_t q = pc_quot31r(Q.Xb[b], Q.Xd[b], m, rm);
+            if constexpr (!GRP) {
+                in = k - (uint32_t)Q.e_start[b] < (uint32_t)Q.e_scount[b];
+            } else {
+                const uint4 cl = Q.e_clu[b];
+                in = (k - cl.y <= cl.x) && cl.x != 0;
+                q = min(max(q, cl.z), cl.w);
+            }
+            const uint32_t v = pc_pi_lookup32(T.pitab, in ? q : 2u);
+            a += in ? v : 0u;
+        }
+    }
+    *acc += a;
 }
 
 // pi(x) = S1 + S2t + S2e + S2h + a - 1 - P2, with

@@ -70,7 +70,7 @@ __global__ void k_strip_counts(const uint64_t *e_count, uint64_t *e_off, uint64_
         e_off[i] = e_count[i] & ~PC_MODEBIT;
 }
 
-// Easy leaves of one query, tiles of EZ_T * EZ_PER items (pc_easy_tiles).
+// Candidate easy leaves of one query, tiles of EZ_T * EZ_PER items (pc_easy_tiles).
 #define EZ_T 256
 #define EZ_PER 32
 
@@ -94,6 +94,39 @@ hipError_t pc_launch_easy(const pc_tables &T, const pc_query &Q, pc_s128 *part, 
                           hipStream_t s)
 {
     k_easy<<<nblocks, EZ_T, 0, s>>>(T, Q, part);
+    return hipGetLastError();
+}
+
+// The bands of the singles and groups (pc_easy_band_item), one thread per band.
+__global__ __launch_bounds__(LV_T) void k_easy_bands(pc_tables T, pc_query Q)
+{
+    pc_easy_band_item(T, Q, blockIdx.x * LV_T + threadIdx.x);
+}
+
+hipError_t pc_launch_easy_bands(const pc_tables &T, const pc_query &Q, hipStream_t s)
+{
+    const uint32_t nband = Q.a / PC_EZ_BAND + 1;
+    k_easy_bands<<<(nband + LV_T - 1) / LV_T, LV_T, 0, s>>>(T, Q);
+    return hipGetLastError();
+}
+
+// The singles and the groups of the easy leaves of one query (pc_easy_bands).
+__global__ __launch_bounds__(PC_EZ_UNIT) void k_easy_band(pc_tables T, pc_query Q, pc_s128 *part)
+{
+    __shared__ pc_s128 scr[PC_EZ_UNIT / 64];
+    __shared__ uint32_t s_g[2];
+    int64_t acc = 0;
+    pc_easy_bands<PC_EZ_UNIT, false>(T, Q, blockIdx.x, gridDim.x, &s_g[0], &acc);
+    pc_easy_bands<PC_EZ_UNIT, true>(T, Q, blockIdx.x, gridDim.x, &s_g[1], &acc);
+    const pc_s128 s = pc_block_sum128<PC_EZ_UNIT>((pc_s128)acc, scr);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = s;
+}
+
+hipError_t pc_launch_easy_band(const pc_tables &T, const pc_query &Q, pc_s128 *part,
+                               uint32_t nblocks, hipStream_t s)
+{
+    k_easy_band<<<nblocks, PC_EZ_UNIT, 0, s>>>(T, Q, part);
     return hipGetLastError();
 }
 

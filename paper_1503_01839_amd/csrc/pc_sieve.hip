@@ -24,10 +24,10 @@
 // prime sieve).  Per column the workgroup first answers the leaves, then
 // crosses.  Columns are processed in order; for primes with p^3 >= hi (every
 // unsieved integer below the segment end then has at most two prime factors
-// >= p) a run of columns without leaves is crossed in one step, one lane per
-// prime: an integer n = p k unsieved at the start of the run is first removed
-// by p exactly when k = 1 or k >= p, which gives the per-column counts
-// without ordering the lanes.
+// >= p) each wave crosses up to 64 columns of its region in one step, one
+// lane per prime: an integer n = p k unsieved at the start of the step is
+// first removed by p exactly when k = 1 or k >= p, which gives the
+// per-column counts without ordering the lanes.
 #include "pc_block.h"
 #include "pc_internal.h"
 #include "pc_leafrange.h"
@@ -37,6 +37,7 @@
 #ifndef PC_PHASE_TRACE
 #define PC_PHASE_TRACE 0
 #endif
+
 
 // Waves per SIMD that the LDS footprint of k_sieve<LOG2_S, T, CH> allows on a
 // CU (160 KiB of LDS, at most 8 waves per SIMD); the kernel asks the compiler
@@ -78,7 +79,6 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     static_assert((1u << RSL) == RS && RS == 64 * BPT * 512, "a region is 64 threads' blocks");
     constexpr uint32_t GCAP = pc_sieve_gcap<LOG2_S, T, CH>(); // gathered leaf items
     constexpr uint32_t LIGHT = GCAP / 2; // more leaf items: the column is answered workgroup-wide
-    constexpr uint32_t GAPB = 8;         // leafless large-prime columns worth one batched crossing
     constexpr uint32_t XB_P = RS / 32;   // p >= XB_P: at most 32 multiples in a wave's region
     constexpr uint32_t KMAX = 64;         // columns per gather round (as in pc_sieve_waves_per_simd)
     static_assert(GCAP < 2048 && LIGHT < 2048, "gathered-column fields");
@@ -101,7 +101,6 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     __shared__ uint64_t c_leafy[CH / 64];
     __shared__ uint64_t c_heavy[CH / 64];
     __shared__ uint32_t s_first_large, s_first_skip;
-    __shared__ uint32_t reg_dec[NWV];  // integers a batched crossing removed, per region
     __shared__ uint32_t scr32[NWV];
     __shared__ pc_s128 scr128[NWV];
 
@@ -164,17 +163,19 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     {
         const uint32_t P = TB.pattern_bits;
         const uint32_t g0 = (uint32_t)((lo >> 1) % P);
+        const uint32_t step = (32u * T) % P; // from word w to word w + T
+        uint32_t off = (uint32_t)(((uint64_t)g0 + 32u * tid) % P);
         for (uint32_t w = tid; w < NW; w += T) {
-            uint32_t off = (g0 + 32u * w) % P;
-            uint32_t wi = off >> 5, sh = off & 31;
+            const uint32_t wi = off >> 5, sh = off & 31;
             uint32_t v = TB.pattern[wi] >> sh;
             if (sh)
                 v |= TB.pattern[wi + 1] << (32 - sh);
             BW(w) = v;
+            off += step;
+            if (off >= P)
+                off -= P;
         }
     }
-    if (tid < NWV)
-        reg_dec[tid] = 0;
     if (tid < 2 * KMAX)
         g_rm[tid] = 0;
     __syncthreads();
@@ -858,54 +859,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             if (gath)
                 g_rc[lane * NWV + wv] = (uint16_t)(rc0 - before);
         };
-        // Leafless columns [j, jb) of primes with p^3 >= hi, one lane per
-        // prime: an integer n = p k unsieved at the start of the run is first
-        // removed by p exactly when k = 1 or k >= p.
-        auto batch = [&](uint32_t j, uint32_t jb) {
-            PC_PH(4);
-            __syncthreads(); // every wave has crossed the columns before j
-            const uint32_t jj = j + tid;
-            const bool mine_col = jj < jb;
-            uint32_t i0 = S, p = 0;
-            if (mine_col) {
-                i0 = c_i0[jj];
-                p = c_p[jj];
-                uint32_t credit = 0;
-                // n = lo + 2 bit + 1 >= p^2  <=>  bit >= tb;  n = p  <=>  bit = ip
-                const uint64_t p2 = (uint64_t)p * p;
-                const uint32_t tb = p2 <= lo ? 0u : (uint32_t)min<uint64_t>(S, (p2 - lo - 1) >> 1);
-                const uint32_t ip = lo <= p ? i0 : S;
-                auto credit_bit = [&](uint32_t bit, uint32_t v) {
-                    if (((v >> (bit & 31)) & 1) && (bit >= tb || bit == ip)) {
-                        credit++;
-                        atomicAdd(&reg_dec[bit >> RSL], 1u);
-                    }
-                };
-                for (uint32_t bit = i0; bit < S; bit += 2 * p) {
-                    const uint32_t b1 = bit + p;
-                    const uint32_t v0 = BW(bit >> 5);
-                    const uint32_t v1 = b1 < S ? BW(b1 >> 5) : 0u;
-                    credit_bit(bit, v0);
-                    if (b1 < S)
-                        credit_bit(b1, v1);
-                }
-                c_new[jj] = credit;
-            }
-            __syncthreads(); // every read of the run precedes every clear
-            if (mine_col)
-                for (uint32_t bit = i0; bit < S; bit += p)
-                    __hip_atomic_fetch_and(&BW(bit >> 5), ~(1u << (bit & 31)), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-            __syncthreads(); // clears and region counts complete
-            rc -= (uint32_t)__builtin_amdgcn_readfirstlane((int)reg_dec[wv]);
-            if (lane == 0)
-                reg_dec[wv] = 0; // next written after the next run's first barrier
-            PC_PH(5);
-        };
-
         // Columns in order.  Each wave crosses its own region, so between the
-        // workgroup-wide steps (gather, heavy column, batched run) the waves
-        // move through the columns independently.
+        // workgroup-wide steps (gather, heavy column) the waves move through
+        // the columns independently.
         uint32_t j = 0, jb_next = 0; // jb_next: the next leafy column, once known
         uint32_t lw_at = ~0u;        // c_leafy word cached for columns [64 lw_at, 64 lw_at + 64)
         uint64_t lw = 0;
@@ -935,16 +891,10 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                     msk = c_leafy[wd];
                 jb_next = msk ? min(jend, wd * 64 + (uint32_t)__builtin_ctzll(msk)) : jend;
             }
-            if (BATCH && j >= first_large && jb_next - j >= GAPB) {
-                batch(j, jb_next);
-                j = jb_next;
-                continue;
-            }
-            // a leafless run: stop where large primes begin, so that a long
-            // remainder can still be batched
-            const uint32_t je = j < first_large ? min(jb_next, first_large) : jb_next;
-            cross_run(j, je);
-            j = je;
+            // a leafless run, each wave in its own region (large primes a
+            // group of 64 at a time, xbatch)
+            cross_run(j, jb_next);
+            j = jb_next;
         }
         flush_removed();
         PC_PH(4);

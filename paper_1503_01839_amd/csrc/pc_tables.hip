@@ -230,20 +230,26 @@ hipError_t pc_launch_base_primes(uint32_t *base, uint32_t *nbase, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// Reciprocals recip[k] = floor((2^64-1) / p_k), k in [1, n].
+// Reciprocals recip[k] = floor((2^64-1) / p_k) and rcpd[k] = 1/p_k (IEEE
+// double, correctly rounded), k in [1, n].
 // ---------------------------------------------------------------------------
-__global__ void k_recip(const uint32_t *primes, uint64_t *recip, uint32_t n)
+__global__ void k_recip(const uint32_t *primes, uint64_t *recip, double *rcpd, uint32_t n)
 {
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0)
+    if (k == 0) {
         recip[0] = 0;
-    if (k >= 1 && k <= n)
+        rcpd[0] = 0.0;
+    }
+    if (k >= 1 && k <= n) {
         recip[k] = pc_recip(primes[k]);
+        rcpd[k] = 1.0 / (double)primes[k];
+    }
 }
 
-hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, uint32_t n, hipStream_t s)
+hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, double *rcpd, uint32_t n,
+                           hipStream_t s)
 {
-    k_recip<<<(n + 256) / 256, 256, 0, s>>>(primes, recip, n);
+    k_recip<<<(n + 256) / 256, 256, 0, s>>>(primes, recip, rcpd, n);
     return hipGetLastError();
 }
 
