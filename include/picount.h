@@ -92,8 +92,10 @@ typedef struct {
      * stream concurrently with the sieve. */
     double ms_total, ms_tables, ms_leaves, ms_sieve;
     double ms_k_sieve, ms_k_scan, ms_k_easy, ms_k_s1;  /* kernel time, HIP events     */
-    uint64_t n_easy_items;          /* work items of the easy-leaf kernel: one easy leaf,
-                                       or a run of easy leaves sharing pi(u)     */
+    uint64_t n_easy_items;          /* work items of the easy-leaf kernels: a candidate m,
+                                       a single prime m, or a value K = pi(u) of a run
+                                       of primes m sharing it                   */
+    uint64_t x_hi;                  /* x = x_hi * 2^64 + x (pc_pi_count_wide)       */
 } pc_result;
 
 /* ---------------------------------------------------------------------- */
@@ -107,6 +109,16 @@ pc_status pc_pi_count(uint64_t x, double alpha, uint64_t *pi_out);
 /* As pc_pi_count with explicit knobs (cfg may be NULL) and the full
  * decomposition in *res (may be NULL). */
 pc_status pc_pi_count_ex(uint64_t x, const pc_config *cfg, pc_result *res);
+
+/* pi(x) for x = x_hi * 2^64 + x_lo, 0 <= x < 17 * 2^64 (x_hi <= 16, else
+ * PC_ERANGE): the range of Table 2's 2^64 .. 2^68 and Table 1's 10^20
+ * (Section 5).  Knobs and *res (either may be NULL) as in pc_pi_count_ex;
+ * res->x and res->x_hi hold the two words of x.  Above 2^64 the method is
+ * unchanged: every X_b = x / p_b with p_b > p_c = 13, every leaf quotient and
+ * every x / p of P2 still fits 64 bits there, S1's x / 1 is taken in 128
+ * bits, and the pi table reaches isqrt(x) < 2^34.1 with the primes above 2^32
+ * held as 64-bit values (about 7 GB of device memory at 2^68). */
+pc_status pc_pi_count_wide(uint64_t x_lo, uint64_t x_hi, const pc_config *cfg, pc_result *res);
 
 /* Hard special-leaf sum S2h = -sum over hard leaves of mu(m) phi(u, b-1),
  * u = floor(x/(m p_b)) (Sections 2.3 and 3).  Requires

@@ -23,7 +23,8 @@ FLAG_NO_GRAPH = 16
 FLAG_BATCH_SEQUENTIAL = 32
 TABLE_PRIMES, TABLE_PI, TABLE_MULPF = 1, 2, 3
 
-EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
+EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_pi_count_wide", "pc_s2_hard", "pc_decompose",
+           "pc_p2",
            "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_workspace_bytes",
            "pc_pi_count_batch_async", "pc_pi_count_batch_noalloc", "pc_serve", "pc_read_table",
            "pc_wheel_c",
@@ -59,7 +60,7 @@ class _Result(C.Structure):
                [(n, C.c_uint32) for n in ("sieve_launches", "scan_launches")] + \
                [(n, C.c_double) for n in ("ms_total", "ms_tables", "ms_leaves", "ms_sieve",
                                           "ms_k_sieve", "ms_k_scan", "ms_k_easy", "ms_k_s1")] + \
-               [("n_easy_items", C.c_uint64)]
+               [("n_easy_items", C.c_uint64), ("x_hi", C.c_uint64)]
 
 
 @dataclass
@@ -100,6 +101,7 @@ class Result:
     ms_k_easy: float
     ms_k_s1: float
     n_easy_items: int
+    x_hi: int
 
 class ServeConfig(C.Structure):
     _fields_ = [("max_inflight", C.c_uint32), ("max_round", C.c_uint32),
@@ -126,6 +128,7 @@ def lib():
         u64, P = C.c_uint64, C.POINTER
         L.pc_pi_count.argtypes = [u64, C.c_double, P(u64)]
         L.pc_pi_count_ex.argtypes = [u64, P(Config), P(_Result)]
+        L.pc_pi_count_wide.argtypes = [u64, u64, P(Config), P(_Result)]
         L.pc_s2_hard.argtypes = [u64, u64, u64, P(I128)]
         L.pc_decompose.argtypes = [u64, u64, P(Config), P(_Result)]
         L.pc_p2.argtypes = [u64, u64, P(u64)]
@@ -138,7 +141,8 @@ def lib():
         L.pc_pi_count_batch_async.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                               C.c_size_t, C.c_void_p]
         L.pc_pi_count_batch_noalloc.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
-        for f in ("pc_pi_count", "pc_pi_count_ex", "pc_s2_hard", "pc_decompose", "pc_p2",
+        for f in ("pc_pi_count", "pc_pi_count_ex", "pc_pi_count_wide", "pc_s2_hard",
+                  "pc_decompose", "pc_p2",
                   "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_pi_count_batch_async",
                   "pc_pi_count_batch_noalloc", "pc_serve"):
             getattr(L, f).restype = C.c_int
@@ -184,6 +188,17 @@ def pi_count_ex(x: int, **cfg) -> Result:
     r = _Result()
     c = _config(**cfg)
     _check(lib().pc_pi_count_ex(x, C.byref(c), C.byref(r)))
+    return _result(r)
+
+
+def pi_count_wide(x: int, **cfg) -> Result:
+    """pi(x) and its decomposition for 0 <= x < 17 * 2^64 (x may exceed 2^64);
+    the result's x field is then x mod 2^64 and x_hi the high word."""
+    if not 0 <= x < 17 << 64:
+        raise ValueError("x must satisfy 0 <= x < 17 * 2^64")
+    r = _Result()
+    c = _config(**cfg)
+    _check(lib().pc_pi_count_wide(x & ((1 << 64) - 1), x >> 64, C.byref(c), C.byref(r)))
     return _result(r)
 
 

@@ -97,6 +97,25 @@ __device__ __forceinline__ uint32_t pc_quot31(uint64_t n, double nd, uint32_t d)
     return q - (rem < 0 ? 1u : 0u);
 }
 
+// pc_quot_in for a 64-bit divisor 2^32 <= d < 2^40 (the primes above 2^32 of
+// P2 when x > 2^64): n is x modulo 2^64 and nd the rounded x; the remainder of
+// the estimate, formed modulo 2^64, is small and exact.
+__device__ __forceinline__ bool pc_quot_in64(uint64_t n, double nd, uint64_t d, uint64_t base,
+                                             uint32_t span, uint32_t *off)
+{
+    const double t = nd / (double)d - (double)base;
+    if (!(t > -2.0 && t < (double)span + 2.0))
+        return false;
+    int32_t q = (int32_t)t;
+    const int64_t rem = (int64_t)(n - (base + (uint64_t)(int64_t)q) * d);
+    if (rem < 0)
+        q--;
+    else if (rem >= (int64_t)d)
+        q++;
+    *off = (uint32_t)q;
+    return q >= 0 && (uint32_t)q < span;
+}
+
 // floor(n / d) - base for 1 <= d < 2^32, base < 2^47, n/d < 2^47:
 // returns false if the quotient lies outside [base, base + span), span <
 // 2^30, else true with *off = the quotient - base.  nd = (double)n.
@@ -134,6 +153,42 @@ PC_HD uint64_t pc_div_any(uint64_t n, uint32_t d)
     while (rem >= (int64_t)d) {
         q++;
         rem -= d;
+    }
+    return q;
+}
+
+// Queries above 2^64: x = hi 2^64 + lo with hi <= 16 (x < 17 2^64).
+//
+// floor((hi 2^64 + lo) / d) for 1 <= d < 2^32 and hi < d (so the quotient is
+// below 2^64), by long division in base 2^32; *rem receives the remainder.
+PC_HD uint64_t pc_div_wide32(uint64_t hi, uint64_t lo, uint32_t d, uint32_t *rem)
+{
+    uint64_t r = hi;
+    const uint64_t n1 = (r << 32) | (lo >> 32);
+    const uint64_t q1 = n1 / d;
+    r = n1 - q1 * d;
+    const uint64_t n0 = (r << 32) | (lo & 0xFFFFFFFFull);
+    const uint64_t q0 = n0 / d;
+    if (rem)
+        *rem = (uint32_t)(n0 - q0 * d);
+    return (q1 << 32) | q0;
+}
+
+// floor(x / d) for x = hi 2^64 + lo (xd = x rounded to double) when the
+// quotient is below 2^52 and d < 2^62: the fp64 estimate is within 2 of the
+// quotient, so the remainder x - q d, formed modulo 2^64, is a small signed
+// number that steers the correction.
+PC_HD uint64_t pc_div_wide(uint64_t lo, double xd, uint64_t d)
+{
+    uint64_t q = (uint64_t)(xd / (double)d);
+    int64_t rem = (int64_t)(lo - q * d);
+    while (rem < 0) {
+        q--;
+        rem += (int64_t)d;
+    }
+    while (rem >= (int64_t)d) {
+        q++;
+        rem -= (int64_t)d;
     }
     return q;
 }

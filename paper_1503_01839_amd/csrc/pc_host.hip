@@ -110,9 +110,10 @@ struct Tables {
     bool base_ok = false;
     uint32_t nbase = 0;
     DevBuf base, nbase_d;
-    DevBuf pitab, primes, cnt_tmp, scan_tmp;
+    DevBuf pitab, primes, primes_hi, cnt_tmp, scan_tmp;
     uint64_t pi_limit = 0; // pi table and primes cover n <= pi_limit
     uint64_t nprimes = 0;
+    uint64_t k32 = ~0ull;  // index of the first prime above 2^32 (in primes_hi), if covered
     DevBuf recip, rcpd;
     uint64_t recip_n = 0;
     DevBuf mulpf;
@@ -122,8 +123,8 @@ struct Tables {
     uint32_t pattern_bits[kWheelC + 1] = {}, Qc[kWheelC + 1] = {}, phiQ[kWheelC + 1] = {};
     DevBuf lk_in, lk_out, chk;
     // the first entries of the device pi table, read back for planning the
-    // count staircase on the host (pi at isqrt(x / lo) < 2^24: x < 2^64 and
-    // every segment but the first starts at lo >= 2^16)
+    // count staircase on the host (pi at isqrt(x / lo) < 2^27: x < 17 2^64
+    // and every segment but the first starts at lo >= 2^16)
     std::vector<uint2> pi_host;
     uint64_t pi_host_max = 0; // pi_host answers n <= pi_host_max
 };
@@ -182,7 +183,7 @@ void ensure_pi(uint64_t need)
 {
     Tables &T = g_T;
     if (!T.base_ok) {
-        ensure(T.base, 8192 * 4, "base primes");
+        ensure(T.base, 32768 * 4, "base primes"); // the primes below 2^18
         ensure(T.nbase_d, 8, "base count");
         hipck(pc_launch_base_primes(ptr<uint32_t>(T.base), ptr<uint32_t>(T.nbase_d), g_stream),
               "base primes");
@@ -192,28 +193,42 @@ void ensure_pi(uint64_t need)
     }
     if (T.pi_limit >= need)
         return;
-    uint64_t lim = std::max<uint64_t>({need, 2 * T.pi_limit, 1ull << 22});
-    if (lim > 0xFFFFFFFFull)
-        lim = 0xFFFFFFFFull;
-    if (need > lim)
-        fail(PC_ERANGE, "pi table beyond 2^32 requested");
+    // up to 2^32 the table doubles as it grows; above, it is sized to the
+    // request (isqrt x <= 2^34.05 for x < 17 2^64), the primes above 2^32
+    // held as 64-bit values
+    constexpr uint64_t kPiMax = (1ull << 35) - 1, k2_32 = 0xFFFFFFFFull;
+    if (need > kPiMax)
+        fail(PC_ERANGE, "pi table beyond 2^35 requested");
+    uint64_t lim = std::max<uint64_t>({need, std::min(2 * T.pi_limit, k2_32), 1ull << 22});
     uint64_t nent = lim / 64 + 1;
-    if (nent > (1ull << 26))
-        nent = 1ull << 26;
     uint64_t covered = 64 * nent - 1;
+    if (covered > k2_32 && need <= k2_32) { // stay within 2^32 when that covers the request
+        nent = 1ull << 26;
+        covered = k2_32;
+    }
     ensure(T.pitab, nent * 8, "pi table");
     ensure(T.cnt_tmp, nent * 4, "pi counts");
     ensure(T.scan_tmp, (nent / 4096 + 2) * 4, "scan");
-    ensure(T.primes, (pi_upper(covered) + 4) * 4, "primes");
+    ensure(T.primes, (pi_upper(std::min(covered, k2_32)) + 4) * 4, "primes");
+    // pi(2^32) = 203280221, so the first prime above 2^32 is p_203280222
+    constexpr uint64_t kK32 = 203280222ull;
+    if (covered > k2_32)
+        ensure(T.primes_hi, (pi_upper(covered) + 4 - kK32) * 8, "primes above 2^32");
+    else
+        dfree(T.primes_hi);
     hipck(pc_launch_pitab(nent, ptr<uint32_t>(T.base), T.nbase, nullptr, ptr<uint32_t>(T.cnt_tmp),
                           ptr<uint2>(T.pitab), ptr<uint32_t>(T.primes),
+                          covered > k2_32 ? ptr<uint64_t>(T.primes_hi) : nullptr,
                           ptr<uint32_t>(T.scan_tmp), g_stream),
           "pi table");
     dfree(T.cnt_tmp);
     T.pi_limit = covered;
     T.nprimes = lookup({covered})[0];
+    T.k32 = covered > k2_32 ? kK32 : ~0ull;
+    if (covered > k2_32 && lookup({k2_32})[0] + 1 != kK32)
+        fail(PC_EINTERNAL, "pi(2^32) of the device table is not 203280221");
     T.recip_n = 0; // the primes array was rebuilt
-    const uint64_t nh = std::min<uint64_t>(nent, (1ull << 24) / 64);
+    const uint64_t nh = std::min<uint64_t>(nent, (1ull << 27) / 64);
     T.pi_host.resize(nh);
     hipck(hipMemcpyAsync(T.pi_host.data(), T.pitab.p, nh * 8, hipMemcpyDeviceToHost, g_stream),
           "D2H");
@@ -224,11 +239,14 @@ void ensure_pi(uint64_t need)
 // Row lengths of the count staircase of a query (x, c, nb): a hard leaf of
 // p_b has u < x / p_b^2, so the row whose first integer is lo > 0 keeps the
 // columns of the primes p_b <= isqrt(x / lo); the first row keeps all nb.
-uint32_t row_len(uint64_t x, uint32_t c, uint32_t nb, uint64_t lo)
+uint32_t row_len(pc_u128 x, uint32_t c, uint32_t nb, uint64_t lo)
 {
     if (lo == 0)
         return nb;
-    const uint64_t v = pc_isqrt(x / lo);
+    const pc_u128 q = x / lo;
+    if (q >> 64)
+        fail(PC_EINTERNAL, "row length: x / lo beyond 2^64");
+    const uint64_t v = pc_isqrt((uint64_t)q);
     const Tables &T = g_T;
     if (v > T.pi_host_max)
         fail(PC_EINTERNAL, "row length beyond the host copy of the pi table");
@@ -241,7 +259,9 @@ void ensure_recip(uint64_t kmax)
     Tables &T = g_T;
     if (T.recip_n >= kmax)
         return;
-    uint64_t k = std::min<uint64_t>(T.nprimes, std::max<uint64_t>(kmax, 2 * T.recip_n));
+    // (the reciprocal tables cover primes below 2^32 only: p_a+1 < 2^31 for every y)
+    uint64_t k = std::min<uint64_t>(std::min(T.nprimes, T.k32 - 1),
+                                    std::max<uint64_t>(kmax, 2 * T.recip_n));
     ensure(T.recip, (k + 1) * 8, "reciprocals");
     ensure(T.rcpd, (k + 1) * 8, "reciprocals");
     hipck(pc_launch_recip(ptr<uint32_t>(T.primes), ptr<uint64_t>(T.recip), ptr<double>(T.rcpd),
@@ -339,6 +359,8 @@ pc_tables tables_view(uint32_t c)
     Tables &T = g_T;
     pc_tables v{};
     v.primes = ptr<uint32_t>(T.primes);
+    v.primes_hi = ptr<uint64_t>(T.primes_hi);
+    v.k32 = T.k32;
     v.recip = ptr<uint64_t>(T.recip);
     v.rcpd = ptr<double>(T.rcpd);
     v.pitab = ptr<uint2>(T.pitab);
@@ -356,7 +378,8 @@ pc_tables tables_view(uint32_t c)
 void drop_tables()
 {
     Tables &T = g_T;
-    DevBuf *all[] = {&T.base, &T.nbase_d, &T.pitab, &T.primes, &T.cnt_tmp, &T.scan_tmp, &T.recip,
+    DevBuf *all[] = {&T.base, &T.nbase_d, &T.pitab, &T.primes, &T.primes_hi, &T.cnt_tmp,
+                     &T.scan_tmp, &T.recip,
                      &T.rcpd, &T.mulpf, &T.lk_in, &T.lk_out, &T.chk};
     for (DevBuf *b : all)
         dfree(*b);
@@ -368,6 +391,7 @@ void drop_tables()
     }
     T.base_ok = false;
     T.pi_limit = T.nprimes = T.recip_n = T.y_limit = 0;
+    T.k32 = ~0ull;
     T.pi_host.clear();
     T.pi_host_max = 0;
 }
@@ -396,7 +420,7 @@ pc_i128 to_abi(pc_s128 v)
 // log10 x.  alpha only moves work between the sieve (falls as 1/alpha) and
 // the easy leaves (rise), the segment and workgroup shape only how the sieve
 // runs; neither ever changes a result.
-const pc_alpha_entry &tuned_entry(uint64_t x)
+const pc_alpha_entry &tuned_entry(pc_u128 x)
 {
     const double lx = std::log10((double)x);
     const size_t n = sizeof kAlphaTable / sizeof kAlphaTable[0];
@@ -407,15 +431,37 @@ const pc_alpha_entry &tuned_entry(uint64_t x)
     return kAlphaTable[best];
 }
 
-double default_alpha(uint64_t x) { return tuned_entry(x).alpha; }
+double default_alpha(pc_u128 x) { return tuned_entry(x).alpha; }
 
 // alpha for a query in a batch round: the least total work rather than the
 // least latency of the query alone
 double default_batch_alpha(uint64_t x) { return tuned_entry(x).batch_alpha; }
 
-uint64_t choose_y(uint64_t x, double alpha)
+// Integer square and cube roots of a 128-bit x (the host planner of queries
+// above 2^64).
+uint64_t isqrt128(pc_u128 n)
 {
-    uint64_t r = pc_icbrt(x), s = pc_isqrt(x);
+    uint64_t r = (uint64_t)std::sqrt((long double)n);
+    while (r > 0 && (pc_u128)r * r > n)
+        r--;
+    while ((pc_u128)(r + 1) * (r + 1) <= n)
+        r++;
+    return r;
+}
+
+uint64_t icbrt128(pc_u128 n)
+{
+    uint64_t r = (uint64_t)std::cbrt((long double)n);
+    while (r > 0 && (pc_u128)r * r * r > n)
+        r--;
+    while ((pc_u128)(r + 1) * (r + 1) * (r + 1) <= n)
+        r++;
+    return r;
+}
+
+uint64_t choose_y(pc_u128 x, double alpha)
+{
+    uint64_t r = icbrt128(x), s = isqrt128(x);
     double yd = std::floor(alpha * (double)r);
     uint64_t y = yd >= (double)s ? s : (uint64_t)yd;
     if (y < r)
@@ -622,20 +668,28 @@ void plan_tiles(const pc_tables &T, const pc_query &Q, const Knobs &K, uint32_t 
             tiles.push_back(pc_tile{(uint32_t)(s0 + r), 0, Q.ncol, 0});
 }
 
-// Full decomposition for one (x, y); x >= 8, icbrt(x) <= y <= isqrt(x).
-void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
+// Full decomposition for one (x, y); x >= 8, icbrt(x) <= y <= isqrt(x),
+// x < 17 2^64 (above 2^64 every X_b of a prime p_b > p_c = 13 fits 64 bits).
+void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
 {
     auto t0 = clk::now();
     init_stream();
     QueryBufs &B = g_Q;
-    const uint64_t sx = pc_isqrt(x);
-    const uint64_t z = x / y;
+    const uint64_t x_hi = (uint64_t)(x >> 64);
+    if (x_hi > 16)
+        fail(PC_ERANGE, "x beyond 17 * 2^64");
+    const uint64_t sx = isqrt128(x);
+    if ((x / y) >> 64)
+        fail(PC_ERANGE, "x / y beyond 2^64");
+    const uint64_t z = (uint64_t)(x / y);
     ensure_pi(std::max<uint64_t>({sx, y, 1024}) + 1);
     std::vector<uint64_t> lk = lookup({y, sx, pc_isqrt(z)});
     const uint64_t a = lk[0], kx = lk[1], bmax = lk[2];
     const uint32_t c = (uint32_t)std::min<uint64_t>(kWheelC, a);
     if (c < 1)
         fail(PC_EINVAL, "y too small");
+    if (x_hi && c != 6)
+        fail(PC_EINTERNAL, "queries above 2^64 need the wheel of the primes up to 13");
     ensure_mulpf(y);
     ensure_recip(a + 1);
     ensure_wheel(c);
@@ -644,7 +698,9 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
 
     const pc_tables T = tables_view(c);
     pc_query Q{};
-    Q.x = x;
+    Q.x = (uint64_t)x;
+    Q.x_hi = x_hi;
+    Q.xd = (double)x;
     Q.y = y;
     Q.z = z;
     Q.y1 = y + 1;
@@ -679,7 +735,7 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
     // --- per-query tables and the leaves outside the sieve ---
     ensure(B.Xb, (a + 2) * 8, "X_b");
     Q.Xb = Q.Xb_w = ptr<uint64_t>(B.Xb);
-    hipck(pc_launch_xb(T, x, (uint32_t)a, ptr<uint64_t>(B.Xb), g_stream), "X_b");
+    hipck(pc_launch_xb(T, (uint64_t)x, x_hi, (uint32_t)a, ptr<uint64_t>(B.Xb), g_stream), "X_b");
 
     ensure(B.sums, sizeof(pc_sums), "sums");
     ensure(B.fin, sizeof(pc_final), "final");
@@ -1018,7 +1074,8 @@ void run_query(uint64_t x, uint64_t y, const Knobs &K, pc_result *res)
 
     if (res) {
         memset(res, 0, sizeof *res);
-        res->x = x;
+        res->x = (uint64_t)x;
+        res->x_hi = x_hi;
         res->y = y;
         res->a = a;
         res->c = c;
@@ -1095,15 +1152,15 @@ template <typename F> pc_status guarded(F &&f)
     }
 }
 
-void pi_one(uint64_t x, const Knobs &K, double alpha, pc_result *res, uint64_t *pi)
+void pi_one(pc_u128 x, const Knobs &K, double alpha, pc_result *res, uint64_t *pi)
 {
     if (std::isnan(alpha) || alpha < 0)
         fail(PC_EINVAL, "alpha must be >= 0 (0 = tuned)");
     if (x < kSmallX) {
-        uint64_t v = small_pi(x);
+        uint64_t v = small_pi((uint64_t)x);
         if (res) {
             memset(res, 0, sizeof *res);
-            res->x = x;
+            res->x = (uint64_t)x;
             res->pi = v;
         }
         *pi = v;
@@ -1333,6 +1390,8 @@ void round_queries(const std::vector<BatchQuery> &R, const RoundPlan &P, char *b
         };
         const uint64_t na = b.a + 2;
         Q.x = b.x;
+        Q.x_hi = 0;
+        Q.xd = (double)b.x;
         Q.y = b.y;
         Q.z = b.z;
         Q.y1 = b.y + 1;
@@ -2113,6 +2172,23 @@ pc_status pc_pi_count_ex(uint64_t x, const pc_config *cfg, pc_result *res)
     return st;
 }
 
+pc_status pc_pi_count_wide(uint64_t x_lo, uint64_t x_hi, const pc_config *cfg, pc_result *res)
+{
+    pc_result r;
+    uint64_t v = 0;
+    pc_status st = guarded([&] {
+        if (x_hi > 16)
+            fail(PC_ERANGE, "x must be below 17 * 2^64");
+        Knobs K = knobs_from(cfg);
+        if (cfg && (cfg->flags & PC_FLAG_REBUILD_TABLES))
+            drop_tables();
+        pi_one(((pc_u128)x_hi << 64) | x_lo, K, cfg ? cfg->alpha : 0.0, &r, &v);
+    });
+    if (st == PC_OK && res)
+        *res = r;
+    return st;
+}
+
 pc_status pc_decompose(uint64_t x, uint64_t y, const pc_config *cfg, pc_result *res)
 {
     pc_result r;
@@ -2290,6 +2366,8 @@ pc_status pc_read_table(int which, uint64_t lo, uint64_t n, void *out)
                     fail(PC_EINVAL, "p_k beyond 2^32 requested");
                 lim = std::min<uint64_t>(2 * T.pi_limit + 2, 0xFFFFFFFFull);
             }
+            if (last >= T.k32) // the 32-bit array ends below 2^32
+                fail(PC_EINVAL, "p_k beyond 2^32 requested");
             hipck(hipMemcpyAsync(out, ptr<uint32_t>(T.primes) + lo, n * 4, hipMemcpyDeviceToHost,
                                  g_stream),
                   "D2H");

@@ -20,7 +20,9 @@ struct pc_tile {
 
 // Shared device tables (read-only during a query).
 struct pc_tables {
-    const uint32_t *primes; // primes[k] = p_k, 1-based (primes[1] = 2)
+    const uint32_t *primes; // primes[k] = p_k, 1-based (primes[1] = 2), p_k < 2^32
+    const uint64_t *primes_hi; // p_k for k >= k32 (the primes above 2^32): primes_hi[k - k32]
+    uint64_t k32;           // index of the first prime above 2^32 (UINT64_MAX: none tabulated)
     const uint64_t *recip;  // recip[k] = floor((2^64-1)/p_k) for k <= n_recip
     const double *rcpd;     // rcpd[k] = 1/p_k correctly rounded, k <= n_recip
     const uint2 *pitab;     // pi table, see pc_pi_lookup
@@ -38,7 +40,9 @@ struct pc_sums;
 
 // Per-query scalars.
 struct pc_query {
-    uint64_t x, y, z;
+    uint64_t x, y, z;       // x: its low 64 bits when x_hi != 0
+    uint64_t x_hi;          // x = x_hi 2^64 + x, x_hi <= 16
+    double xd;              // x rounded to double
     uint64_t y1, recip_y1;  // y + 1 and its reciprocal
     uint64_t sqrtx;         // isqrt(x)
     uint64_t sqrty;         // isqrt(y): p_b^2 > y  <=>  p_b > sqrty
@@ -119,7 +123,7 @@ struct pc_sieve_args {
 hipError_t pc_launch_base_primes(uint32_t *base, uint32_t *nbase, hipStream_t s);
 hipError_t pc_launch_pitab(uint64_t nentries, const uint32_t *base, uint32_t nbase,
                            uint32_t *bits, uint32_t *cnts, uint2 *pitab, uint32_t *primes,
-                           uint32_t *scan_tmp, hipStream_t s);
+                           uint64_t *primes_hi, uint32_t *scan_tmp, hipStream_t s);
 hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, double *rcpd, uint32_t n,
                            hipStream_t s);
 hipError_t pc_launch_mulpf(const uint32_t *primes, uint32_t nsmall, uint64_t ymax,
@@ -131,7 +135,8 @@ hipError_t pc_launch_wheel(uint32_t c, const uint32_t *primes, uint32_t *pattern
                            hipStream_t s);
 hipError_t pc_launch_lookup(const uint2 *pitab, const uint64_t *in, uint32_t n, uint64_t *out,
                             hipStream_t s);
-hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint32_t a, uint64_t *Xb, hipStream_t s);
+hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint64_t x_hi, uint32_t a, uint64_t *Xb,
+                        hipStream_t s);
 
 // Leaves outside the sieve: S1, trivial and easy special leaves.  The set-up
 // and easy kernels use the per-query arrays named in pc_query.

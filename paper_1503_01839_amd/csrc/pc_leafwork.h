@@ -15,13 +15,20 @@
 
 #define PC_MODEBIT (1ull << 63)
 
-// X_b = floor(x / p_b) for 1 <= b <= a (X_0 = x).
+// X_b = floor(x / p_b) for 1 <= b <= a (X_0 = x).  Above 2^64 (x_hi != 0)
+// the quotients of p_b <= x_hi, all with b <= c and never read, are stored as
+// 2^64 - 1.
 __device__ __forceinline__ void pc_xb_item(const pc_tables &T, const pc_query &Q, uint32_t b)
 {
-    if (b == 0)
-        Q.Xb_w[0] = Q.x;
-    else if (b <= Q.a)
-        Q.Xb_w[b] = pc_div(Q.x, T.primes[b], T.recip[b]);
+    if (b == 0) {
+        Q.Xb_w[0] = Q.x_hi ? ~0ull : Q.x;
+    } else if (b <= Q.a) {
+        const uint32_t p = T.primes[b];
+        if (!Q.x_hi)
+            Q.Xb_w[b] = pc_div(Q.x, p, T.recip[b]);
+        else
+            Q.Xb_w[b] = Q.x_hi < p ? pc_div_wide32(Q.x_hi, Q.x, p, nullptr) : ~0ull;
+    }
 }
 
 // The S1 term of n (pcc = p_c): adds mu(n) phi(x/n, c) to *acc when n <= y is
@@ -33,10 +40,21 @@ __device__ __forceinline__ bool pc_s1_item(const pc_tables &T, const pc_query &Q
     const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
     if (v == 0 || l <= pcc) // mu(n) = 0, or n has a prime factor <= p_c
         return false;
-    const uint64_t u = pc_div_any(Q.x, (uint32_t)n);
-    const uint64_t qq = pc_div(u, Q.Qc, Q.recip_Qc);
-    const uint64_t phi = qq * T.phiQ + T.phitab[u - qq * Q.Qc];
-    *acc += v > 0 ? (pc_s128)phi : -(pc_s128)phi;
+    pc_s128 phi;
+    if (!Q.x_hi) {
+        const uint64_t u = pc_div_any(Q.x, (uint32_t)n);
+        const uint64_t qq = pc_div(u, Q.Qc, Q.recip_Qc);
+        phi = (pc_s128)(qq * T.phiQ + T.phitab[u - qq * Q.Qc]);
+    } else if (n == 1) { // u = x above 2^64: x = qq Q_c + r with qq < 2^64
+        uint32_t r;
+        const uint64_t qq = pc_div_wide32(Q.x_hi, Q.x, (uint32_t)Q.Qc, &r);
+        phi = (pc_s128)qq * T.phiQ + T.phitab[r];
+    } else { // n >= 17 > x_hi (lpf(n) > p_c = 13): u = x / n < 2^64
+        const uint64_t u = pc_div_wide32(Q.x_hi, Q.x, (uint32_t)n, nullptr);
+        const uint64_t qq = pc_div(u, Q.Qc, Q.recip_Qc);
+        phi = (pc_s128)(qq * T.phiQ + T.phitab[u - qq * Q.Qc]);
+    }
+    *acc += v > 0 ? phi : -phi;
     return true;
 }
 

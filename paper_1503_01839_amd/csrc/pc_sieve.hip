@@ -962,8 +962,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         total = build_pre(); // (the running total skips the cleared-only columns)
         uint32_t k1 = 1, k2 = 0;
         {
-            const uint64_t tA = pc_div(Q.x, hi, rhi);              // x/p < hi  <=> p > x/hi
-            const uint64_t tB = lo ? pc_div(Q.x, lo, rlo) : ~0ull; // x/p >= lo <=> p <= x/lo
+            // x/p < hi <=> p > x/hi;  x/p >= lo <=> p <= x/lo  (above 2^64: every
+            // segment but the first has lo >= 2^16, so both quotients are < 2^52)
+            const uint64_t tA = Q.x_hi ? pc_div_wide(Q.x, Q.xd, hi) : pc_div(Q.x, hi, rhi);
+            const uint64_t tB =
+                !lo ? ~0ull : Q.x_hi ? pc_div_wide(Q.x, Q.xd, lo) : pc_div(Q.x, lo, rlo);
             const uint64_t pl = tA > Q.y ? tA : Q.y;
             const uint64_t ph = tB < Q.sqrtx ? tB : Q.sqrtx;
             if (pl < ph) {
@@ -972,11 +975,15 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             }
         }
         if (MODE != PC_MODE_COUNT) {
-            const uint64_t x = Q.x;
-            const double xd = (double)x;
+            const uint64_t x = Q.x;     // modulo 2^64 above 2^64
+            const double xd = Q.xd;
             for (uint32_t k = k1 + tid; k <= k2; k += T) {
                 uint32_t off; // x/p_k - lo
-                if (!pc_quot_in(x, xd, TB.primes[k], lo, 2u << LOG2_S, &off)) {
+                const bool in = k < TB.k32
+                                    ? pc_quot_in(x, xd, TB.primes[k], lo, 2u << LOG2_S, &off)
+                                    : pc_quot_in64(x, xd, TB.primes_hi[k - TB.k32], lo,
+                                                   2u << LOG2_S, &off);
+                if (!in) {
                     atomicOr(A.err, 4);
                     continue;
                 }

@@ -16,25 +16,36 @@
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_base_primes(uint32_t *base, uint32_t *nbase)
 {
-    __shared__ uint32_t bits[1024]; // bit j of word w <-> 64w + 2j + 1
+    constexpr uint32_t W = 4096, N = 64 * W; // the odd numbers below 2^18
+    __shared__ uint32_t bits[W]; // bit j of word w <-> 64w + 2j + 1
     __shared__ uint32_t scr[16];
     const uint32_t t = threadIdx.x;
-    bits[t] = t == 0 ? 0xFFFFFFFEu : 0xFFFFFFFFu; // 1 is not prime
+    for (uint32_t w = t; w < W; w += 1024)
+        bits[w] = w == 0 ? 0xFFFFFFFEu : 0xFFFFFFFFu; // 1 is not prime
     __syncthreads();
-    // odd q in [3, 255], the odd multiples from q^2 shared by all threads;
+    // odd q in [3, 511], the odd multiples from q^2 shared by all threads;
     // composite q only repeats its factors' work
-    for (uint32_t q = 3; q < 256; q += 2)
-        for (uint32_t n = q * q + 2 * q * t; n < 65536u; n += 2 * q * 1024) {
+    for (uint32_t q = 3; q < 512; q += 2)
+        for (uint32_t n = q * q + 2 * q * t; n < N; n += 2 * q * 1024) {
             const uint32_t i = n >> 1;
             atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
         }
     __syncthreads();
-    uint32_t w = bits[t], total;
-    uint32_t off = pc_block_excl_scan<1024>((uint32_t)__builtin_popcount(w), scr, &total);
-    while (w) {
-        uint32_t j = __builtin_ctz(w);
-        w &= w - 1;
-        base[off++] = 64 * t + 2 * j + 1;
+    // thread t owns words 4t .. 4t + 3
+    uint32_t w4[4], c = 0;
+    for (uint32_t k = 0; k < 4; k++) {
+        w4[k] = bits[4 * t + k];
+        c += (uint32_t)__builtin_popcount(w4[k]);
+    }
+    uint32_t total;
+    uint32_t off = pc_block_excl_scan<1024>(c, scr, &total);
+    for (uint32_t k = 0; k < 4; k++) {
+        uint32_t w = w4[k];
+        while (w) {
+            uint32_t j = __builtin_ctz(w);
+            w &= w - 1;
+            base[off++] = 64 * (4 * t + k) + 2 * j + 1;
+        }
     }
     if (t == 0)
         *nbase = total;
@@ -57,20 +68,19 @@ __global__ __launch_bounds__(PT_T) void k_sieve_pitab(uint64_t nent, const uint3
     const uint64_t e0 = (uint64_t)blockIdx.x * PT_WORDS;
     for (uint32_t i = t; i < PT_WORDS; i += PT_T)
         bits[i] = 0xFFFFFFFFu;
-    // The table has at most 2^26 entries, so every integer it covers is below
-    // 2^32 and the first multiple of a prime comes from a 32-bit remainder.
-    const uint32_t nlo = (uint32_t)(64 * e0);       // first integer covered
+    const uint64_t nlo = 64 * e0;                   // first integer covered
     const uint64_t nhi = 64 * (e0 + PT_WORDS) - 1;  // last integer covered
     const uint32_t NBIT = PT_WORDS * 32;
     // bit index (from nlo) of the first odd multiple of q that is >= nlo and >= q^2
     auto start = [&](uint32_t q) -> uint32_t {
-        const uint32_t r = nlo % q;
-        uint64_t m = (uint64_t)nlo + (r ? q - r : 0);
+        const uint32_t r = (uint32_t)(nlo % q);
+        uint64_t m = nlo + (r ? q - r : 0);
         if ((m & 1) == 0)
             m += q;
         if (m < (uint64_t)q * q)
             m = (uint64_t)q * q;
-        return (uint32_t)(((m - 1) >> 1) - (nlo >> 1));
+        const uint64_t bi = ((m - 1) >> 1) - (nlo >> 1);
+        return bi < NBIT ? (uint32_t)bi : NBIT;
     };
     // small primes (q < 4 PT_T, q^2 <= nhi: a prefix of base[], at most PT_T
     // of them): their starts once per workgroup, then all threads share the
@@ -186,9 +196,13 @@ hipError_t pc_launch_scan_u64(uint64_t *data, uint64_t n, uint64_t *tmp, uint64_
     return scan_excl<uint64_t>(data, n, tmp, total, s);
 }
 
-// tab[e].y = number of odd primes in entries < e; primes[] filled in order.
-__global__ void k_pitab_pack(uint64_t nent, uint2 *tab, const uint32_t *pre, uint32_t *primes)
+// tab[e].y = number of odd primes in entries < e; primes[] filled in order,
+// the primes of entries e >= 2^26 (above 2^32) into primes_hi[k - k32], k32
+// the index of the first of them.
+__global__ void k_pitab_pack(uint64_t nent, uint2 *tab, const uint32_t *pre, uint32_t *primes,
+                             uint64_t *primes_hi)
 {
+    constexpr uint64_t E32 = 1ull << 26;
     uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e == 0) {
         primes[0] = 0;
@@ -200,26 +214,38 @@ __global__ void k_pitab_pack(uint64_t nent, uint2 *tab, const uint32_t *pre, uin
     uint32_t w = tab[e].x;
     tab[e].y = off;
     uint32_t k = off + 2; // odd prime of rank off is p_{off+2}
-    while (w) {
-        uint32_t j = __builtin_ctz(w);
-        w &= w - 1;
-        primes[k++] = (uint32_t)(64 * e + 2 * j + 1);
+    if (e < E32) {
+        while (w) {
+            uint32_t j = __builtin_ctz(w);
+            w &= w - 1;
+            primes[k++] = (uint32_t)(64 * e + 2 * j + 1);
+        }
+    } else {
+        const uint32_t k32 = pre[E32] + 2;
+        while (w) {
+            uint32_t j = __builtin_ctz(w);
+            w &= w - 1;
+            primes_hi[k++ - k32] = 64 * e + 2 * j + 1;
+        }
     }
 }
 
 hipError_t pc_launch_pitab(uint64_t nent, const uint32_t *base, uint32_t nbase, uint32_t *bits,
-                           uint32_t *cnts, uint2 *pitab, uint32_t *primes, uint32_t *scan_tmp,
-                           hipStream_t s)
+                           uint32_t *cnts, uint2 *pitab, uint32_t *primes, uint64_t *primes_hi,
+                           uint32_t *scan_tmp, hipStream_t s)
 {
     (void)bits;
-    if (nent > (1ull << 26)) // k_sieve_pitab's 32-bit arithmetic
+    // base primes reach 2^18, so the table reaches 2^36; prefix counts are
+    // 32-bit (pi(2^36) < 2^32)
+    if (nent > (1ull << 30) || (nent > (1ull << 26) && !primes_hi))
         return hipErrorInvalidValue;
     uint32_t nblk = (uint32_t)((nent + PT_WORDS - 1) / PT_WORDS);
     k_sieve_pitab<<<nblk, PT_T, 0, s>>>(nent, base, nbase, pitab, cnts);
     hipError_t e = scan_excl<uint32_t>(cnts, nent, scan_tmp, (uint32_t *)nullptr, s);
     if (e != hipSuccess)
         return e;
-    k_pitab_pack<<<(uint32_t)((nent + 255) / 256), 256, 0, s>>>(nent, pitab, cnts, primes);
+    k_pitab_pack<<<(uint32_t)((nent + 255) / 256), 256, 0, s>>>(nent, pitab, cnts, primes,
+                                                                 primes_hi);
     return hipGetLastError();
 }
 
@@ -460,17 +486,26 @@ hipError_t pc_launch_lookup(const uint2 *pitab, const uint64_t *in, uint32_t n, 
     return hipGetLastError();
 }
 
-__global__ void k_xb(pc_tables T, uint64_t x, uint32_t a, uint64_t *Xb)
+// X_b = floor(x / p_b), x = x_hi 2^64 + x; above 2^64 the quotients of the
+// primes p_b <= x_hi (b <= c: never read) do not fit and are stored as
+// 2^64 - 1.
+__global__ void k_xb(pc_tables T, uint64_t x, uint64_t x_hi, uint32_t a, uint64_t *Xb)
 {
     uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b == 0)
-        Xb[0] = x;
-    if (b >= 1 && b <= a)
-        Xb[b] = pc_div(x, T.primes[b], T.recip[b]);
+        Xb[0] = x_hi ? ~0ull : x;
+    if (b >= 1 && b <= a) {
+        const uint32_t p = T.primes[b];
+        if (!x_hi)
+            Xb[b] = pc_div(x, p, T.recip[b]);
+        else
+            Xb[b] = x_hi < p ? pc_div_wide32(x_hi, x, p, nullptr) : ~0ull;
+    }
 }
 
-hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint32_t a, uint64_t *Xb, hipStream_t s)
+hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint64_t x_hi, uint32_t a, uint64_t *Xb,
+                        hipStream_t s)
 {
-    k_xb<<<(a + 256) / 256, 256, 0, s>>>(T, x, a, Xb);
+    k_xb<<<(a + 256) / 256, 256, 0, s>>>(T, x, x_hi, a, Xb);
     return hipGetLastError();
 }
