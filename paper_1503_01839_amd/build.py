@@ -27,29 +27,32 @@ def _compile(src: str) -> str:
     return obj
 
 
-# The GPU test of the device quotient helpers (tests/device): a shared library
-# of its own, compiled from the test's source against csrc/pc_device.h.
-DEVICE_TEST_SRC = os.path.join(ROOT, "tests", "device", "div_check.hip")
-DEVICE_TEST_LIB = os.path.join(ROOT, "tests", "device", "libdivcheck.so")
+# The GPU tests' device libraries (tests/device): each a shared library of its
+# own, compiled from the test's source against csrc/pc_device.h: the check of
+# the device quotient helpers, and the comparison of two pi tables.
+DEVICE_TESTS = [(os.path.join(ROOT, "tests", "device", src), os.path.join(ROOT, "tests", "device", lib))
+                for src, lib in (("div_check.hip", "libdivcheck.so"),
+                                 ("pi_table_bench.hip", "libpitable.so"))]
 
 
-def _device_test() -> str:
-    tmp = DEVICE_TEST_LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-shared", DEVICE_TEST_SRC, "-o", tmp]
+def _device_test(src: str, lib: str) -> str:
+    tmp = lib + ".tmp"
+    cmd = ["hipcc", *FLAGS, "-shared", src, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {DEVICE_TEST_SRC}:\n{r.stderr}")
-    os.replace(tmp, DEVICE_TEST_LIB)
-    return DEVICE_TEST_LIB
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    os.replace(tmp, lib)
+    return lib
 
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
-        dev = ex.submit(_device_test) if os.path.exists(DEVICE_TEST_SRC) else None
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + len(DEVICE_TESTS)) as ex:
+        devs = [ex.submit(_device_test, src, lib) for src, lib in DEVICE_TESTS
+                if os.path.exists(src)]
         objs = list(ex.map(_compile, SOURCES))
-        if dev is not None:
-            dev.result()
+        for d in devs:
+            d.result()
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,7 +1,10 @@
 // Device check of the quotient helpers the kernels use (pc_device.h), run on
 // the GPU itself: the fp64 reciprocal with Newton steps (pc_rcp_f64), the
-// varying-divisor quotients pc_quot32 and pc_quot_in, the fp64 division
-// quotient pc_div_small_q and the reciprocal division pc_div.  Every result q
+// varying-divisor quotients pc_quot32, pc_quot31, pc_quot31r (stored
+// reciprocal) and pc_quot_in, the fp64 division quotient pc_div_small_q, the
+// reciprocal division pc_div, and the helpers of x above 2^64: pc_div_wide32
+// (long division of a 128-bit dividend), pc_div_wide and pc_quot_in64 (a
+// 128-bit dividend given as its low word and its value in fp64).  Every result q
 // is checked exactly, without any division: either n is built as q d + r
 // with r < d, or q d <= n < (q + 1) d is tested in 128-bit arithmetic.
 // Inputs: pairs drawn from a counter-based generator (splitmix64 of the pair
@@ -109,6 +112,64 @@ __global__ void k_div_check(uint64_t n_pairs, uint64_t seed, unsigned long long 
                 atomicMin(&first[4], (unsigned long long)i);
             }
         }
+        // pc_quot31r / pc_quot31: divisors below 2^31, quotients below 2^32 - 1
+        {
+            const uint32_t d31 = d >> 1 ? d >> 1 : 1u;
+            const uint64_t q = (r2 >> (32 + ((r1 >> 16) & 31))) % 0xFFFFFFFEull;
+            const uint64_t rr = rm == 0 ? 0 : rm == 1 ? d31 - 1 : (uint64_t)(uint32_t)r3 % d31;
+            const uint64_t n = q * d31 + rr;
+            if (!exact(n, d31, pc_quot31r(n, (double)n, d31, 1.0 / (double)d31))) {
+                atomicAdd(&fails[5], 1ull);
+                atomicMin(&first[5], (unsigned long long)i);
+            }
+            if (!exact(n, d31, pc_quot31(n, (double)n, d31))) {
+                atomicAdd(&fails[6], 1ull);
+                atomicMin(&first[6], (unsigned long long)i);
+            }
+        }
+        // pc_div_wide32: x = hi 2^64 + lo with hi < d
+        {
+            const uint64_t hi = r2 % d, lo = r3;
+            uint32_t rem = 0xFFFFFFFFu;
+            const uint64_t q = pc_div_wide32(hi, lo, d, &rem);
+            const pc_u128 x = ((pc_u128)hi << 64) | lo;
+            if (rem >= d || (pc_u128)q * d + rem != x) {
+                atomicAdd(&fails[7], 1ull);
+                atomicMin(&first[7], (unsigned long long)i);
+            }
+        }
+        // pc_div_wide: quotient below 2^52, divisor below 2^46, x up to 2^98
+        // given as its low word and its fp64 value
+        {
+            uint64_t D = r0 >> (18 + ((r1 >> 32) & 63) % 46);
+            if (D == 0)
+                D = 1;
+            const uint64_t q = r2 >> (12 + ((r1 >> 56) & 31));
+            const uint64_t rr = rm == 0 ? 0 : rm == 1 ? D - 1 : r3 % D;
+            const pc_u128 x = (pc_u128)q * D + rr;
+            if (pc_div_wide((uint64_t)x, (double)x, D) != q) {
+                atomicAdd(&fails[8], 1ull);
+                atomicMin(&first[8], (unsigned long long)i);
+            }
+        }
+        // pc_quot_in64: divisors in [2^32, 2^40), quotient < 2^47, x beyond 2^64
+        {
+            const uint64_t D = (1ull << 32) | (r0 >> (24 + (r1 & 7)));
+            const uint64_t q = (r2 >> (17 + ((r1 >> 24) & 31))) & ((1ull << 47) - 1);
+            const uint64_t rr = rm == 0 ? 0 : rm == 1 ? D - 1 : r3 % D;
+            const pc_u128 x = (pc_u128)q * D + rr;
+            const uint32_t span = 1u + (uint32_t)(r3 >> 35);
+            const int64_t shift = (int64_t)((r0 >> 3) & 7) - 3;
+            int64_t b = (q > (uint64_t)span ? (int64_t)(q - span / 2) : 0) + shift;
+            const uint64_t base = b < 0 ? 0 : (uint64_t)b;
+            uint32_t off = 0xFFFFFFFFu;
+            const bool in = pc_quot_in64((uint64_t)x, (double)x, D, base, span, &off);
+            const bool want_in = q >= base && q < base + span;
+            if (in != want_in || (in && base + off != q)) {
+                atomicAdd(&fails[9], 1ull);
+                atomicMin(&first[9], (unsigned long long)i);
+            }
+        }
     }
 }
 
@@ -155,20 +216,26 @@ __global__ void k_div_edges(unsigned long long *fails)
 } // namespace
 
 // Runs n_pairs random pairs (seeded) and the edge pairs on the current device;
-// fails_out[0..4] = failures of pc_quot32, pc_quot_in, pc_div_small_q, pc_div,
-// pc_rcp_f64; first_out[0..4] = the first failing pair index (or ~0).
+// fails_out[0..9] = failures of pc_quot32, pc_quot_in, pc_div_small_q, pc_div,
+// pc_rcp_f64, pc_quot31r, pc_quot31, pc_div_wide32, pc_div_wide,
+// pc_quot_in64; first_out[0..9] = the first failing pair index (or ~0).
 // Returns 0, or the HIP error code.
 extern "C" int pc_div_check(uint64_t n_pairs, uint64_t seed, uint64_t *fails_out,
                             uint64_t *first_out)
 {
+    constexpr int NH = 10;
     unsigned long long *d = nullptr;
-    hipError_t e = hipMalloc(&d, 10 * sizeof(unsigned long long));
+    hipError_t e = hipMalloc(&d, 2 * NH * sizeof(unsigned long long));
     if (e != hipSuccess)
         return (int)e;
-    unsigned long long init[10] = {0, 0, 0, 0, 0, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull};
+    unsigned long long init[2 * NH];
+    for (int k = 0; k < NH; k++) {
+        init[k] = 0;
+        init[NH + k] = ~0ull;
+    }
     e = hipMemcpy(d, init, sizeof init, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        k_div_check<<<4096, 256>>>(n_pairs, seed, d, d + 5);
+        k_div_check<<<4096, 256>>>(n_pairs, seed, d, d + NH);
         k_div_edges<<<1, 640>>>(d);
         e = hipDeviceSynchronize();
     }
@@ -177,9 +244,9 @@ extern "C" int pc_div_check(uint64_t n_pairs, uint64_t seed, uint64_t *fails_out
     (void)hipFree(d);
     if (e != hipSuccess)
         return (int)e;
-    for (int k = 0; k < 5; k++) {
+    for (int k = 0; k < NH; k++) {
         fails_out[k] = init[k];
-        first_out[k] = init[5 + k];
+        first_out[k] = init[NH + k];
     }
     return 0;
 }
