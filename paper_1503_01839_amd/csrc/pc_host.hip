@@ -123,8 +123,9 @@ struct Tables {
     uint32_t pattern_bits[kWheelC + 1] = {}, Qc[kWheelC + 1] = {}, phiQ[kWheelC + 1] = {};
     DevBuf lk_in, lk_out, chk;
     // the first entries of the device pi table, read back for planning the
-    // count staircase on the host (pi at isqrt(x / lo) < 2^27: x < 17 2^64
-    // and every segment but the first starts at lo >= 2^16)
+    // count staircase on the host (pi at isqrt(x / lo): every segment but the
+    // first starts at lo >= 2^16, so below 2^24 for x < 2^64 and below 2^27
+    // for x < 17 2^64)
     std::vector<uint2> pi_host;
     uint64_t pi_host_max = 0; // pi_host answers n <= pi_host_max
 };
@@ -228,7 +229,9 @@ void ensure_pi(uint64_t need)
     if (covered > k2_32 && lookup({k2_32})[0] + 1 != kK32)
         fail(PC_EINTERNAL, "pi(2^32) of the device table is not 203280221");
     T.recip_n = 0; // the primes array was rebuilt
-    const uint64_t nh = std::min<uint64_t>(nent, (1ull << 27) / 64);
+    // the host copy answers the staircase's pi(isqrt(x / lo)): below 2^24 for
+    // x < 2^64, below 2^27 for the queries up to 17 2^64 (tables above 2^32)
+    const uint64_t nh = std::min<uint64_t>(nent, (covered > k2_32 ? 1ull << 27 : 1ull << 24) / 64);
     T.pi_host.resize(nh);
     hipck(hipMemcpyAsync(T.pi_host.data(), T.pitab.p, nh * 8, hipMemcpyDeviceToHost, g_stream),
           "D2H");
