@@ -359,8 +359,8 @@ def main():
     modes = tuple(m for m in args.serve_modes.split(",") if m)
     if not modes or any(m not in ("served", "plain") for m in modes):
         raise SystemExit("--serve-modes takes served and/or plain")
-    if args.serve_piece < 0 or not 0 <= args.x < 17 * 2**64:
-        raise SystemExit("--serve-piece must be >= 0 and --x in [0, 17 * 2^64)")
+    if args.serve_piece < 0 or not 0 <= args.x <= 2**72:
+        raise SystemExit("--serve-piece must be >= 0 and --x in [0, 2^72]")
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return

@@ -96,6 +96,7 @@ typedef struct {
                                        a single prime m, or a value K = pi(u) of a run
                                        of primes m sharing it                   */
     uint64_t x_hi;                  /* x = x_hi * 2^64 + x (pc_pi_count_wide)       */
+    uint64_t pi_hi;                 /* pi(x) = pi_hi * 2^64 + pi (pc_pi_count_wide) */
 } pc_result;
 
 /* ---------------------------------------------------------------------- */
@@ -110,14 +111,15 @@ pc_status pc_pi_count(uint64_t x, double alpha, uint64_t *pi_out);
  * decomposition in *res (may be NULL). */
 pc_status pc_pi_count_ex(uint64_t x, const pc_config *cfg, pc_result *res);
 
-/* pi(x) for x = x_hi * 2^64 + x_lo, 0 <= x < 17 * 2^64 (x_hi <= 16, else
- * PC_ERANGE): the range of Table 2's 2^64 .. 2^68 and Table 1's 10^20
- * (Section 5).  Knobs and *res (either may be NULL) as in pc_pi_count_ex;
- * res->x and res->x_hi hold the two words of x.  Above 2^64 the method is
- * unchanged: every X_b = x / p_b with p_b > p_c = 13, every leaf quotient and
- * every x / p of P2 still fits 64 bits there, S1's x / 1 is taken in 128
- * bits, and the pi table reaches isqrt(x) < 2^34.1 with the primes above 2^32
- * held as 64-bit values (about 7 GB of device memory at 2^68). */
+/* pi(x) for x = x_hi * 2^64 + x_lo, 0 <= x <= 2^72 (else PC_ERANGE): the
+ * range of Table 2's 2^64 .. 2^72 and Table 1's 10^20 and 10^21 (Section 5).
+ * Knobs and *res (either may be NULL) as in pc_pi_count_ex; res->x, res->x_hi
+ * hold the two words of x and res->pi, res->pi_hi those of pi(x) (pi(x) passes
+ * 2^64 from x = 2^70 on).  Above 2^64 the method is unchanged: every leaf
+ * quotient, every x / p of P2 and every segment bound stays below 2^64; X_b,
+ * S1's x / n and the sums are taken in 128 bits; the pi table reaches
+ * isqrt(x) <= 2^36 with the primes above 2^32 held as 64-bit values (about
+ * 30 GB of device memory at 2^72). */
 pc_status pc_pi_count_wide(uint64_t x_lo, uint64_t x_hi, const pc_config *cfg, pc_result *res);
 
 /* Hard special-leaf sum S2h = -sum over hard leaves of mu(m) phi(u, b-1),

@@ -60,7 +60,7 @@ class _Result(C.Structure):
                [(n, C.c_uint32) for n in ("sieve_launches", "scan_launches")] + \
                [(n, C.c_double) for n in ("ms_total", "ms_tables", "ms_leaves", "ms_sieve",
                                           "ms_k_sieve", "ms_k_scan", "ms_k_easy", "ms_k_s1")] + \
-               [("n_easy_items", C.c_uint64), ("x_hi", C.c_uint64)]
+               [("n_easy_items", C.c_uint64), ("x_hi", C.c_uint64), ("pi_hi", C.c_uint64)]
 
 
 @dataclass
@@ -102,6 +102,7 @@ class Result:
     ms_k_s1: float
     n_easy_items: int
     x_hi: int
+    pi_hi: int
 
 class ServeConfig(C.Structure):
     _fields_ = [("max_inflight", C.c_uint32), ("max_round", C.c_uint32),
@@ -192,14 +193,18 @@ def pi_count_ex(x: int, **cfg) -> Result:
 
 
 def pi_count_wide(x: int, **cfg) -> Result:
-    """pi(x) and its decomposition for 0 <= x < 17 * 2^64 (x may exceed 2^64);
-    the result's x field is then x mod 2^64 and x_hi the high word."""
-    if not 0 <= x < 17 << 64:
-        raise ValueError("x must satisfy 0 <= x < 17 * 2^64")
+    """pi(x) and its decomposition for 0 <= x <= 2^72 (x may exceed 2^64): the
+    result's x and pi fields are full integers (x_hi and pi_hi keep the high
+    words the C ABI returns)."""
+    if not 0 <= x <= 1 << 72:
+        raise ValueError("x must satisfy 0 <= x <= 2^72")
     r = _Result()
     c = _config(**cfg)
     _check(lib().pc_pi_count_wide(x & ((1 << 64) - 1), x >> 64, C.byref(c), C.byref(r)))
-    return _result(r)
+    res = _result(r)
+    res.x = (res.x_hi << 64) | res.x
+    res.pi = (res.pi_hi << 64) | res.pi
+    return res
 
 
 def decompose(x: int, y: int, **cfg) -> Result:

@@ -188,7 +188,7 @@ __global__ void k_batch_out(const pc_final *fin, const uint64_t *pos, uint32_t n
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q < nq)
-        out[pos[q]] = (*err == 0 && fin[q].ok) ? fin[q].pi : ~0ull;
+        out[pos[q]] = (*err == 0 && fin[q].ok == 1) ? fin[q].pi : ~0ull;
 }
 
 // Results known on the host, as (position, value) pairs, into out.

@@ -157,7 +157,7 @@ PC_HD uint64_t pc_div_any(uint64_t n, uint32_t d)
     return q;
 }
 
-// Queries above 2^64: x = hi 2^64 + lo with hi <= 16 (x < 17 2^64).
+// Queries above 2^64: x = hi 2^64 + lo (x <= 2^72).
 //
 // floor((hi 2^64 + lo) / d) for 1 <= d < 2^32 and hi < d (so the quotient is
 // below 2^64), by long division in base 2^32; *rem receives the remainder.
@@ -175,13 +175,17 @@ PC_HD uint64_t pc_div_wide32(uint64_t hi, uint64_t lo, uint32_t d, uint32_t *rem
 }
 
 // floor(x / d) for x = hi 2^64 + lo (xd = x rounded to double) when the
-// quotient is below 2^52 and d < 2^62: the fp64 estimate is within 2 of the
-// quotient, so the remainder x - q d, formed modulo 2^64, is a small signed
-// number that steers the correction.
+// quotient is below 2^64 and d < 2^46: the fp64 estimate q0 is within
+// q 2^-51 + 1 < 2^13 of the quotient, so the remainder x - q0 d, formed
+// modulo 2^64, is a signed number below 2^59 in size; one integer division of
+// it brings the estimate within one, and the remainder's sign settles it.
 PC_HD uint64_t pc_div_wide(uint64_t lo, double xd, uint64_t d)
 {
-    uint64_t q = (uint64_t)(xd / (double)d);
+    const double t = xd / (double)d;
+    uint64_t q = t < 0x1p64 ? (uint64_t)t : ~0ull;
     int64_t rem = (int64_t)(lo - q * d);
+    q += rem / (int64_t)d;
+    rem = (int64_t)(lo - q * d);
     while (rem < 0) {
         q--;
         rem += (int64_t)d;
@@ -191,6 +195,42 @@ PC_HD uint64_t pc_div_wide(uint64_t lo, double xd, uint64_t d)
         rem -= (int64_t)d;
     }
     return q;
+}
+
+// floor(x / d) for x = hi 2^64 + lo, 1 <= d < 2^32, any hi: the quotient's
+// high word in *qhi, its low word returned (long division in base 2^32).
+PC_HD uint64_t pc_div_u128_32(uint64_t hi, uint64_t lo, uint32_t d, uint64_t *qhi, uint32_t *rem)
+{
+    *qhi = hi / d;
+    return pc_div_wide32(hi % d, lo, d, rem);
+}
+
+// floor(x / d) for 1 <= d < 2^32 when the quotient is below 2^50, x given as
+// its low word lo and its value xd in fp64 (x may exceed 2^64): the estimate
+// is within one of the quotient and the remainder, formed modulo 2^64, is
+// exact.  For x < 2^64 this is pc_div_small_q.
+PC_HD uint64_t pc_div_small_qd(uint64_t lo, double xd, uint32_t d)
+{
+    uint64_t q = (uint64_t)(xd / (double)d);
+    const int64_t rem = (int64_t)(lo - q * (uint64_t)d);
+    if (rem < 0)
+        q--;
+    else if (rem >= (int64_t)d)
+        q++;
+    return q;
+}
+
+// isqrt(hi 2^64 + lo) for values below 2^126: the fp64 root is within one of
+// the integer root below 2^104, and the loops settle it.
+PC_HD uint64_t pc_isqrt_wide(uint64_t hi, uint64_t lo)
+{
+    const pc_u128 n = ((pc_u128)hi << 64) | lo;
+    uint64_t r = (uint64_t)__builtin_sqrt((double)n);
+    while (r > 0 && (pc_u128)r * r > n)
+        r--;
+    while ((pc_u128)(r + 1) * (r + 1) <= n)
+        r++;
+    return r;
 }
 
 // Integer square and cube roots, exact (used by the host planner).

@@ -124,15 +124,15 @@ struct Tables {
     DevBuf lk_in, lk_out, chk;
     // the first entries of the device pi table, read back for planning the
     // count staircase on the host (pi at isqrt(x / lo): every segment but the
-    // first starts at lo >= 2^16, so below 2^24 for x < 2^64 and below 2^27
-    // for x < 17 2^64)
+    // first starts at lo >= 2^16, so below 2^24 for x < 2^64 and at most 2^28
+    // for x <= 2^72)
     std::vector<uint2> pi_host;
     uint64_t pi_host_max = 0; // pi_host answers n <= pi_host_max
 };
 Tables g_T;
 
 struct QueryBufs {
-    DevBuf Ub, Xb, Xd, e_start, e_count, e_off, e_scount, e_bk, e_boff, e_tmp, e_total, e_clu,
+    DevBuf Ub, Xb, Xd, Xbh, e_start, e_count, e_off, e_scount, e_bk, e_boff, e_tmp, e_total, e_clu,
         part, sums, fin, qdev;
     DevBuf work, hot, bounds, tiles_a, trace;
     DevBuf tiles, cnt, wgt, carry_rows, carry_a, carry_b, status, ticket, part_tile_h,
@@ -195,11 +195,11 @@ void ensure_pi(uint64_t need)
     if (T.pi_limit >= need)
         return;
     // up to 2^32 the table doubles as it grows; above, it is sized to the
-    // request (isqrt x <= 2^34.05 for x < 17 2^64), the primes above 2^32
-    // held as 64-bit values
-    constexpr uint64_t kPiMax = (1ull << 35) - 1, k2_32 = 0xFFFFFFFFull;
+    // request (isqrt x <= 2^36 for x <= 2^72), the primes above 2^32 held as
+    // 64-bit values; the base primes below 2^18 sieve every n < 262147^2
+    constexpr uint64_t kPiMax = (1ull << 36) + (1ull << 20), k2_32 = 0xFFFFFFFFull;
     if (need > kPiMax)
-        fail(PC_ERANGE, "pi table beyond 2^35 requested");
+        fail(PC_ERANGE, "pi table beyond 2^36 + 2^20 requested");
     uint64_t lim = std::max<uint64_t>({need, std::min(2 * T.pi_limit, k2_32), 1ull << 22});
     uint64_t nent = lim / 64 + 1;
     uint64_t covered = 64 * nent - 1;
@@ -230,8 +230,9 @@ void ensure_pi(uint64_t need)
         fail(PC_EINTERNAL, "pi(2^32) of the device table is not 203280221");
     T.recip_n = 0; // the primes array was rebuilt
     // the host copy answers the staircase's pi(isqrt(x / lo)): below 2^24 for
-    // x < 2^64, below 2^27 for the queries up to 17 2^64 (tables above 2^32)
-    const uint64_t nh = std::min<uint64_t>(nent, (covered > k2_32 ? 1ull << 27 : 1ull << 24) / 64);
+    // x < 2^64, at most 2^28 for the queries up to 2^72 (tables above 2^32)
+    const uint64_t nh =
+        std::min<uint64_t>(nent, (covered > k2_32 ? (1ull << 28) + 64 : 1ull << 24) / 64 + 1);
     T.pi_host.resize(nh);
     hipck(hipMemcpyAsync(T.pi_host.data(), T.pitab.p, nh * 8, hipMemcpyDeviceToHost, g_stream),
           "D2H");
@@ -402,7 +403,7 @@ void drop_tables()
 void drop_query_bufs()
 {
     QueryBufs &B = g_Q;
-    DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.Xd, &B.e_start, &B.e_count, &B.e_off, &B.e_scount, &B.e_bk, &B.e_boff, &B.e_tmp, &B.e_total, &B.e_clu, &B.part,
+    DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.Xd, &B.Xbh, &B.e_start, &B.e_count, &B.e_off, &B.e_scount, &B.e_bk, &B.e_boff, &B.e_tmp, &B.e_total, &B.e_clu, &B.part,
                      &B.sums, &B.fin, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
                      &B.carry_a, &B.carry_b, &B.status, &B.ticket, &B.part_tile_h,
                      &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err, &B.qdev,
@@ -672,15 +673,18 @@ void plan_tiles(const pc_tables &T, const pc_query &Q, const Knobs &K, uint32_t 
 }
 
 // Full decomposition for one (x, y); x >= 8, icbrt(x) <= y <= isqrt(x),
-// x < 17 2^64 (above 2^64 every X_b of a prime p_b > p_c = 13 fits 64 bits).
+// x <= 2^72 (above 2^64 X_b, S1's quotients and pi(x) itself may take 128
+// bits; the sieve's and the leaves' quotients all stay below 2^64).
+constexpr pc_u128 kWideMax = (pc_u128)1 << 72;
+
 void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
 {
     auto t0 = clk::now();
     init_stream();
     QueryBufs &B = g_Q;
     const uint64_t x_hi = (uint64_t)(x >> 64);
-    if (x_hi > 16)
-        fail(PC_ERANGE, "x beyond 17 * 2^64");
+    if (x > kWideMax)
+        fail(PC_ERANGE, "x beyond 2^72");
     const uint64_t sx = isqrt128(x);
     if ((x / y) >> 64)
         fail(PC_ERANGE, "x / y beyond 2^64");
@@ -737,8 +741,15 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
 
     // --- per-query tables and the leaves outside the sieve ---
     ensure(B.Xb, (a + 2) * 8, "X_b");
+    ensure(B.Xd, (a + 2) * 8, "X_b");
     Q.Xb = Q.Xb_w = ptr<uint64_t>(B.Xb);
-    hipck(pc_launch_xb(T, (uint64_t)x, x_hi, (uint32_t)a, ptr<uint64_t>(B.Xb), g_stream), "X_b");
+    Q.Xd = ptr<double>(B.Xd);
+    Q.Xbh = nullptr;
+    if (x_hi) {
+        ensure(B.Xbh, (a + 2) * 4, "X_b");
+        Q.Xbh = ptr<uint32_t>(B.Xbh);
+    }
+    hipck(pc_launch_xb(T, Q, g_stream), "X_b");
 
     ensure(B.sums, sizeof(pc_sums), "sums");
     ensure(B.fin, sizeof(pc_final), "final");
@@ -763,7 +774,7 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
     const uint64_t nband = a / PC_EZ_BAND + 1;
     ensure(B.e_bk, 2 * nband * 4, "easy bands");
     ensure(B.e_boff, 2 * nband * 8, "easy bands");
-    ensure(B.Xd, (a + 2) * 8, "easy bands");
+
     ensure(B.e_clu, (a + 2) * 16, "easy clusters");
     ensure(B.e_tmp, ((a + 2) / 4096 + 2) * 8, "scan");
     ensure(B.Ub, (a + 2) * 16, "hard-leaf u ranges");
@@ -774,7 +785,6 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
     Q.e_scount = ptr<uint64_t>(B.e_scount);
     Q.e_bk = ptr<uint32_t>(B.e_bk);
     Q.e_boff = ptr<uint64_t>(B.e_boff);
-    Q.Xd = ptr<double>(B.Xd);
     Q.e_total = ptr<uint64_t>(B.e_total);
     Q.e_clu = ptr<uint4>(B.e_clu);
     hipck(pc_launch_leaf_setup(T, Q, ptr<pc_s128>(B.part), ls_blocks, g_stream), "leaf setup");
@@ -1072,7 +1082,7 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
         fail(PC_EINTERNAL, "a sieving column before the cut lay outside its row's stored range");
     if (err)
         fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment");
-    if (!fin.ok)
+    if (fin.ok == 0 || (fin.ok == 2 && !x_hi))
         fail(PC_EINTERNAL, "pi(x) outside [0, 2^64)");
 
     if (res) {
@@ -1085,6 +1095,7 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
         res->z = z;
         res->bmax = bmax;
         res->pi = fin.pi;
+        res->pi_hi = fin.pi_hi;
         res->s1 = to_abi(fin.s1);
         res->s2_trivial = to_abi(fin.s2t);
         res->s2_easy = to_abi(fin.s2e);
@@ -1417,6 +1428,7 @@ void round_queries(const std::vector<BatchQuery> &R, const RoundPlan &P, char *b
         Q.e_scount = reinterpret_cast<uint64_t *>(carve(na * 8));
         Q.e_clu = reinterpret_cast<uint4 *>(carve(na * 16));
         Q.Xd = reinterpret_cast<double *>(carve(na * 8));
+        Q.Xbh = nullptr; // batch queries lie below 2^64
         const size_t nband = b.a / PC_EZ_BAND + 1;
         Q.e_bk = reinterpret_cast<uint32_t *>(carve(2 * nband * 4));
         Q.e_boff = reinterpret_cast<uint64_t *>(carve(2 * nband * 8));
@@ -1550,7 +1562,7 @@ void collect_round(BatchSlot &sl, uint64_t *out)
     if (*sl.h_err)
         fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment (batch)");
     for (size_t i = 0; i < sl.R.size(); i++) {
-        if (!sl.h_fin[i].ok)
+        if (sl.h_fin[i].ok != 1)
             fail(PC_EINTERNAL, "pi(x) outside [0, 2^64), or the round's results were not read "
                                "back in order (batch)");
         out[sl.R[i].idx] = sl.h_fin[i].pi;
@@ -2180,8 +2192,8 @@ pc_status pc_pi_count_wide(uint64_t x_lo, uint64_t x_hi, const pc_config *cfg, p
     pc_result r;
     uint64_t v = 0;
     pc_status st = guarded([&] {
-        if (x_hi > 16)
-            fail(PC_ERANGE, "x must be below 17 * 2^64");
+        if (x_hi > 256 || (x_hi == 256 && x_lo != 0))
+            fail(PC_ERANGE, "x must be at most 2^72");
         Knobs K = knobs_from(cfg);
         if (cfg && (cfg->flags & PC_FLAG_REBUILD_TABLES))
             drop_tables();

@@ -41,7 +41,7 @@ struct pc_sums;
 // Per-query scalars.
 struct pc_query {
     uint64_t x, y, z;       // x: its low 64 bits when x_hi != 0
-    uint64_t x_hi;          // x = x_hi 2^64 + x, x_hi <= 16
+    uint64_t x_hi;          // x = x_hi 2^64 + x, x <= 2^72
     double xd;              // x rounded to double
     uint64_t y1, recip_y1;  // y + 1 and its reciprocal
     uint64_t sqrtx;         // isqrt(x)
@@ -49,7 +49,8 @@ struct pc_query {
     uint64_t Qc, recip_Qc;
     uint32_t c, a, bmax, nb, ncol;
     uint32_t kx;            // pi(isqrt(x))
-    const uint64_t *Xb;     // Xb[b] = floor(x / p_b), 1-based, b <= a
+    const uint64_t *Xb;     // Xb[b] = floor(x / p_b) modulo 2^64, 1-based, b <= a
+    uint32_t *Xbh;          // its high word (above 2^64; null: every X_b < 2^64)
     uint64_t sieve_end;     // the sieve covers [0, sieve_end): segments * 2S integers
     uint64_t nseg;          // segments (rows of cnt and wgt when the query has one window)
     const ulonglong2 *Ub;   // Ub[b].x <= u of every hard leaf of b <= Ub[b].y, and Ub[b].y is
@@ -79,7 +80,7 @@ struct pc_query {
     // taken against every b of the band.  e_bk[g] / e_boff[g] (g < nband):
     // first k and exclusive prefix of the units of the singles; at nband + g
     // the same for the groups; e_total[1] / e_total[2] the units.  Xd[b] =
-    // (double)Xb[b].
+    // X_b rounded to double.
     uint64_t *e_start;
     uint64_t *e_count;
     uint64_t *e_off;
@@ -92,6 +93,41 @@ struct pc_query {
     ulonglong2 *Ub_w;       // writable view of Ub (set-up kernels)
     uint64_t *Xb_w;         // writable view of Xb (set-up kernels)
 };
+
+// X_b of a query: its low word, high word and value in fp64 (above 2^64 the
+// high word is nonzero for the primes p_b below x / 2^64).
+struct pc_xv {
+    uint64_t lo;
+    uint32_t hi;
+    double d;
+};
+
+__device__ __forceinline__ pc_xv pc_xb(const pc_query &Q, uint32_t b)
+{
+    pc_xv v;
+    v.lo = Q.Xb[b];
+    v.hi = Q.Xbh ? Q.Xbh[b] : 0u;
+    v.d = Q.x_hi ? Q.Xd[b] : (double)v.lo;
+    return v;
+}
+
+// floor(X / p) for a prime p > X's high word (X / p < 2^64), rp = pc_recip(p)
+__device__ __forceinline__ uint64_t pc_xv_div(pc_xv X, uint32_t p, uint64_t rp)
+{
+    return X.hi ? pc_div_wide32(X.hi, X.lo, p, nullptr) : pc_div(X.lo, p, rp);
+}
+
+// floor(X / d) for d < 2^46 when the quotient is below 2^64, rd = pc_recip(d)
+__device__ __forceinline__ uint64_t pc_xv_div64(pc_xv X, uint64_t d, uint64_t rd)
+{
+    return X.hi ? pc_div_wide(X.lo, X.d, d) : pc_div(X.lo, d, rd);
+}
+
+// floor(X / m) for m < 2^32 when the quotient is below 2^50
+__device__ __forceinline__ uint64_t pc_xv_small_q(pc_xv X, uint32_t m)
+{
+    return X.hi ? pc_div_small_qd(X.lo, X.d, m) : pc_div_small_q(X.lo, m);
+}
 
 enum { PC_MODE_TALLY = 0, PC_MODE_COUNT = 1, PC_MODE_LEAVES = 2 };
 
@@ -135,8 +171,7 @@ hipError_t pc_launch_wheel(uint32_t c, const uint32_t *primes, uint32_t *pattern
                            hipStream_t s);
 hipError_t pc_launch_lookup(const uint2 *pitab, const uint64_t *in, uint32_t n, uint64_t *out,
                             hipStream_t s);
-hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint64_t x_hi, uint32_t a, uint64_t *Xb,
-                        hipStream_t s);
+hipError_t pc_launch_xb(const pc_tables &T, const pc_query &Q, hipStream_t s);
 
 // Leaves outside the sieve: S1, trivial and easy special leaves.  The set-up
 // and easy kernels use the per-query arrays named in pc_query.
@@ -203,8 +238,9 @@ struct pc_sums {
 };
 struct pc_final {
     pc_s128 s1, s2t, s2e, s2h, p2, phi;
-    uint64_t pi;
-    uint64_t ok;
+    uint64_t pi, pi_hi;     // pi(x) = pi_hi 2^64 + pi
+    uint64_t ok;            // 1: pi in [0, 2^64); 2: pi in [2^64, 2^128); 0: negative
+    uint64_t pad;
 };
 // Batches: the queries' set-up (X_b, S1, per-b leaf set-up, easy offsets),
 // their easy leaves, and their carries and combination, each over all queries

@@ -42,16 +42,16 @@ __device__ __forceinline__ void pc_leaf_mrange(const pc_query &Q, uint32_t b, ui
                                                uint64_t rhi, uint64_t rlo, uint64_t *m1o,
                                                uint64_t *m2o)
 {
-    const uint64_t X = Q.Xb[b];
-    const uint64_t mA = pc_div(X, hi, rhi) + 1;            // u < hi   <=> m > X/hi
-    const uint64_t mB = lo ? pc_div(X, lo, rlo) : X;        // u >= lo  <=> m <= X/lo
+    const pc_xv X = pc_xb(Q, b);
+    const uint64_t mA = pc_xv_div64(X, hi, rhi) + 1;                // u < hi   <=> m > X/hi
+    const uint64_t mB = lo ? pc_xv_div64(X, lo, rlo) : Q.y;          // u >= lo  <=> m <= X/lo
     uint64_t m1 = pc_div(Q.y, p, rp) + 1;
     if (m1 < mA)
         m1 = mA;
     if (m1 < p + 1)
         m1 = p + 1;
-    const uint64_t h1 = pc_div(pc_div(X, p, rp), p, rp);
-    const uint64_t h2 = pc_div(X, Q.y1, Q.recip_y1);
+    const uint64_t h1 = pc_div(pc_xv_div(X, (uint32_t)p, rp), p, rp);
+    const uint64_t h2 = pc_xv_div64(X, Q.y1, Q.recip_y1);
     uint64_t m2 = h1 > h2 ? h1 : h2;
     if (m2 > Q.y)
         m2 = Q.y;

@@ -15,20 +15,25 @@
 
 #define PC_MODEBIT (1ull << 63)
 
-// X_b = floor(x / p_b) for 1 <= b <= a (X_0 = x).  Above 2^64 (x_hi != 0)
-// the quotients of p_b <= x_hi, all with b <= c and never read, are stored as
-// 2^64 - 1.
+// X_b = floor(x / p_b) for 1 <= b <= a (X_0 = x): its low word, its high
+// word (above 2^64, when Xbh is not null) and its value in fp64.
 __device__ __forceinline__ void pc_xb_item(const pc_tables &T, const pc_query &Q, uint32_t b)
 {
+    if (b > Q.a)
+        return;
+    uint64_t lo, hi = 0;
     if (b == 0) {
-        Q.Xb_w[0] = Q.x_hi ? ~0ull : Q.x;
-    } else if (b <= Q.a) {
-        const uint32_t p = T.primes[b];
-        if (!Q.x_hi)
-            Q.Xb_w[b] = pc_div(Q.x, p, T.recip[b]);
-        else
-            Q.Xb_w[b] = Q.x_hi < p ? pc_div_wide32(Q.x_hi, Q.x, p, nullptr) : ~0ull;
+        lo = Q.x;
+        hi = Q.x_hi;
+    } else if (!Q.x_hi) {
+        lo = pc_div(Q.x, T.primes[b], T.recip[b]);
+    } else {
+        lo = pc_div_u128_32(Q.x_hi, Q.x, T.primes[b], &hi, nullptr);
     }
+    Q.Xb_w[b] = lo;
+    if (Q.Xbh)
+        Q.Xbh[b] = (uint32_t)hi;
+    Q.Xd[b] = hi ? (double)(((pc_u128)hi << 64) | lo) : (double)lo;
 }
 
 // The S1 term of n (pcc = p_c): adds mu(n) phi(x/n, c) to *acc when n <= y is
@@ -45,14 +50,12 @@ __device__ __forceinline__ bool pc_s1_item(const pc_tables &T, const pc_query &Q
         const uint64_t u = pc_div_any(Q.x, (uint32_t)n);
         const uint64_t qq = pc_div(u, Q.Qc, Q.recip_Qc);
         phi = (pc_s128)(qq * T.phiQ + T.phitab[u - qq * Q.Qc]);
-    } else if (n == 1) { // u = x above 2^64: x = qq Q_c + r with qq < 2^64
+    } else { // above 2^64: u = x / n in 128 bits, u = qq Q_c + r with qq < 2^64
+        uint64_t uh;
+        const uint64_t ul = pc_div_u128_32(Q.x_hi, Q.x, (uint32_t)n, &uh, nullptr);
         uint32_t r;
-        const uint64_t qq = pc_div_wide32(Q.x_hi, Q.x, (uint32_t)Q.Qc, &r);
+        const uint64_t qq = pc_div_wide32(uh, ul, (uint32_t)Q.Qc, &r); // uh < Q_c: x <= 2^72
         phi = (pc_s128)qq * T.phiQ + T.phitab[r];
-    } else { // n >= 17 > x_hi (lpf(n) > p_c = 13): u = x / n < 2^64
-        const uint64_t u = pc_div_wide32(Q.x_hi, Q.x, (uint32_t)n, nullptr);
-        const uint64_t qq = pc_div(u, Q.Qc, Q.recip_Qc);
-        phi = (pc_s128)(qq * T.phiQ + T.phitab[u - qq * Q.Qc]);
     }
     *acc += v > 0 ? phi : -phi;
     return true;
@@ -77,15 +80,16 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
     *triv = 0;
     *cross = 0;
     if (b > Q.c && b <= Q.c + Q.nb) { // a sieving prime
-        const uint64_t p = T.primes[b], rp = T.recip[b], X = Q.Xb[b];
+        const uint64_t p = T.primes[b], rp = T.recip[b];
+        const pc_xv X = pc_xb(Q, b);
         // odd multiples k p_b, k odd, below the sieve end
         *cross = (pc_div(Q.sieve_end - 1, p, rp) + 1) / 2;
         // u range of the hard leaves of b: y/p < m <= y, m > p, m <= max(x/p^3, x/(p(y+1)))
         uint64_t m1 = pc_div(Q.y, p, rp) + 1;
         if (m1 < p + 1)
             m1 = p + 1;
-        const uint64_t h1 = pc_div(pc_div(X, p, rp), p, rp);
-        const uint64_t h2 = pc_div(X, Q.y1, Q.recip_y1);
+        const uint64_t h1 = pc_div(pc_xv_div(X, (uint32_t)p, rp), p, rp);
+        const uint64_t h2 = pc_xv_div64(X, Q.y1, Q.recip_y1);
         uint64_t m2 = h1 > h2 ? h1 : h2;
         if (m2 > Q.y)
             m2 = Q.y;
@@ -93,8 +97,8 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
         ub.x = 1;
         ub.y = 0;
         if (m1 <= m2) {
-            ub.x = pc_div_small_q(X, (uint32_t)m2);
-            ub.y = pc_div_small_q(X, (uint32_t)m1);
+            ub.x = pc_xv_small_q(X, (uint32_t)m2);
+            ub.y = pc_xv_small_q(X, (uint32_t)m1);
         }
         Q.Ub_w[b] = ub;
     }
@@ -103,19 +107,19 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
         uint4 clu = make_uint4(0, 0, 0, 0);
         if (b > Q.c && b < Q.a) {
             const uint64_t p = T.primes[b], rp = T.recip[b];
-            const uint64_t X = Q.Xb[b];
-            const uint64_t tp = pc_div(X, p, rp); // floor(x / p^2): u >= p  <=>  m <= tp
+            const pc_xv X = pc_xb(Q, b);
+            const uint64_t tp = pc_xv_div(X, (uint32_t)p, rp); // floor(x / p^2): u >= p <=> m <= tp
             uint64_t m1 = pc_div(Q.y, p, rp) + 1;
             if (m1 < p + 1)
                 m1 = p + 1;
             const uint64_t h1 = pc_div(tp, p, rp);
-            const uint64_t h2 = pc_div(X, Q.y1, Q.recip_y1);
+            const uint64_t h2 = pc_xv_div64(X, Q.y1, Q.recip_y1);
             const uint64_t H = h1 > h2 ? h1 : h2;
             uint64_t e1 = H + 1 > m1 ? H + 1 : m1;
             uint64_t e2 = tp < Q.y ? tp : Q.y;
             if (p > Q.sqrty) {
                 if (e1 <= e2) {
-                    const uint64_t sx = pc_isqrt(X);
+                    const uint64_t sx = X.hi ? pc_isqrt_wide(X.hi, X.lo) : pc_isqrt(X.lo);
                     uint64_t s = sx + sx / 2; // single-m items: m <= s
                     if (s < e1 - 1)
                         s = e1 - 1;
@@ -125,8 +129,8 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
                     const uint64_t ns = pc_pi_lookup(T.pitab, s) + 1 - k1;
                     uint64_t klo = 0, nk = 0;
                     if (s < e2) { // K = pi(u) for u in [X / e2, X / (s + 1)]
-                        klo = pc_pi_lookup(T.pitab, pc_div_any(X, (uint32_t)e2));
-                        nk = pc_pi_lookup(T.pitab, pc_div_any(X, (uint32_t)(s + 1))) + 1 - klo;
+                        klo = pc_pi_lookup(T.pitab, pc_xv_small_q(X, (uint32_t)e2));
+                        nk = pc_pi_lookup(T.pitab, pc_xv_small_q(X, (uint32_t)(s + 1))) + 1 - klo;
                     }
                     st = k1;
                     sn = ns;
@@ -234,7 +238,7 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
         uint32_t b = *s_b0;
         const uint32_t n = (uint32_t)(i0 + TILE < E ? TILE : E - i0); // items of the tile
         uint64_t off = e_off[b], cn = e_count[b] & ~PC_MODEBIT, st = e_start[b], X = Q.Xb[b];
-        double Xd = (double)X;
+        double Xd = Q.Xd[b];
         uint32_t p = T.primes[b];
         const uint64_t iend = i0 + n;
         for (uint64_t i = i0 + threadIdx.x; i < iend; i += NT) {
@@ -244,7 +248,7 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
                 cn = e_count[b] & ~PC_MODEBIT;
                 st = e_start[b];
                 X = Q.Xb[b];
-                Xd = (double)X;
+                Xd = Q.Xd[b];
                 p = T.primes[b];
             }
             const uint32_t m = (uint32_t)(st + (i - off));
@@ -263,7 +267,7 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
 
 // The bands of the singles and groups (layout in pc_query): for band g, the
 // first and one past the last prime index of each kind over the band's b, and
-// its units; also Xd[b] for the band's b, and the parts of S2e and of the
+// its units; and the parts of S2e and of the
 // leaf count that the bands' sums leave out: -(b - 2) for each single
 // (pc_easy_bands adds pi(u) alone), the two end terms of each b's groups
 // (pc_easy_group_v), and every single and group leaf.
@@ -280,8 +284,7 @@ __device__ __forceinline__ void pc_easy_band_item(const pc_tables &T, const pc_q
     unsigned long long terms = 0;
     for (uint32_t b = b0; b < b1; b++) {
         const uint64_t X = Q.Xb[b];
-        const double Xd = (double)X;
-        Q.Xd[b] = Xd;
+        const double Xd = Q.Xd[b];
         const uint32_t ns = (uint32_t)Q.e_scount[b];
         if (ns) {
             const uint32_t k1 = (uint32_t)Q.e_start[b];
@@ -403,5 +406,6 @@ __device__ __forceinline__ void pc_combine_one(const pc_sums &S, const pc_query 
     out->p2 = p2;
     out->phi = phi;
     out->pi = (uint64_t)pi;
-    out->ok = (pi >= 0 && (pi >> 64) == 0) ? 1 : 0;
+    out->pi_hi = (uint64_t)(pi >> 64);
+    out->ok = pi < 0 ? 0 : (pi >> 64) == 0 ? 1 : 2;
 }

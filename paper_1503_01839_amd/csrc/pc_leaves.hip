@@ -33,6 +33,18 @@ hipError_t pc_launch_s1(const pc_tables &T, const pc_query &Q, pc_s128 *part, ui
     return hipGetLastError();
 }
 
+// X_b for b <= a (pc_xb_item).
+__global__ __launch_bounds__(LV_T) void k_xb(pc_tables T, pc_query Q)
+{
+    pc_xb_item(T, Q, blockIdx.x * LV_T + threadIdx.x);
+}
+
+hipError_t pc_launch_xb(const pc_tables &T, const pc_query &Q, hipStream_t s)
+{
+    k_xb<<<Q.a / LV_T + 1, LV_T, 0, s>>>(T, Q);
+    return hipGetLastError();
+}
+
 // Per-b set-up of the special leaves outside the sieve (pc_leaf_setup_item).
 __global__ __launch_bounds__(LV_T) void k_leaf_setup(pc_tables T, pc_query Q, pc_s128 *part_t)
 {

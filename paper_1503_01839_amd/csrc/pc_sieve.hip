@@ -153,6 +153,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         Q.row_off ? pc_uniform((uint32_t)(Q.row_off[row + 1] - Q.row_off[row])) : Q.nb;
     const uint32_t qc = pc_uniform(Q.c);
     const uint64_t *const Xb1 = pc_uniform_ptr(Q.Xb) + qc + 1; // X_b of column j of chunk cb: Xb1[cb + j]
+    // above 2^64 the leaf quotients take X_b's value in fp64 beside its low word
+    const bool wide = Q.x_hi != 0;
+    const double *const Xd1 = Q.Xd + qc + 1;
     const pc_tables &TB = A.T;
     const uint64_t rhi = pc_recip(hi);
     const uint64_t rlo = lo ? pc_recip(lo) : 0;
@@ -279,9 +282,10 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         *w = 1;
         return true;
     };
-    // q = bits of the segment below u = floor(X_b / m), u in [lo, hi)
-    auto leaf_q = [&](uint64_t X, uint64_t m, bool *ok) -> uint32_t {
-        const uint64_t u = pc_div_small_q(X, m);
+    // q = bits of the segment below u = floor(X_b / m), u in [lo, hi); X is
+    // X_b modulo 2^64 and Xd its value in fp64 (read only above 2^64)
+    auto leaf_q = [&](uint64_t X, double Xd, uint64_t m, bool *ok) -> uint32_t {
+        const uint64_t u = wide ? pc_div_small_qd(X, Xd, (uint32_t)m) : pc_div_small_q(X, m);
         *ok = u >= lo && u < hi;
         if (!*ok) // cannot happen if the m range is right
             atomicOr(A.err, 2);
@@ -659,7 +663,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                     uint32_t e = 0;
                     if (leaf_filter(aj, s - oa, &m, &w)) {
                         bool ok;
-                        const uint32_t q = leaf_q(Xb1[cb + aj], m, &ok);
+                        const uint32_t q =
+                            leaf_q(Xb1[cb + aj], wide ? Xd1[cb + aj] : 0.0, m, &ok);
                         if (ok) {
                             const uint32_t r = q >> RSL;
                             e = (a << 22) | (q << 2) | (w < 0 ? 2u : 0u) | 1u;
@@ -736,11 +741,12 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             build_pre();     // (its barriers also end settle's reads of gbuf)
             const uint32_t lc = c_lc[j], n = lc & ~PC_CAND, ls = c_ls[j];
             const uint64_t X = pc_uniform64(Xb1[cb + j]);
+            const double Xd = wide ? Xd1[cb + j] : 0.0;
             int32_t wsum = 0;
             int64_t lsum = 0;
             auto one = [&](uint64_t m, int32_t w) {
                 bool ok;
-                const uint32_t q = leaf_q(X, m, &ok);
+                const uint32_t q = leaf_q(X, Xd, m, &ok);
                 if (ok) {
                     lsum += (int64_t)w * (int64_t)count_pre(q);
                     wsum += w;

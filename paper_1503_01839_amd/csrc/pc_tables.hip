@@ -235,9 +235,9 @@ hipError_t pc_launch_pitab(uint64_t nent, const uint32_t *base, uint32_t nbase, 
                            uint32_t *scan_tmp, hipStream_t s)
 {
     (void)bits;
-    // base primes reach 2^18, so the table reaches 2^36; prefix counts are
-    // 32-bit (pi(2^36) < 2^32)
-    if (nent > (1ull << 30) || (nent > (1ull << 26) && !primes_hi))
+    // base primes reach 2^18 (every n < 262147^2 sieved), so the table reaches
+    // 2^36 + 2^20; prefix counts are 32-bit (pi(2^37) < 2^32)
+    if (nent > (1ull << 30) + (1ull << 14) || (nent > (1ull << 26) && !primes_hi))
         return hipErrorInvalidValue;
     uint32_t nblk = (uint32_t)((nent + PT_WORDS - 1) / PT_WORDS);
     k_sieve_pitab<<<nblk, PT_T, 0, s>>>(nent, base, nbase, pitab, cnts);
@@ -486,26 +486,3 @@ hipError_t pc_launch_lookup(const uint2 *pitab, const uint64_t *in, uint32_t n, 
     return hipGetLastError();
 }
 
-// X_b = floor(x / p_b), x = x_hi 2^64 + x; above 2^64 the quotients of the
-// primes p_b <= x_hi (b <= c: never read) do not fit and are stored as
-// 2^64 - 1.
-__global__ void k_xb(pc_tables T, uint64_t x, uint64_t x_hi, uint32_t a, uint64_t *Xb)
-{
-    uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b == 0)
-        Xb[0] = x_hi ? ~0ull : x;
-    if (b >= 1 && b <= a) {
-        const uint32_t p = T.primes[b];
-        if (!x_hi)
-            Xb[b] = pc_div(x, p, T.recip[b]);
-        else
-            Xb[b] = x_hi < p ? pc_div_wide32(x_hi, x, p, nullptr) : ~0ull;
-    }
-}
-
-hipError_t pc_launch_xb(const pc_tables &T, uint64_t x, uint64_t x_hi, uint32_t a, uint64_t *Xb,
-                        hipStream_t s)
-{
-    k_xb<<<(a + 256) / 256, 256, 0, s>>>(T, x, x_hi, a, Xb);
-    return hipGetLastError();
-}

@@ -3,8 +3,9 @@
 // varying-divisor quotients pc_quot32, pc_quot31, pc_quot31r (stored
 // reciprocal) and pc_quot_in, the fp64 division quotient pc_div_small_q, the
 // reciprocal division pc_div, and the helpers of x above 2^64: pc_div_wide32
-// (long division of a 128-bit dividend), pc_div_wide and pc_quot_in64 (a
-// 128-bit dividend given as its low word and its value in fp64).  Every result q
+// and pc_div_u128_32 (long division of a 128-bit dividend), pc_div_wide,
+// pc_div_small_qd and pc_quot_in64 (a 128-bit dividend given as its low word
+// and its value in fp64) and pc_isqrt_wide.  Every result q
 // is checked exactly, without any division: either n is built as q d + r
 // with r < d, or q d <= n < (q + 1) d is tested in 128-bit arithmetic.
 // Inputs: pairs drawn from a counter-based generator (splitmix64 of the pair
@@ -138,13 +139,13 @@ __global__ void k_div_check(uint64_t n_pairs, uint64_t seed, unsigned long long 
                 atomicMin(&first[7], (unsigned long long)i);
             }
         }
-        // pc_div_wide: quotient below 2^52, divisor below 2^46, x up to 2^98
+        // pc_div_wide: quotient below 2^64, divisor below 2^46, x up to 2^110
         // given as its low word and its fp64 value
         {
             uint64_t D = r0 >> (18 + ((r1 >> 32) & 63) % 46);
             if (D == 0)
                 D = 1;
-            const uint64_t q = r2 >> (12 + ((r1 >> 56) & 31));
+            const uint64_t q = r2 >> ((r1 >> 56) & 63);
             const uint64_t rr = rm == 0 ? 0 : rm == 1 ? D - 1 : r3 % D;
             const pc_u128 x = (pc_u128)q * D + rr;
             if (pc_div_wide((uint64_t)x, (double)x, D) != q) {
@@ -168,6 +169,37 @@ __global__ void k_div_check(uint64_t n_pairs, uint64_t seed, unsigned long long 
             if (in != want_in || (in && base + off != q)) {
                 atomicAdd(&fails[9], 1ull);
                 atomicMin(&first[9], (unsigned long long)i);
+            }
+        }
+        // pc_div_u128_32: any x below 2^128
+        {
+            const uint64_t hi = r2 >> ((r1 >> 8) & 63), lo = r3;
+            uint64_t qh = 0;
+            uint32_t rem = 0xFFFFFFFFu;
+            const uint64_t ql = pc_div_u128_32(hi, lo, d, &qh, &rem);
+            const pc_u128 x = ((pc_u128)hi << 64) | lo, q = ((pc_u128)qh << 64) | ql;
+            if (rem >= d || q * d + rem != x) {
+                atomicAdd(&fails[10], 1ull);
+                atomicMin(&first[10], (unsigned long long)i);
+            }
+        }
+        // pc_div_small_qd: quotient below 2^50, x up to 2^82 as its low word and fp64 value
+        {
+            const uint64_t q = (r2 >> (14 + ((r1 >> 40) & 31))) & ((1ull << 50) - 1);
+            const pc_u128 x = (pc_u128)q * d + rem(r3);
+            if (pc_div_small_qd((uint64_t)x, (double)x, d) != q) {
+                atomicAdd(&fails[11], 1ull);
+                atomicMin(&first[11], (unsigned long long)i);
+            }
+        }
+        // pc_isqrt_wide: below 2^80 (X_b <= 2^72 in the leaf set-up)
+        {
+            const uint64_t hi = r2 >> (48 + ((r1 >> 16) & 15)), lo = r3;
+            const pc_u128 n = ((pc_u128)hi << 64) | lo;
+            const pc_u128 r = pc_isqrt_wide(hi, lo);
+            if (!(r * r <= n && (r + 1) * (r + 1) > n)) {
+                atomicAdd(&fails[12], 1ull);
+                atomicMin(&first[12], (unsigned long long)i);
             }
         }
     }
@@ -216,14 +248,15 @@ __global__ void k_div_edges(unsigned long long *fails)
 } // namespace
 
 // Runs n_pairs random pairs (seeded) and the edge pairs on the current device;
-// fails_out[0..9] = failures of pc_quot32, pc_quot_in, pc_div_small_q, pc_div,
+// fails_out[0..12] = failures of pc_quot32, pc_quot_in, pc_div_small_q, pc_div,
 // pc_rcp_f64, pc_quot31r, pc_quot31, pc_div_wide32, pc_div_wide,
-// pc_quot_in64; first_out[0..9] = the first failing pair index (or ~0).
+// pc_quot_in64, pc_div_u128_32, pc_div_small_qd, pc_isqrt_wide; first_out the
+// first failing pair index of each (or ~0).
 // Returns 0, or the HIP error code.
 extern "C" int pc_div_check(uint64_t n_pairs, uint64_t seed, uint64_t *fails_out,
                             uint64_t *first_out)
 {
-    constexpr int NH = 10;
+    constexpr int NH = 13;
     unsigned long long *d = nullptr;
     hipError_t e = hipMalloc(&d, 2 * NH * sizeof(unsigned long long));
     if (e != hipSuccess)

@@ -22,7 +22,7 @@ def test_more_than_one_gpu_is_refused():
 def test_bad_serving_options_are_refused():
     r = run("--serve-modes", "fast")
     assert r.returncode != 0 and "--serve-modes" in r.stderr
-    r = run("--x", str(17 * 2**64))
+    r = run("--x", str(2**72 + 1))
     assert r.returncode != 0 and "--x" in r.stderr
 
 

@@ -1,8 +1,9 @@
-"""The quotient helpers of the kernels (pc_device.h: pc_quot32, pc_quot31,
-pc_quot31r, pc_quot_in, pc_div_small_q, pc_div, the fp64 reciprocal
-pc_rcp_f64, and the helpers of x above 2^64: pc_div_wide32, pc_div_wide,
-pc_quot_in64) run on the GPU over 10^8 seeded random pairs shaped to each
-helper's domain plus edge pairs; every quotient is checked exactly against
+"""The quotient helpers of the kernels (pc_device.h) run on the GPU over 10^8
+seeded random pairs shaped to each helper's domain plus edge pairs: pc_quot32,
+pc_quot31, pc_quot31r, pc_quot_in, pc_div_small_q, pc_div, the fp64
+reciprocal pc_rcp_f64, and the helpers of x above 2^64: pc_div_wide32,
+pc_div_u128_32, pc_div_wide, pc_div_small_qd, pc_quot_in64 and
+pc_isqrt_wide.  Every quotient is checked exactly against
 q d <= n < (q + 1) d in 128-bit integer arithmetic
 (tests/device/div_check.hip)."""
 import ctypes as C
@@ -14,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "device", "libdivcheck.so")
 NAMES = ("pc_quot32", "pc_quot_in", "pc_div_small_q", "pc_div", "pc_rcp_f64", "pc_quot31r",
-         "pc_quot31", "pc_div_wide32", "pc_div_wide", "pc_quot_in64")
+         "pc_quot31", "pc_div_wide32", "pc_div_wide", "pc_quot_in64", "pc_div_u128_32",
+         "pc_div_small_qd", "pc_isqrt_wide")
 
 
 @pytest.mark.parametrize("seed", [1503, 1839])

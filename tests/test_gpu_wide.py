@@ -1,16 +1,16 @@
 """pi(x) above 2^64 (pc_pi_count_wide) against Tables 1 and 2 (Section 5).
 
-Up to 17 * 2^64 the method needs no new arithmetic on its hot path: every
-X_b = x / p_b with p_b > 13, every leaf quotient and every x / p of P2 fits 64
-bits; S1's x / 1, the per-segment bounds x / lo of P2 and X_b themselves are
-formed from the two words of x.  The pi table then reaches isqrt(x) > 2^32,
-with the primes above 2^32 held as 64-bit values.
+Up to 2^72 every leaf quotient, every x / p of P2 and every segment bound
+still fits 64 bits; X_b (128-bit below p_b < x / 2^64), S1's x / n, the
+per-segment bounds of P2 and pi(x) itself (from 2^70 on) are formed in 128
+bits.  The pi table then reaches isqrt(x) > 2^32, with the primes above 2^32
+held as 64-bit values.
 """
 import ctypes as C
 
 import pytest
 
-WIDE = [64, 65, 66, 67, 68]
+WIDE = [64, 65, 66, 67, 68, 69, 70, 71, 72]
 
 
 def say(*a):
@@ -23,7 +23,7 @@ def test_last_u64_and_first_wide(pc, paper_pow2):
     say("step: pi(2^64 - 1) and pi(2^64)")
     assert pc.pi_count((1 << 64) - 1) == paper_pow2[64]
     r = pc.pi_count_wide(1 << 64)
-    assert (r.x, r.x_hi, r.pi) == (0, 1, paper_pow2[64])
+    assert (r.x, r.x_hi, r.pi) == (1 << 64, 1, paper_pow2[64])
     assert r.phi == r.s1 + r.s2_trivial + r.s2_easy + r.s2_hard
 
 
@@ -37,9 +37,12 @@ def test_table2_wide(pc, paper_pow2, m):
 
 
 @pytest.mark.gpu
-def test_table1_1e20(pc, paper_pow10):
-    say("step: pi(10^20)")
-    assert pc.pi_count_wide(10**20).pi == paper_pow10[20]
+@pytest.mark.parametrize("n", [20, 21])
+def test_table1_wide(pc, paper_pow10, n):
+    say(f"step: pi(10^{n})")
+    r = pc.pi_count_wide(10**n)
+    assert r.pi == paper_pow10[n]
+    assert r.pi == r.phi + r.a - 1 - r.p2
 
 
 @pytest.mark.gpu
@@ -68,7 +71,7 @@ def test_wide_matches_narrow_below_2_64(pc, paper_pow10):
 @pytest.mark.gpu
 def test_wide_range_refused(pc):
     r = pc._Result()
-    st = pc.lib().pc_pi_count_wide(0, 17, None, C.byref(r))
-    assert st == pc.PC_ERANGE
+    for lo, hi in [(1, 256), (0, 257), ((1 << 64) - 1, (1 << 64) - 1)]:
+        assert pc.lib().pc_pi_count_wide(lo, hi, None, C.byref(r)) == pc.PC_ERANGE
     with pytest.raises(ValueError):
-        pc.pi_count_wide(17 << 64)
+        pc.pi_count_wide((1 << 72) + 1)
