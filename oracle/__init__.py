@@ -64,6 +64,8 @@ def lib():
         L.or_phi.restype = I128
         L.or_phi_direct.argtypes = [u64, u64]
         L.or_phi_direct.restype = u64
+        L.or_phi_column.argtypes = [u64, u64, C.c_void_p]
+        L.or_phi_column.restype = C.c_int
         L.or_p2.argtypes = [u64, u64]
         L.or_p2.restype = I128
         L.or_p2_brute.argtypes = [u64, u64]
@@ -124,6 +126,15 @@ def phi(u: int, b: int, c: int = 6) -> int:
 def phi_direct(u: int, b: int) -> int:
     """phi(u, b) by testing every n <= u against the first b primes."""
     return lib().or_phi_direct(u, b)
+
+
+def phi_column(m: int, b_hi: int):
+    """phi(m, b) for 0 <= b <= b_hi (numpy uint64), counted from the definition."""
+    import numpy as np
+    out = np.zeros(b_hi + 1, dtype=np.uint64)
+    if lib().or_phi_column(m, b_hi, out.ctypes.data) != 0:
+        raise MemoryError(f"or_phi_column({m})")
+    return out
 
 
 def p2(x: int, y: int) -> int:

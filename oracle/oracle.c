@@ -356,6 +356,44 @@ uint64_t or_phi_direct(uint64_t u, uint64_t b)
     return cnt;
 }
 
+/* phi(m, b) for every 0 <= b <= b_hi at one m, straight from the definition
+ * (§3): start from the integers 1..m and, for b = 1, 2, ..., remove the ones
+ * that p_b divides and that are still present; out[b] is the number left.
+ * This is the value a sieve started at m = m_min needs in every column
+ * (§4, the seeding of phi(m_min, b)).  One byte per integer up to m.
+ * Returns 0, or -1 if memory runs out. */
+int or_phi_column(uint64_t m, uint64_t b_hi, uint64_t *out)
+{
+    uint64_t np = 0, lim = 64;
+    uint32_t *pr;
+    for (;;) {
+        pr = small_primes(lim, &np);
+        if (np >= b_hi)
+            break;
+        free(pr);
+        lim *= 2;
+    }
+    unsigned char *gone = calloc(m + 1, 1);
+    if (!gone) {
+        free(pr);
+        return -1;
+    }
+    uint64_t left = m;
+    out[0] = m;
+    for (uint64_t b = 1; b <= b_hi; b++) {
+        const uint64_t p = pr[b - 1];
+        for (uint64_t n = p; n <= m; n += p)
+            if (!gone[n]) {
+                gone[n] = 1;
+                left--;
+            }
+        out[b] = left;
+    }
+    free(gone);
+    free(pr);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* S1: ordinary leaves, enumerated with the nested loops of §2.2.            */
 /* ------------------------------------------------------------------------ */

@@ -149,6 +149,44 @@ def test_phi_closed_forms():
                 assert O.phi(u, b) == O.pi_brute(u) - b + 1
 
 
+def test_phi_column_pins():
+    # phi(m, b) for every b at one m (the seed of a sieve started at m, §4)
+    P = py_primes(4000)
+    rng = random.Random(41)
+    for _ in range(40):  # gcd counts, written here
+        m = rng.randrange(0, 2500)
+        col = O.phi_column(m, 30)
+        for b in range(31):
+            assert int(col[b]) == phi_gcd(m, b, P), (m, b)
+    for m in (1, 2, 3, 30030, 10**6 + 7, 3 * 10**6 + 1):
+        n_pi = sum(1 for p in P if p <= m) if m <= P[-1] else None
+        col = O.phi_column(m, 500)
+        assert int(col[0]) == m and int(col[1]) == (m + 1) // 2
+        if m >= 30030:
+            assert int(O.phi_column(m + 30030, 6)[6]) == int(col[6]) + 5760
+        if n_pi is not None:  # below p_{b+1}^2 and from pi(m) on: closed forms
+            r = math.isqrt(m)
+            for b in range(1, 501):
+                if P[b - 1] <= r:
+                    continue
+                assert int(col[b]) == max(n_pi - b + 1, 1), (m, b)
+    # the recurrence eq. (4.1) of the oracle, sampled at a larger m
+    m = 12_345_679
+    col = O.phi_column(m, 800)
+    for b in (0, 6, 7, 8, 30, 100, 301, 446, 447, 800):
+        assert int(col[b]) == O.phi(m, b), b
+    # Legendre at m: pi(m) - b + 1 for pi(sqrt m) <= b, pi(m) from a plain sieve
+    sv = bytearray([1]) * (m + 1)
+    sv[0] = sv[1] = 0
+    for q in range(2, math.isqrt(m) + 1):
+        if sv[q]:
+            sv[q * q::q] = bytearray(len(range(q * q, m + 1, q)))
+    pm = sum(sv)
+    kr = sum(1 for p in P if p * p <= m)
+    for b in (kr, kr + 1, 600, 800):
+        assert int(col[b]) == pm - b + 1, b
+
+
 def test_phi_large_vs_meissel_and_table(paper_pow10):
     # phi(x, pi(icbrt x)) + a - 1 - P2 reproduces Table 1 for n <= 12
     for n in range(3, 13):
