@@ -73,6 +73,9 @@ typedef struct {
 #define PC_FLAG_NO_SMALL_SEGMENTS 8u /* no one-wavefront segments even if small_span is set        */
 #define PC_FLAG_NO_GRAPH 16u         /* batches: launch each phase directly, not as a HIP graph     */
 #define PC_FLAG_BATCH_SEQUENTIAL 32u /* batches: one query after another (the plain per-query path) */
+#define PC_FLAG_SEEDED 64u           /* windows of segments seeded on their own with phi(m_min, b)
+                                        (Section 4) instead of carried from the window before;
+                                        they then run last to first                               */
 
 /* Everything one pi(x) evaluation produced, for tests and measurement. */
 typedef struct {
@@ -266,6 +269,19 @@ pc_status pc_serve(const uint64_t *xs, const double *arrival_s, size_t n,
 #define PC_TABLE_PI 2
 #define PC_TABLE_MULPF 3
 pc_status pc_read_table(int which, uint64_t lo, uint64_t n, void *out);
+
+/* The seeds of a sieve started at m (Section 4, the values phi(m_min, b) that
+ * let a block of the sieve run without the blocks before it): out[b - c] =
+ * phi(m, b) for c <= b <= b_hi, phi(m, b) = #{1 <= n <= m : no p_i, i <= b,
+ * divides n} (Section 3).  Computed on the device from the wheel's phi(m, c)
+ * by the recurrence eq. (4.1), each term closed where Section 4's rules close
+ * it (a single survivor past pi(sqrt m); Legendre's pi(u) - b + 2 from the pi
+ * table) and otherwise expanded by eq. (4.1) again, depth first.  This is
+ * what PC_FLAG_SEEDED runs for every window of segments but the first.
+ * c: the wheel size, 1 <= c <= pc_wheel_c(), c <= b_hi; m <= 2^48 and
+ * b_hi < 2^27 (else PC_ERANGE); out: b_hi - c + 1 host words (null ->
+ * PC_EINVAL).  Grows the shared tables as needed (the pi table to m^(2/3)). */
+pc_status pc_phi_seed(uint64_t m, uint32_t c, uint32_t b_hi, uint64_t *out);
 
 /* Wheel size c used by the library (c = min(pc_wheel_c(), a)). */
 int pc_wheel_c(void);

@@ -21,13 +21,14 @@ FLAG_REBUILD_TABLES = 4
 FLAG_NO_SMALL_SEGMENTS = 8
 FLAG_NO_GRAPH = 16
 FLAG_BATCH_SEQUENTIAL = 32
+FLAG_SEEDED = 64
 TABLE_PRIMES, TABLE_PI, TABLE_MULPF = 1, 2, 3
 
 EXPORTS = ["pc_pi_count", "pc_pi_count_ex", "pc_pi_count_wide", "pc_s2_hard", "pc_decompose",
            "pc_p2",
            "pc_pi_count_batch", "pc_pi_count_batch_ex", "pc_workspace_bytes",
            "pc_pi_count_batch_async", "pc_pi_count_batch_noalloc", "pc_serve", "pc_read_table",
-           "pc_wheel_c",
+           "pc_phi_seed", "pc_wheel_c",
            "pc_status_str", "pc_last_error", "pc_shutdown"]
 
 
@@ -149,6 +150,8 @@ def lib():
             getattr(L, f).restype = C.c_int
         L.pc_read_table.argtypes = [C.c_int, u64, u64, C.c_void_p]
         L.pc_read_table.restype = C.c_int
+        L.pc_phi_seed.argtypes = [u64, C.c_uint32, C.c_uint32, C.c_void_p]
+        L.pc_phi_seed.restype = C.c_int
         L.pc_wheel_c.restype = C.c_int
         L.pc_status_str.argtypes = [C.c_int]
         L.pc_status_str.restype = C.c_char_p
@@ -314,6 +317,15 @@ def read_table(which: int, lo: int, n: int):
     out = np.zeros(max(n, 1), dtype=dt)
     _check(lib().pc_read_table(which, lo, n, out.ctypes.data))
     return out[:n]
+
+
+def phi_seed(m: int, b_hi: int, c: int = 6):
+    """phi(m, b) for c <= b <= b_hi (numpy uint64, entry b - c), computed on the
+    device as the seeds of a sieve started at m (Section 4)."""
+    import numpy as np
+    out = np.zeros(b_hi - c + 1 if b_hi >= c else 1, dtype=np.uint64)
+    _check(lib().pc_phi_seed(m, c, b_hi, out.ctypes.data))
+    return out
 
 
 def wheel_c() -> int:

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpicount.so")
-SOURCES = ["pc_tables.hip", "pc_leaves.hip", "pc_sieve.hip", "pc_plan.hip", "pc_batch.hip", "pc_host.hip"]
+SOURCES = ["pc_tables.hip", "pc_leaves.hip", "pc_sieve.hip", "pc_plan.hip", "pc_batch.hip", "pc_seed.hip", "pc_host.hip"]
 ARCH = os.environ.get("PICOUNT_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -131,13 +131,25 @@ struct Tables {
 };
 Tables g_T;
 
+// The columns j >= 1 whose seed term at m expands by eq. (4.1): those with
+// p_{c+j}^3 <= m, pi(icbrt m) - c of them (icbrt m <= 2^16 for m <= 2^48).
+uint32_t seed_rec_cols(uint64_t m, uint32_t c, uint32_t nb)
+{
+    const uint64_t v = pc_icbrt(m);
+    const Tables &T = g_T;
+    if (v > T.pi_host_max)
+        fail(PC_EINTERNAL, "seed columns beyond the host copy of the pi table");
+    const uint64_t pv = v >= 2 ? pc_pi_lookup(T.pi_host.data(), v) : 0;
+    return (uint32_t)std::min<uint64_t>(nb, pv > c ? pv - c : 0);
+}
+
 struct QueryBufs {
     DevBuf Ub, Xb, Xd, Xbh, e_start, e_count, e_off, e_scount, e_bk, e_boff, e_tmp, e_total, e_clu,
         part, sums, fin, qdev;
     DevBuf work, hot, bounds, tiles_a, trace;
     DevBuf tiles, cnt, wgt, carry_rows, carry_a, carry_b, status, ticket, part_tile_h,
         part_tile_p, part_scan_h, part_scan_p, err;
-    DevBuf row_off, blkoff, cntP, wP, carryP;
+    DevBuf row_off, blkoff, cntP, wP, carryP, seed_term;
 };
 QueryBufs g_Q;
 
@@ -407,7 +419,7 @@ void drop_query_bufs()
                      &B.sums, &B.fin, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
                      &B.carry_a, &B.carry_b, &B.status, &B.ticket, &B.part_tile_h,
                      &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err, &B.qdev,
-                     &B.row_off, &B.blkoff, &B.cntP, &B.wP, &B.carryP};
+                     &B.row_off, &B.blkoff, &B.cntP, &B.wP, &B.carryP, &B.seed_term};
     for (DevBuf *b : all)
         dfree(*b);
 }
@@ -480,6 +492,7 @@ struct Knobs {
     uint32_t wg = 512;
     bool two_pass = false;
     bool batch = true;
+    bool seeded = false;             // windows seeded on their own (Section 4), run last to first
     uint64_t carry_budget = 6ull << 30;
     uint64_t tile_leaves = 1u << 21; // hard-leaf items per tile; 0 = no column splitting
     uint32_t hot_log2 = 15;          // small one-wavefront segments below hot_span * y
@@ -525,6 +538,7 @@ Knobs knobs_from(const pc_config *cfg)
         fail(PC_EINVAL, "unsupported segment_kib / wg_size pair (32: 256|512, 64: 512|1024)");
     k.two_pass = (cfg->flags & PC_FLAG_TWO_PASS) != 0;
     k.batch = (cfg->flags & PC_FLAG_NO_BATCH_LARGE) == 0;
+    k.seeded = (cfg->flags & PC_FLAG_SEEDED) != 0;
     if (cfg->carry_budget)
         k.carry_budget = cfg->carry_budget;
     if (cfg->tile_leaves == 0xFFFFFFFFu)
@@ -884,6 +898,8 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
     ensure(B.blkoff, (max_chunks + 1) * 4, "scan blocks");
     ensure(B.carry_a, (size_t)Q.ncol * 8, "carry");
     ensure(B.carry_b, (size_t)Q.ncol * 8, "carry");
+    if (K.seeded)
+        ensure(B.seed_term, (size_t)Q.ncol * 8, "seed terms");
     ensure(B.status, max_tickets * 256 * 8 + 8, "look-back status");
     ensure(B.ticket, 8, "ticket");
     ensure(B.part_scan_h, max_tickets * 16 + 16, "scan partials");
@@ -916,8 +932,21 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
     uint64_t ntiles_total = 0;
     uint64_t *cin = ptr<uint64_t>(B.carry_a), *cout = ptr<uint64_t>(B.carry_b);
     const int bflag = K.batch ? 0 : 0x100;
-    for (uint64_t w = 0; w < nwin; w++) {
+    for (uint64_t wi = 0; wi < nwin; wi++) {
+        // seeded windows need nothing from each other: they run last to first
+        const uint64_t w = K.seeded ? nwin - 1 - wi : wi;
         const uint64_t r0 = win_start[w], r1 = win_start[w + 1], rows = r1 - r0;
+        if (K.seeded && w > 0) {
+            // the window's carries on their own: every integer below its first
+            // one, phi(lo - 1, c + j) in column j (Section 4)
+            const uint64_t lo_w = r0 < nA ? r0 * 2 * SA : baseB + (r0 - nA) * 2 * S;
+            hipck(pc_launch_seed(T, c, lo_w - 1, Q.nb, seed_rec_cols(lo_w - 1, c, Q.nb),
+                                 g_T.pi_limit, ptr<int64_t>(B.seed_term), cin,
+                                 ptr<int32_t>(B.err), g_stream),
+                  "seeds");
+        } else if (K.seeded) {
+            hipck(pc_launch_fill_u64(cin, Q.ncol, 0, g_stream), "fill");
+        }
         {
             std::vector<uint64_t> off(rows + 1, 0);
             for (uint64_t r = 0; r < rows; r++)
@@ -1059,7 +1088,8 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
         sent.push_back(std::move(tiles_b));
         tiles_a = std::vector<pc_tile>();
         tiles_b = std::vector<pc_tile>();
-        std::swap(cin, cout);
+        if (!K.seeded)
+            std::swap(cin, cout);
     }
     if (trace_file)
         std::fclose(trace_file);
@@ -1080,6 +1110,8 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
         fail(PC_EINTERNAL, "look-back scan did not complete");
     if (err & 8)
         fail(PC_EINTERNAL, "a sieving column before the cut lay outside its row's stored range");
+    if (err & 16)
+        fail(PC_EINTERNAL, "window seeds: pi table too short, stack too deep or a negative phi");
     if (err)
         fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment");
     if (fin.ok == 0 || (fin.ok == 2 && !x_hi))
@@ -2407,6 +2439,55 @@ pc_status pc_read_table(int which, uint64_t lo, uint64_t n, void *out)
         } else {
             fail(PC_EINVAL, "unknown table");
         }
+    });
+}
+
+pc_status pc_phi_seed(uint64_t m, uint32_t c, uint32_t b_hi, uint64_t *out)
+{
+    if (!out) {
+        t_err = "out must not be null";
+        return PC_EINVAL;
+    }
+    if (c < 1 || c > (uint32_t)kWheelC || c > b_hi) {
+        t_err = "need 1 <= c <= pc_wheel_c() and c <= b_hi";
+        return PC_EINVAL;
+    }
+    if (m > (1ull << 48) || b_hi >= (1u << 27)) {
+        t_err = "need m <= 2^48 and b_hi < 2^27";
+        return PC_ERANGE;
+    }
+    return guarded([&] {
+        init_stream();
+        Tables &T = g_T;
+        // the pi table answers every Legendre lookup (below m^(2/3)) and holds p_{b_hi + 1}
+        const uint64_t r = pc_icbrt(m) + 1;
+        uint64_t lim = std::max<uint64_t>(r * r, 1024);
+        for (;;) {
+            ensure_pi(lim);
+            if (T.nprimes >= (uint64_t)b_hi + 1)
+                break;
+            lim = 2 * T.pi_limit + 2;
+        }
+        ensure_recip((uint64_t)b_hi + 1);
+        ensure_wheel(c);
+        const uint32_t nb = b_hi - c;
+        QueryBufs &B = g_Q;
+        ensure(B.seed_term, ((size_t)nb + 1) * 8, "seed terms");
+        ensure(B.carry_a, ((size_t)nb + 1) * 8, "carry");
+        ensure(B.err, 8, "error flag");
+        hipck(pc_launch_fill_u64(ptr<uint64_t>(B.err), 1, 0, g_stream), "fill");
+        hipck(pc_launch_seed(tables_view(c), c, m, nb, seed_rec_cols(m, c, nb), T.pi_limit,
+                             ptr<int64_t>(B.seed_term), ptr<uint64_t>(B.carry_a),
+                             ptr<int32_t>(B.err), g_stream),
+              "seeds");
+        int32_t err = 0;
+        hipck(hipMemcpyAsync(out, B.carry_a.p, ((size_t)nb + 1) * 8, hipMemcpyDeviceToHost,
+                             g_stream),
+              "D2H");
+        hipck(hipMemcpyAsync(&err, B.err.p, 4, hipMemcpyDeviceToHost, g_stream), "D2H");
+        hipck(hipStreamSynchronize(g_stream), "sync");
+        if (err)
+            fail(PC_EINTERNAL, "seeds: pi table too short, stack too deep or a negative phi");
     });
 }
 

@@ -230,6 +230,16 @@ struct pc_scan_args {
 };
 hipError_t pc_launch_scan(const pc_scan_args &A, int mode, hipStream_t s);
 
+// The seeds of a window that starts at m (Section 4): out[j] = phi(m, c + j)
+// for 0 <= j <= nb, from phi(m, c) by eq. (4.1), each term closed (one left,
+// Legendre from the pi table) or expanded depth first.  T's wheel is of size
+// c; T's primes and reciprocals cover p_{c+nb}; the pi table covers
+// m^(2/3) (pi_limit, else err |= 16); m <= 2^48.  nrec >= the columns j with
+// p_{c+j}^3 <= m (one workgroup each); term: nb + 1 words of scratch.
+hipError_t pc_launch_seed(const pc_tables &T, uint32_t c, uint64_t m, uint32_t nb,
+                          uint32_t nrec, uint64_t pi_limit, int64_t *term, uint64_t *out,
+                          int32_t *err, hipStream_t s);
+
 // Final combination of the partial sums into pi(x) and its parts.
 struct pc_sums {
     pc_s128 s1, s2t, s2e, hard_local, hard_dot, p2_local, p2_dot;
