@@ -340,6 +340,10 @@ def main():
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--keep-tables", action="store_true",
                     help="reuse device tables across steps (default: rebuild every step)")
+    ap.add_argument("--carry-budget", type=int, default=0, metavar="BYTES",
+                    help="bytes of stored counts per window of segments; 0 = library default")
+    ap.add_argument("--seeded", action="store_true",
+                    help="seed every window on its own with phi(m_min, b) (Section 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-queries", type=int, default=BATCH_N, help="0 = skip the batch leg")
     ap.add_argument("--serve-requests", type=int, default=400,
@@ -369,7 +373,12 @@ def main():
     import paper_1503_01839_amd as pc
 
     flags = 0 if args.keep_tables else pc.FLAG_REBUILD_TABLES
-    cfg = dict(alpha=args.alpha, segment_kib=args.segment_kib, wg_size=args.wg, flags=flags)
+    if args.seeded:
+        flags |= pc.FLAG_SEEDED
+    cfg = dict(alpha=args.alpha, segment_kib=args.segment_kib, wg_size=args.wg, flags=flags,
+               carry_budget=args.carry_budget)
+    default_knobs = not (args.seeded or args.carry_budget or args.alpha or args.segment_kib
+                         or args.wg)
     x = args.x
     pi_want = expected_pi(x)
     rec = None
@@ -410,7 +419,7 @@ def main():
     achieved = ops_per_launch / (avg_launch_ms / 1e3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK / 1e12,
             "unit": "T int-ops/s", "frac": achieved / INT_PEAK,
-            "traffic": traffic_bytes() if x == X else None,
+            "traffic": traffic_bytes() if x == X and default_knobs else None,
             "kernel": "k_sieve", "launches": launches, "avg_launch_ms": avg_launch_ms,
             "ops_per_launch": ops_per_launch,
             "work": {"crossings": r.crossings, "prime_visits": visits, "hard_leaves": r.n_hard,
@@ -437,7 +446,9 @@ def main():
                                 else f"pi(x) single query, x = {x}"), "x": x,
                    "alpha": r.y / icbrt(x), "y": r.y, "a": r.a, "c": r.c, "z": r.z, "bmax": r.bmax,
                    "segment_bits": r.segment_bits, "segments": r.segments,
-                   "windows": r.windows, "tables_rebuilt_each_step": not args.keep_tables},
+                   "windows": r.windows, "carry_budget": args.carry_budget or "default",
+                   "windows_seeded": args.seeded,
+                   "tables_rebuilt_each_step": not args.keep_tables},
         "pi": r.pi, "parts": parts(r),
         "checked_against": {"paper_table": pi_want is not None,
                             "oracle_record": rec is not None,
@@ -454,7 +465,7 @@ def main():
         "crossings_per_s": r.crossings / (ms_step / 1e3),
         "phase_ms": {"tables": r.ms_tables, "leaves": r.ms_leaves, "sieve": r.ms_sieve,
                      "k_sieve": r.ms_k_sieve, "k_scan": r.ms_k_scan, "k_easy": r.ms_k_easy,
-                     "k_s1": r.ms_k_s1},
+                     "k_s1": r.ms_k_s1, "k_seed": r.ms_k_seed},
         "device_bytes": r.device_bytes,
         "roofline": roof,
         "roofline_easy": roof_easy,

@@ -61,7 +61,8 @@ class _Result(C.Structure):
                [(n, C.c_uint32) for n in ("sieve_launches", "scan_launches")] + \
                [(n, C.c_double) for n in ("ms_total", "ms_tables", "ms_leaves", "ms_sieve",
                                           "ms_k_sieve", "ms_k_scan", "ms_k_easy", "ms_k_s1")] + \
-               [("n_easy_items", C.c_uint64), ("x_hi", C.c_uint64), ("pi_hi", C.c_uint64)]
+               [("n_easy_items", C.c_uint64), ("x_hi", C.c_uint64), ("pi_hi", C.c_uint64),
+                ("ms_k_seed", C.c_double)]
 
 
 @dataclass
@@ -104,6 +105,7 @@ class Result:
     n_easy_items: int
     x_hi: int
     pi_hi: int
+    ms_k_seed: float
 
 class ServeConfig(C.Structure):
     _fields_ = [("max_inflight", C.c_uint32), ("max_round", C.c_uint32),

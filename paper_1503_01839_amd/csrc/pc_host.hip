@@ -844,7 +844,7 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
 
     // --- the sieve of [1, z] in windows of segments ---
     auto t2 = clk::now();
-    std::vector<size_t> ev_sieve, ev_scan;
+    std::vector<size_t> ev_sieve, ev_scan, ev_seed;
     // Row lengths of the count staircase: a hard leaf of p_b has u < x / p_b^2,
     // so row r (first integer lo_r) stores the columns of the primes
     // p_b <= isqrt(x / lo_r), and the first row stores every column.
@@ -940,10 +940,13 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
             // the window's carries on their own: every integer below its first
             // one, phi(lo - 1, c + j) in column j (Section 4)
             const uint64_t lo_w = r0 < nA ? r0 * 2 * SA : baseB + (r0 - nA) * 2 * S;
-            hipck(pc_launch_seed(T, c, lo_w - 1, Q.nb, seed_rec_cols(lo_w - 1, c, Q.nb),
-                                 g_T.pi_limit, ptr<int64_t>(B.seed_term), cin,
-                                 ptr<int32_t>(B.err), g_stream),
-                  "seeds");
+            const uint32_t nrec = seed_rec_cols(lo_w - 1, c, Q.nb);
+            ev_seed.push_back(timed([&] {
+                hipck(pc_launch_seed(T, c, lo_w - 1, Q.nb, nrec, g_T.pi_limit,
+                                     ptr<int64_t>(B.seed_term), cin, ptr<int32_t>(B.err),
+                                     g_stream),
+                      "seeds");
+            }));
         } else if (K.seeded) {
             hipck(pc_launch_fill_u64(cin, Q.ncol, 0, g_stream), "fill");
         }
@@ -1159,6 +1162,8 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
             res->ms_k_sieve += ev_ms(i);
         for (size_t i : ev_scan)
             res->ms_k_scan += ev_ms(i);
+        for (size_t i : ev_seed)
+            res->ms_k_seed += ev_ms(i);
         res->sieve_launches = (uint32_t)ev_sieve.size();
         res->scan_launches = (uint32_t)ev_scan.size();
     }
