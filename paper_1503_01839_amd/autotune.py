@@ -24,7 +24,7 @@ values, Section 5), must equal Table 1 where x is a power of ten, and a
 batch must return the same values at every alpha it is timed at; any
 disagreement stops the tuner.  Segments of 128 KiB are not among the shapes:
 the library builds 32 and 64 KiB segments only (the 64 KiB ones already run
-30-55% slower than 32 KiB at 1e16 and 1e18, and 128 KiB would leave one
+35-60% slower than 32 KiB at 1e18 and 1e19, and 128 KiB would leave one
 workgroup per CU).
 
 Rebuild the library afterwards (__graft_entry__.build())."""
@@ -36,7 +36,7 @@ import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HEADER = os.path.join(HERE, "csrc", "pc_alpha_table.h")
-ALPHAS = [1, 1.5, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48]
+ALPHAS = [1, 1.5, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96]
 SHAPES = [(32, 512), (32, 256), (64, 512), (64, 1024)]  # (segment KiB, workgroup threads)
 BATCH_HI = 16.0   # half decades above take the single-query alpha in batches
 BATCH_SEED = 1503
@@ -63,7 +63,8 @@ def candidates(log10x: float) -> list[float]:
     """alpha values worth timing at this size (small alpha at large x means a
     sieve too long to be competitive, and minutes of tuning)."""
     lo = 1 if log10x < 12 else 2 if log10x < 15 else 4 if log10x < 17 else 8
-    return [a for a in ALPHAS if a >= lo]
+    hi = 48 if log10x < 15 else 96  # the largest alphas pay off only once the sieve is long
+    return [a for a in ALPHAS if lo <= a <= hi]
 
 
 def tune(lo: float = 7.0, hi: float = 19.0, reps: int = 3, log=print):
