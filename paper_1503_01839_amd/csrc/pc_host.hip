@@ -1115,6 +1115,8 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
         fail(PC_EINTERNAL, "a sieving column before the cut lay outside its row's stored range");
     if (err & 16)
         fail(PC_EINTERNAL, "window seeds: pi table too short, stack too deep or a negative phi");
+    if (err & 32)
+        fail(PC_EINTERNAL, "a segment's carried unsieved count disagreed with its recount");
     if (err)
         fail(PC_EINTERNAL, "a leaf or P2 quotient fell outside its segment");
     if (fin.ok == 0 || (fin.ok == 2 && !x_hi))

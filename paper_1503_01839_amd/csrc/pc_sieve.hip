@@ -294,6 +294,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
 
     const uint32_t col_lo = tile.col_lo, col_hi = tile.col_hi;
     const uint32_t ncross = min(col_hi, Q.nb);
+    bool recounted = false; // the carried count was checked against the bitmap (uniform)
     for (uint32_t cb = 0; cb < ncross; cb += CH) {
         const uint32_t jall = min((uint32_t)CH, ncross - cb);
         if (tid == 0) {
@@ -930,6 +931,12 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         }
         PC_PH(7);
         if (jend < jall) {
+            // Device invariant: the unsieved count carried through every
+            // crossing so far (each wave's own hits, summed per column) must
+            // equal a fresh count of the bitmap.
+            if (build_pre() != total && tid == 0)
+                atomicOr(A.err, 32);
+            recounted = true;
             // Every column from cb + jend on is past its last hard leaf: its
             // count is read by no leaf and it removes nothing a later leaf of
             // this segment counts, so its multiples are only cleared, in any
@@ -965,7 +972,10 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     pc_s128 extra_p2 = 0; // PC_MODE_LEAVES: carry * (lookups), kept by thread 0
     if (col_hi == ncol) {
         __syncthreads();
-        total = build_pre(); // (the running total skips the cleared-only columns)
+        const uint32_t rec = build_pre(); // (the carried total skips the cleared-only columns)
+        if (!recounted && rec != total && tid == 0)
+            atomicOr(A.err, 32); // the invariant above, for a segment with no cut
+        total = rec;
         uint32_t k1 = 1, k2 = 0;
         {
             // x/p < hi <=> p > x/hi;  x/p >= lo <=> p <= x/lo  (above 2^64: every
