@@ -106,3 +106,14 @@ def test_seeded_windows_wide(pc, paper_pow2):
     r = pc.pi_count_wide(2**65, carry_budget=1 << 28, flags=pc.FLAG_SEEDED)
     assert r.windows > 1
     assert r.pi == paper_pow2[65]
+
+
+def test_seeded_windows_in_batches(pc, paper_pow10):
+    # a batch whose large members run alone in seeded windows
+    xs = [10**9, 10**13 + 1, 10**14, 3 * 10**11, 10**13]
+    say("case: batch with seeded windows")
+    solo = [pc.pi_count(x) for x in xs]
+    for budget in (1 << 16, 1 << 20):
+        assert pc.pi_count_batch(xs, carry_budget=budget, flags=pc.FLAG_SEEDED) == solo, budget
+    assert solo[2] == paper_pow10[14] and solo[4] == paper_pow10[13]
+
