@@ -14,8 +14,8 @@
 //   * otherwise:                     eq. (4.1) again on (u, b-1): phi(u, c) less
 //     the children (floor(u / p_i), i-1), c < i < b, each resolved the same way
 //     depth first.  These are the b with p_b^3 <= m, a few hundred to a few
-//     thousand columns; their children are dealt out to the threads of one
-//     workgroup per column.
+//     thousand columns; their children's children are dealt out to the
+//     threads of one workgroup per column.
 // Three launches: the closed terms (one thread per column), the recursive
 // terms (one workgroup per column p_b <= icbrt m), and the prefix sum (one
 // workgroup).
@@ -130,9 +130,13 @@ __global__ __launch_bounds__(SEED_T) void k_seed_terms(seed_ctx S, uint64_t m, u
     term[j] = seed_leaf(S, u, b - 1, &v) ? v : seed_wheel(S, u);
 }
 
-// One workgroup per column j = blockIdx.x + 1: if its term expands, the
-// children (floor(u / p_i), i-1), c < i < b, are shared by the threads and
-// their sum comes off the term.
+// One workgroup per column j = blockIdx.x + 1: if its term expands, the sum
+// of its children phi(floor(u / p_i), i-1), c < i < b, comes off the term.
+// The threads share the children one level further down, so that no thread
+// walks a whole child's tree: child a (i = c + 1 + a) owns slots 0..a of a
+// triangle, slot 0 for the child itself (its closed value, or phi(v, c) when
+// it expands) and slot s >= 1 for its own child (floor(v / p_{c+s}), c+s-1),
+// taken with the opposite sign when the child expands.
 __global__ __launch_bounds__(SEED_T) void k_seed_rec(seed_ctx S, uint64_t m, uint32_t nb,
                                                      int64_t *term)
 {
@@ -145,9 +149,27 @@ __global__ __launch_bounds__(SEED_T) void k_seed_rec(seed_ctx S, uint64_t m, uin
     const uint64_t u = pc_div(m, p, S.recip[b]);
     if (u < p * p) // closed (uniform over the workgroup)
         return;
+    const uint64_t na = b - 1 - S.c, nslot = na * (na + 1) / 2;
     int64_t s = 0;
-    for (uint32_t i = S.c + 1 + threadIdx.x; i < b; i += SEED_T)
-        s += seed_phi(S, pc_div(u, S.primes[i], S.recip[i]), i - 1);
+    for (uint64_t t = threadIdx.x; t < nslot; t += SEED_T) {
+        // the child a with a (a + 1) / 2 <= t < (a + 1) (a + 2) / 2
+        uint64_t a = (uint64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((a + 1) * (a + 2) / 2 <= t)
+            a++;
+        while (a * (a + 1) / 2 > t)
+            a--;
+        const uint32_t slot = (uint32_t)(t - a * (a + 1) / 2);
+        const uint32_t i = S.c + 1 + (uint32_t)a;
+        const uint64_t v = pc_div(u, S.primes[i], S.recip[i]);
+        int64_t lv;
+        const bool closed = seed_leaf(S, v, i - 1, &lv);
+        if (slot == 0) {
+            s += closed ? lv : seed_wheel(S, v);
+        } else if (!closed) {
+            const uint32_t i2 = S.c + slot; // c < i2 < i
+            s -= seed_phi(S, pc_div(v, S.primes[i2], S.recip[i2]), i2 - 1);
+        }
+    }
     s = pc_block_sum<SEED_T>(s, scr);
     if (threadIdx.x == 0)
         term[j] -= s;
