@@ -187,6 +187,16 @@ def test_phi_column_pins():
         assert int(col[b]) == pm - b + 1, b
 
 
+def test_phi_column_legendre_tail_vs_table1(paper_pow10):
+    # past pi(sqrt m) the column is pi(m) - b + 1, pi(10^8) from Table 1
+    m = 10**8
+    kr = sum(1 for p in py_primes(10**4) if p * p <= m)  # pi(sqrt m) = pi(10^4)
+    col = O.phi_column(m, kr + 40)
+    for b in range(kr, kr + 41):
+        assert int(col[b]) == paper_pow10[8] - b + 1, b
+    assert int(col[6]) == 5760 * (m // 30030) + int(O.phi_column(m % 30030, 6)[6])
+
+
 def test_phi_large_vs_meissel_and_table(paper_pow10):
     # phi(x, pi(icbrt x)) + a - 1 - P2 reproduces Table 1 for n <= 12
     for n in range(3, 13):
