@@ -250,6 +250,42 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         const uint32_t s = half_count(q, &up), blk = q >> BL;
         return up ? pre[blk + 1] - s : pre[blk] + s;
     };
+    // A wave's own blocks with finer sums (one block per thread): the block's
+    // unsieved count, and in *pk the prefix counts of its first one, two and
+    // three quarters of 128 bits (10 bits each).
+    auto block_counts_q = [&](uint32_t *pk) -> uint32_t {
+        const uint32_t base = tid * 17;
+        uint32_t qs[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; k++) {
+            uint32_t c = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < 4; i++)
+                c += (uint32_t)__builtin_popcount(bm[base + 4 * k + i]);
+            qs[k] = c;
+        }
+        const uint32_t p1 = qs[0], p2 = p1 + qs[1], p3 = p2 + qs[2];
+        *pk = p1 | (p2 << 10) | (p3 << 20);
+        return p3 + qs[3];
+    };
+    // unsieved integers of q's block below q, from the block's quarter
+    // prefixes pk and total tb: two words of q's quarter are read, the ones
+    // on q's side (up from the quarter's start, or down from its end)
+    auto quarter_count = [&](uint32_t q, uint32_t pk, uint32_t tb) -> uint32_t {
+        const uint32_t off = q & 511u, qq = off >> 7, w = (off >> 5) & 3u;
+        const uint32_t part = (1u << (q & 31u)) - 1u; // bits below q in its word
+        const uint32_t below = qq ? (pk >> (10u * (qq - 1u))) & 1023u : 0u;
+        const uint32_t through = qq < 3u ? (pk >> (10u * qq)) & 1023u : tb;
+        const bool low = w < 2u;
+        const uint32_t a0 = (q >> BL) * 17u + qq * 4u + (low ? 0u : 2u);
+        const uint32_t v0 = bm[a0], v1 = bm[a0 + 1];
+        if (low) // words [0, w) of the quarter and the part of w below q
+            return below + (uint32_t)__builtin_popcount(v0 & (w == 0u ? part : ~0u)) +
+                   (uint32_t)__builtin_popcount(v1 & (w == 1u ? part : 0u));
+        // the quarter less the rest of w and the words after it
+        return through - (uint32_t)__builtin_popcount(v0 & (w == 2u ? ~part : 0u)) -
+               (uint32_t)__builtin_popcount(v1 & (w == 2u ? ~0u : ~part));
+    };
 
     uint32_t total = build_pre();
     PC_PH(0);
@@ -467,7 +503,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                 }
             if (es0 < es1) {
                 bool have = false;
-                uint32_t pe = 0, pc0 = 0; // lane prefix of the region's block counts; first block
+                uint32_t pe = 0, pc0 = 0, pq = 0; // lane prefix of the region's block counts;
+                // first block (or, one block a lane, its count and quarter prefixes)
                 const float rp = __builtin_amdgcn_rcpf((float)p);
                 for (uint32_t s = es0; s < es1; s += 64) {
                     const uint32_t e = s + lane < es1 ? gbuf[s + lane] : 0u;
@@ -477,10 +514,16 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                     if (!pend)
                         continue;
                     if (!have) {
-                        uint32_t cnt[BPT];
-                        const uint32_t sum = block_counts(cnt);
+                        uint32_t sum;
+                        if (BPT > 1) {
+                            uint32_t cnt[BPT];
+                            sum = block_counts(cnt);
+                            pc0 = cnt[0];
+                        } else {
+                            sum = block_counts_q(&pq);
+                            pc0 = sum;
+                        }
                         pe = pc_wave_incl_scan_u32(sum) - sum;
-                        pc0 = cnt[0];
                         have = true;
                     }
                     const uint32_t bl = in ? (q >> BL) - (R0 >> BL) : 0u;
@@ -491,13 +534,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                         c += (bl % BPT) ? c0 : 0u;
                         if (in)
                             c += in_block(q);
-                    } else { // the block's count is its lane's: count from q's side
+                    } else { // the block is its lane's: count from its quarter prefixes
                         const uint32_t tb = (uint32_t)__shfl((int)pc0, (int)src, 64);
-                        if (in) {
-                            bool up;
-                            const uint32_t hs = half_count(q, &up);
-                            c += up ? tb - hs : hs;
-                        }
+                        const uint32_t pk = (uint32_t)__shfl((int)pq, (int)src, 64);
+                        if (in)
+                            c += quarter_count(q, pk, tb);
                     }
                     // less the earlier columns' credited multiples below q:
                     // leaf by leaf (all lanes count for one leaf) or column
@@ -695,17 +736,24 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
             PC_EV(1);
             const uint32_t s0 = g >> 11, s1 = s0 + (g & 0x7FFu);
             bool have = false;
-            uint32_t pe = 0, pc0 = 0; // lane prefix of the region's block counts; first block
+            uint32_t pe = 0, pc0 = 0, pq = 0; // lane prefix of the region's block counts;
+                // first block (or, one block a lane, its count and quarter prefixes)
             for (uint32_t s = s0; s < s1; s += 64) {
                 const uint32_t e = s + lane < s1 ? gbuf[s + lane] : 0u;
                 const uint32_t q = (e >> 2) & 0xFFFFFu;
                 const bool in = (e & 1) && (q >> RSL) == wv;
                 if (__ballot(in)) {
                     if (!have) {
-                        uint32_t cnt[BPT];
-                        const uint32_t sum = block_counts(cnt);
+                        uint32_t sum;
+                        if (BPT > 1) {
+                            uint32_t cnt[BPT];
+                            sum = block_counts(cnt);
+                            pc0 = cnt[0];
+                        } else {
+                            sum = block_counts_q(&pq);
+                            pc0 = sum;
+                        }
                         pe = pc_wave_incl_scan_u32(sum) - sum;
-                        pc0 = cnt[0];
                         have = true;
                     }
                     const uint32_t bl = in ? (q >> BL) - (R0 >> BL) : 0u;
@@ -716,14 +764,12 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                         c += (bl % BPT) ? c0 : 0u;
                     }
                     const uint32_t tb = (uint32_t)__shfl((int)pc0, (int)src, 64);
+                    const uint32_t pk = (uint32_t)__shfl((int)pq, (int)src, 64);
                     if (in) {
-                        if (BPT > 1) {
+                        if (BPT > 1)
                             c += in_block(q);
-                        } else { // the block's count is its lane's: count from q's side
-                            bool up;
-                            const uint32_t hs = half_count(q, &up);
-                            c += up ? tb - hs : hs;
-                        }
+                        else // the block is its lane's: count from its quarter prefixes
+                            c += quarter_count(q, pk, tb);
                         acc_local += (e & 2) ? -(int64_t)c : (int64_t)c;
                     }
                 }
