@@ -698,6 +698,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                         oa = o;
                     }
                 }
+                int32_t wl = 0;   // -mu(m) of this slot's leaf, 0 if none
+                uint32_t rl = 0xFFu; // its region (0xFF: none, or above every region)
                 if (s < used) {
                     const uint32_t aj = cg0 + a;
                     uint64_t m;
@@ -710,14 +712,31 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
                         if (ok) {
                             const uint32_t r = q >> RSL;
                             e = (a << 22) | (q << 2) | (w < 0 ? 2u : 0u) | 1u;
-                            atomicAdd(&c_w[aj], w);
-                            if (r < NWV)
-                                atomicOr(&rm[a], 1u << r);
+                            wl = w;
+                            rl = r < NWV ? r : 0xFFu;
                             nleaf++;
                         }
                     }
                     gbuf[s] = e;
                 }
+                // The wave's slots are consecutive, so its lanes hold runs of one
+                // column (and within a column, of one region: u falls with m).
+                // Column weights: one add per run, from a wave scan of the
+                // weights; region masks: one OR per run of (column, region).
+                const uint32_t key = s < used ? a : 0xFFu;
+                const uint32_t kr = key << 8 | rl;
+                const uint32_t kr_prev = (uint32_t)__shfl_up((int)kr, 1, 64);
+                if (rl != 0xFFu && (lane == 0 || kr_prev != kr))
+                    atomicOr(&rm[a], 1u << rl);
+                const uint32_t inc = pc_wave_incl_scan_u32((uint32_t)wl);
+                const uint32_t key_next = (uint32_t)__shfl_down((int)key, 1, 64);
+                const bool tail = lane == 63 || key_next != key;
+                const uint64_t below = __ballot(tail) & ((1ull << lane) - 1);
+                const int32_t pt = below ? 63 - __builtin_clzll(below) : 0;
+                const uint32_t base = (uint32_t)__shfl((int)inc, pt, 64);
+                const int32_t run = (int32_t)(inc - (below ? base : 0u));
+                if (tail && key != 0xFFu && run != 0)
+                    atomicAdd(&c_w[cg0 + key], run);
             }
             if (wv == 0) { // the round's table
                 const bool g = lane < kend && v != 0;
