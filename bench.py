@@ -72,6 +72,7 @@ SERVE_TOTAL = 20000  # the stream's full length; the default run serves a prefix
 # scaled by the same counters on a plain copy of known size; reported only while
 # the kernel source is the one the counters were taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sieve_traffic_1e18.txt")
+PEAKS_FILE = os.path.join(ROOT, "profiles", "gpu_peaks_microbench.txt")
 KERNEL_SRC = [os.path.join(ROOT, "paper_1503_01839_amd", "csrc", f)
               for f in ("pc_sieve.hip", "pc_leafrange.h", "pc_block.h", "pc_device.h",
                         "pc_internal.h")]
@@ -146,6 +147,16 @@ def check_step(tag, r, pi_want, rec, first):
         bad.append({"step": tag, "what": "differs from the first step", "got": got,
                     "want": first})
     return bad
+
+
+def lds_rmw_peak():
+    """LDS atomic read-modify-writes per second of this GPU in the crossing
+    pattern, from the committed micro-benchmark summary, or None."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(PEAKS_FILE) if ":" in line)
+        return float(kv["lds_atomic_crossing_per_s"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def traffic_bytes():
@@ -426,6 +437,14 @@ def main():
                      "p2_lookups": r.n_p2,
                      "ops_per_unit": {"crossing": OPS_CROSSING, "visit": OPS_VISIT,
                                       "leaf": OPS_LEAF}}}
+    # the same kernel against its LDS bound: one atomic read-modify-write per
+    # crossing, at the measured rate of the crossing pattern
+    lds_peak = lds_rmw_peak()
+    rmw = r.crossings / max(launches, 1)
+    roof_lds = None if not lds_peak else {
+        "bound": "lds", "achieved": rmw / (avg_launch_ms / 1e3) / 1e12, "peak": lds_peak / 1e12,
+        "unit": "T LDS RMW/s", "frac": rmw / (avg_launch_ms / 1e3) / lds_peak, "kernel": "k_sieve",
+        "peak_source": "profiles/gpu_peaks_microbench.txt", "rmw_per_launch": rmw}
     e_ms = sum(q.ms_k_easy for q in results) / len(results)
     e_ops = OPS_EASY_ITEM * r.n_easy_items
     roof_easy = {"bound": "alu", "achieved": e_ops / (e_ms / 1e3) / 1e12 if e_ms else None,
@@ -469,6 +488,7 @@ def main():
         "device_bytes": r.device_bytes,
         "roofline": roof,
         "roofline_easy": roof_easy,
+        "roofline_lds": roof_lds,
         "paper_context": "Table 3: pi(1e18) took 108 node-s (v2015.01.30) on 2x Xeon E5-2670 "
                          "(16 cores); not a target",
     }

@@ -29,10 +29,12 @@ def _compile(src: str) -> str:
 
 # The GPU tests' device libraries (tests/device): each a shared library of its
 # own, compiled from the test's source against csrc/pc_device.h: the check of
-# the device quotient helpers, and the comparison of two pi tables.
+# the device quotient helpers, the comparison of two pi tables, and the
+# micro-benchmarks of the GPU's peaks.
 DEVICE_TESTS = [(os.path.join(ROOT, "tests", "device", src), os.path.join(ROOT, "tests", "device", lib))
                 for src, lib in (("div_check.hip", "libdivcheck.so"),
-                                 ("pi_table_bench.hip", "libpitable.so"))]
+                                 ("pi_table_bench.hip", "libpitable.so"),
+                                 ("peaks.hip", "libpeaks.so"))]
 
 
 def _device_test(src: str, lib: str) -> str:
