@@ -281,68 +281,81 @@ hipError_t pc_launch_recip(const uint32_t *primes, uint64_t *recip, double *rcpd
 
 // ---------------------------------------------------------------------------
 // mu(n)*lpf(n) for n <= ymax by a segmented factor sieve.  Each workgroup owns
-// 4096 consecutive n; the primes <= sqrt(ymax) (all below 2^16) are applied in
-// increasing order (one barrier each), so the first prime to touch n is its
-// least prime factor.  A cofactor left above 1 is one prime > sqrt(ymax).
+// MF_N consecutive n and applies every prime p <= sqrt(ymax) (all below 2^16)
+// to them; a cofactor left above 1 is one prime > sqrt(ymax).
 //
-// Per n one state word: bits 0-15 the least prime factor, bit 16 the sign of
-// mu, bit 17 set once some p^2 divides n.  Within one prime p, the thread that
-// records p for a multiple of p and the thread that marks a multiple of p^2
-// are in general different threads, often of different wavefronts, with no
-// barrier between them; both update the word with LDS atomics (xor, or), so
-// neither update can be lost.  (A plain read-modify-write interleaved with
-// the other thread's update would lose it, and a non-squarefree n would be
-// taken as squarefree.)  The product of n's small prime factors has one
-// writer per prime.
+// Per n three words, each updated only by LDS atomics that commute, so that
+// the primes can be applied in any order and by any threads with no barrier
+// between them: the least prime factor (atomic min), the parity of the number
+// of distinct small prime factors in bit 0 and "some p^2 divides n" in bit 1
+// (atomic xor, or), and the product of the distinct small prime factors
+// (compare-and-swap multiply; it stays <= n < 2^31).  The first MF_PS primes,
+// whose multiples are dense, are shared by all threads of the workgroup; each
+// larger prime (at most MF_N / p_(MF_PS+1) < 16 multiples, and at most one
+// multiple of p^2) belongs to one thread.
+// ---------------------------------------------------------------------------
 #define MF_N 4096
-#define MF_T 256
-#define MF_SIGN (1u << 16)
-#define MF_SQ (1u << 17)
+#define MF_T 512
+#define MF_PS 64
 
 __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t nsmall,
                                                uint64_t ymax, int32_t *out)
 {
-    __shared__ uint32_t st[MF_N];
-    __shared__ uint32_t prod[MF_N];
-    __shared__ uint32_t f1[MF_T], f2[MF_T]; // first multiples of p and p^2 in the block
+    __shared__ uint32_t lp[MF_N], fl[MF_N], prod[MF_N];
+    __shared__ uint32_t f1[MF_PS], f2[MF_PS]; // first multiples of p and p^2 in the block
     const uint32_t t = threadIdx.x;
     const uint32_t n0 = blockIdx.x * MF_N; // ymax < 2^31: every n fits 32 bits
     for (uint32_t i = t; i < MF_N; i += MF_T) {
-        st[i] = 0;
+        lp[i] = 0xFFFFFFFFu;
+        fl[i] = 0;
         prod[i] = 1;
     }
-    for (uint32_t k0 = 1; k0 <= nsmall; k0 += MF_T) {
-        // the offsets of the next MF_T primes, one per thread
-        if (k0 + t <= nsmall) {
-            const uint32_t p = primes[k0 + t];
-            const uint32_t r = n0 % p;
-            f1[t] = r ? p - r : 0;
+    // offsets from n0 of the first multiples of p and of p^2 (0xFFFFFFFF:
+    // p^2 has none in the block)
+    auto offsets = [&](uint32_t p, uint32_t *o1, uint32_t *o2) {
+        const uint32_t r = n0 % p;
+        *o1 = r ? p - r : 0;
+        *o2 = 0xFFFFFFFFu;
+        const uint64_t pp = (uint64_t)p * p;
+        if (pp < (uint64_t)n0 + MF_N) { // then pp < 2^32
+            const uint32_t r2 = n0 % (uint32_t)pp;
+            *o2 = r2 ? (uint32_t)pp - r2 : 0;
+        }
+    };
+    const uint32_t ns = min(nsmall, (uint32_t)MF_PS);
+    if (t < ns)
+        offsets(primes[1 + t], &f1[t], &f2[t]);
+    __syncthreads();
+    auto mark = [&](uint32_t i, uint32_t p) {
+        atomicMin(&lp[i], p);
+        atomicXor(&fl[i], 1u);
+        uint32_t old = prod[i];
+        for (;;) {
+            const uint32_t seen = atomicCAS(&prod[i], old, old * p);
+            if (seen == old)
+                break;
+            old = seen;
+        }
+    };
+    for (uint32_t k = 0; k < ns; k++) {
+        const uint32_t p = primes[1 + k];
+        for (uint32_t i = f1[k] + t * p; i < MF_N; i += MF_T * p)
+            mark(i, p);
+        const uint32_t o2 = f2[k];
+        if (o2 != 0xFFFFFFFFu) {
             const uint64_t pp = (uint64_t)p * p;
-            uint32_t o2 = 0xFFFFFFFFu; // p^2 has no multiple in the block
-            if (pp < (uint64_t)n0 + MF_N) { // then pp < 2^32
-                const uint32_t r2 = n0 % (uint32_t)pp;
-                o2 = r2 ? (uint32_t)pp - r2 : 0;
-            }
-            f2[t] = o2;
+            for (uint64_t i = o2 + (uint64_t)t * pp; i < MF_N; i += MF_T * pp)
+                atomicOr(&fl[i], 2u);
         }
-        __syncthreads();
-        const uint32_t kend = min(nsmall + 1, k0 + MF_T);
-        for (uint32_t k = k0; k < kend; k++) {
-            const uint32_t p = primes[k];
-            for (uint32_t i = f1[k - k0] + t * p; i < MF_N; i += MF_T * p) {
-                // bits 0-15 change only here, by this thread, while p is applied
-                const uint32_t lp = (st[i] & 0xFFFFu) ? 0u : p;
-                atomicXor(&st[i], MF_SIGN | lp);
-                prod[i] *= p;
-            }
-            const uint32_t o2 = f2[k - k0];
-            if (o2 != 0xFFFFFFFFu) {
-                const uint64_t pp = (uint64_t)p * p;
-                for (uint64_t i = o2 + (uint64_t)t * pp; i < MF_N; i += MF_T * pp)
-                    atomicOr(&st[i], MF_SQ);
-            }
-            __syncthreads();
-        }
+    }
+    for (uint32_t k = ns + 1 + t; k <= nsmall; k += MF_T) {
+        const uint32_t p = primes[k];
+        uint32_t o1, o2;
+        offsets(p, &o1, &o2);
+        for (uint32_t i = o1; i < MF_N; i += p)
+            mark(i, p);
+        if (o2 < MF_N)
+            atomicOr(&fl[o2], 2u);
     }
     __syncthreads();
     for (uint32_t i = t; i < MF_N; i += MF_T) {
@@ -354,15 +367,15 @@ __global__ __launch_bounds__(MF_T) void k_mulpf(const uint32_t *primes, uint32_t
             v = 0;
         } else if (n == 1) {
             v = 0x7FFFFFFF;
+        } else if (fl[i] & 2u) {
+            v = 0;
         } else {
-            const uint32_t w = st[i];
-            int32_t m = (w & MF_SQ) ? 0 : ((w & MF_SIGN) ? -1 : 1);
-            uint32_t l = w & 0xFFFFu;
-            if (m != 0 && prod[i] < n) {
-                uint32_t big = (uint32_t)n / prod[i];
+            int32_t m = (fl[i] & 1u) ? -1 : 1;
+            uint32_t l = lp[i];
+            if (prod[i] < n) { // one prime factor above sqrt(ymax)
                 m = -m;
-                if (l == 0)
-                    l = big;
+                if (l == 0xFFFFFFFFu)
+                    l = (uint32_t)n / prod[i];
             }
             v = m * (int32_t)l;
         }
