@@ -69,7 +69,8 @@ typedef struct {
 
 #define PC_FLAG_TWO_PASS 1u      /* count pass, carry scan, then leaf pass (else one tally pass) */
 #define PC_FLAG_NO_BATCH_LARGE 2u /* cross large primes one at a time (no batched crossing)     */
-#define PC_FLAG_REBUILD_TABLES 4u /* drop cached tables and rebuild them inside this call       */
+#define PC_FLAG_REBUILD_TABLES 4u /* rebuild the cached tables inside this call (into the same
+                                     device memory; pc_shutdown frees it)                        */
 #define PC_FLAG_NO_SMALL_SEGMENTS 8u /* no one-wavefront segments even if small_span is set        */
 #define PC_FLAG_NO_GRAPH 16u         /* batches: launch each phase directly, not as a HIP graph     */
 #define PC_FLAG_BATCH_SEQUENTIAL 32u /* batches: one query after another (the plain per-query path) */

@@ -126,10 +126,89 @@ struct Tables {
     // count staircase on the host (pi at isqrt(x / lo): every segment but the
     // first starts at lo >= 2^16, so below 2^24 for x < 2^64 and at most 2^28
     // for x <= 2^72)
-    std::vector<uint2> pi_host;
+    // (pinned host memory, kept across rebuilds: the copy runs at the link's rate)
+    uint2 *pi_host = nullptr;
+    size_t pi_host_cap = 0;   // entries allocated
     uint64_t pi_host_max = 0; // pi_host answers n <= pi_host_max
 };
 Tables g_T;
+
+// Pinned host memory for the plan copies of one query (row offsets, scan
+// blocks, tile lists, the tile planner's reads): a copy from pageable memory
+// goes through the runtime's staging at a few GB/s, one from here at the
+// link's rate.  Each copy takes its own stretch, which stays untouched until
+// the next query resets the arena after synchronising the library stream, so
+// a copy that the stream reaches late still reads what was written for it.
+// The chunks are kept from one query to the next, up to 64 MiB (a query near
+// 2^72 plans hundreds of MiB of tiles; that memory goes back after it).
+struct PinnedArena {
+    struct Chunk {
+        char *p;
+        size_t cap, used;
+    };
+    std::vector<Chunk> chunks;
+    size_t cur = 0;
+    void *take(size_t bytes)
+    {
+        bytes = (bytes + 255) & ~(size_t)255;
+        while (cur < chunks.size() && chunks[cur].cap - chunks[cur].used < bytes)
+            cur++;
+        if (cur == chunks.size()) {
+            const size_t cap = std::max<size_t>(bytes, (size_t)8 << 20);
+            void *p = nullptr;
+            if (hipHostMalloc(&p, cap, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                fail(PC_ENOMEM, "pinned staging memory for the query plan");
+            }
+            chunks.push_back(Chunk{static_cast<char *>(p), cap, 0});
+        }
+        Chunk &c = chunks[cur];
+        void *r = c.p + c.used;
+        c.used += bytes;
+        return r;
+    }
+    void reset()
+    {
+        size_t total = 0;
+        for (Chunk &c : chunks) {
+            c.used = 0;
+            total += c.cap;
+        }
+        cur = 0;
+        if (total > ((size_t)64 << 20))
+            release();
+    }
+    void release()
+    {
+        for (Chunk &c : chunks)
+            (void)hipHostFree(c.p);
+        chunks.clear();
+        cur = 0;
+    }
+};
+PinnedArena g_pin;
+
+// n bytes from host memory src to device memory dst, queued on s through the arena
+void h2d(void *dst, const void *src, size_t n, hipStream_t s, const char *what)
+{
+    if (n == 0)
+        return;
+    void *st = g_pin.take(n);
+    memcpy(st, src, n);
+    hipck(hipMemcpyAsync(dst, st, n, hipMemcpyHostToDevice, s), what);
+}
+
+// n bytes from device memory src into host memory dst, through the arena;
+// waits for s
+void d2h_sync(void *dst, const void *src, size_t n, hipStream_t s, const char *what)
+{
+    if (n == 0)
+        return;
+    void *st = g_pin.take(n);
+    hipck(hipMemcpyAsync(st, src, n, hipMemcpyDeviceToHost, s), what);
+    hipck(hipStreamSynchronize(s), "sync");
+    memcpy(dst, st, n);
+}
 
 // The columns j >= 1 whose seed term at m expands by eq. (4.1): those with
 // p_{c+j}^3 <= m, pi(icbrt m) - c of them (icbrt m <= 2^16 for m <= 2^48).
@@ -139,7 +218,7 @@ uint32_t seed_rec_cols(uint64_t m, uint32_t c, uint32_t nb)
     const Tables &T = g_T;
     if (v > T.pi_host_max)
         fail(PC_EINTERNAL, "seed columns beyond the host copy of the pi table");
-    const uint64_t pv = v >= 2 ? pc_pi_lookup(T.pi_host.data(), v) : 0;
+    const uint64_t pv = v >= 2 ? pc_pi_lookup(T.pi_host, v) : 0;
     return (uint32_t)std::min<uint64_t>(nb, pv > c ? pv - c : 0);
 }
 
@@ -234,7 +313,8 @@ void ensure_pi(uint64_t need)
                           covered > k2_32 ? ptr<uint64_t>(T.primes_hi) : nullptr,
                           ptr<uint32_t>(T.scan_tmp), g_stream),
           "pi table");
-    dfree(T.cnt_tmp);
+    if (T.cnt_tmp.cap > (1ull << 30)) // up to 2^32 (256 MiB) kept for the next build
+        dfree(T.cnt_tmp);
     T.pi_limit = covered;
     T.nprimes = lookup({covered})[0];
     T.k32 = covered > k2_32 ? kK32 : ~0ull;
@@ -245,8 +325,19 @@ void ensure_pi(uint64_t need)
     // x < 2^64, at most 2^28 for the queries up to 2^72 (tables above 2^32)
     const uint64_t nh =
         std::min<uint64_t>(nent, (covered > k2_32 ? (1ull << 28) + 64 : 1ull << 24) / 64 + 1);
-    T.pi_host.resize(nh);
-    hipck(hipMemcpyAsync(T.pi_host.data(), T.pitab.p, nh * 8, hipMemcpyDeviceToHost, g_stream),
+    if (T.pi_host_cap < nh) {
+        if (T.pi_host)
+            (void)hipHostFree(T.pi_host);
+        T.pi_host = nullptr;
+        T.pi_host_cap = 0;
+        if (hipHostMalloc((void **)&T.pi_host, nh * 8, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            T.pi_host = nullptr;
+            fail(PC_ENOMEM, "pinned host copy of the pi table");
+        }
+        T.pi_host_cap = nh;
+    }
+    hipck(hipMemcpyAsync(T.pi_host, T.pitab.p, nh * 8, hipMemcpyDeviceToHost, g_stream),
           "D2H");
     hipck(hipStreamSynchronize(g_stream), "sync");
     T.pi_host_max = 64 * nh - 1;
@@ -259,14 +350,19 @@ uint32_t row_len(pc_u128 x, uint32_t c, uint32_t nb, uint64_t lo)
 {
     if (lo == 0)
         return nb;
-    const pc_u128 q = x / lo;
-    if (q >> 64)
-        fail(PC_EINTERNAL, "row length: x / lo beyond 2^64");
+    pc_u128 q;
+    if ((x >> 64) == 0) {
+        q = (uint64_t)x / lo; // (a 64-bit division: the planner takes one per row)
+    } else {
+        q = x / lo;
+        if (q >> 64)
+            fail(PC_EINTERNAL, "row length: x / lo beyond 2^64");
+    }
     const uint64_t v = pc_isqrt((uint64_t)q);
     const Tables &T = g_T;
     if (v > T.pi_host_max)
         fail(PC_EINTERNAL, "row length beyond the host copy of the pi table");
-    const uint64_t pv = pc_pi_lookup(T.pi_host.data(), v);
+    const uint64_t pv = pc_pi_lookup(T.pi_host, v);
     return (uint32_t)std::min<uint64_t>(nb, pv > c ? pv - c : 0);
 }
 
@@ -391,24 +487,40 @@ pc_tables tables_view(uint32_t c)
     return v;
 }
 
-void drop_tables()
+// Marks every table unbuilt, so that the next call that needs one builds it
+// again.  release: also free their memory; else the next build writes into
+// the same allocations (after every kernel queued earlier, which may still
+// read them, has finished).
+void drop_tables(bool release)
 {
     Tables &T = g_T;
-    DevBuf *all[] = {&T.base, &T.nbase_d, &T.pitab, &T.primes, &T.primes_hi, &T.cnt_tmp,
-                     &T.scan_tmp, &T.recip,
-                     &T.rcpd, &T.mulpf, &T.lk_in, &T.lk_out, &T.chk};
-    for (DevBuf *b : all)
-        dfree(*b);
-    for (int c = 0; c <= kWheelC; c++) {
-        dfree(T.pattern[c]);
-        dfree(T.phitab[c]);
-        dfree(T.wres[c]);
-        T.wheel_ok[c] = false;
+    if (release) {
+        DevBuf *all[] = {&T.base, &T.nbase_d, &T.pitab, &T.primes, &T.primes_hi, &T.cnt_tmp,
+                         &T.scan_tmp, &T.recip,
+                         &T.rcpd, &T.mulpf, &T.lk_in, &T.lk_out, &T.chk};
+        for (DevBuf *b : all)
+            dfree(*b);
+        for (int c = 0; c <= kWheelC; c++) {
+            dfree(T.pattern[c]);
+            dfree(T.phitab[c]);
+            dfree(T.wres[c]);
+        }
+        if (T.pi_host)
+            (void)hipHostFree(T.pi_host);
+        T.pi_host = nullptr;
+        T.pi_host_cap = 0;
+    } else {
+        async_wait_all();
+        if (g_stream2)
+            (void)hipStreamSynchronize(g_stream2);
+        if (g_stream)
+            (void)hipStreamSynchronize(g_stream);
     }
+    for (int c = 0; c <= kWheelC; c++)
+        T.wheel_ok[c] = false;
     T.base_ok = false;
     T.pi_limit = T.nprimes = T.recip_n = T.y_limit = 0;
     T.k32 = ~0ull;
-    T.pi_host.clear();
     T.pi_host_max = 0;
 }
 
@@ -626,9 +738,7 @@ void plan_tiles(const pc_tables &T, const pc_query &Q, const Knobs &K, uint32_t 
                                  ptr<uint64_t>(B.work), g_stream),
               "tile plan");
         std::vector<uint64_t> work(np);
-        hipck(hipMemcpyAsync(work.data(), B.work.p, np * 8, hipMemcpyDeviceToHost, g_stream),
-              "D2H");
-        hipck(hipStreamSynchronize(g_stream), "sync");
+        d2h_sync(work.data(), B.work.p, np * 8, g_stream, "D2H");
         // The target: K.tile_leaves, or less when the whole window holds little
         // leaf work, so that no tile outlasts the rest of the launch (about
         // 768 workgroups run at once; a tile should carry at most twice its
@@ -661,17 +771,12 @@ void plan_tiles(const pc_tables &T, const pc_query &Q, const Knobs &K, uint32_t 
             }
             ensure(B.hot, hot.size() * sizeof(uint4), "tile plan");
             ensure(B.bounds, (size_t)off * 4, "tile plan");
-            hipck(hipMemcpyAsync(B.hot.p, hot.data(), hot.size() * sizeof(uint4),
-                                 hipMemcpyHostToDevice, g_stream),
-                  "H2D");
+            h2d(B.hot.p, hot.data(), hot.size() * sizeof(uint4), g_stream, "H2D");
             hipck(pc_launch_seg_split(T, Q, log2s, lo_base, seg_base, ptr<uint4>(B.hot),
                                       (uint32_t)hot.size(), ptr<uint32_t>(B.bounds), g_stream),
                   "tile split");
             std::vector<uint32_t> bd(off);
-            hipck(hipMemcpyAsync(bd.data(), B.bounds.p, (size_t)off * 4, hipMemcpyDeviceToHost,
-                                 g_stream),
-                  "D2H");
-            hipck(hipStreamSynchronize(g_stream), "sync");
+            d2h_sync(bd.data(), B.bounds.p, (size_t)off * 4, g_stream, "D2H");
             for (const uint4 &h : hot) {
                 const uint32_t *b = bd.data() + h.z;
                 for (uint32_t j = 0; j < h.y; j++)
@@ -695,6 +800,9 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
 {
     auto t0 = clk::now();
     init_stream();
+    // the plan copies of an earlier query (one that failed part way too) are done
+    hipck(hipStreamSynchronize(g_stream), "sync");
+    g_pin.reset();
     QueryBufs &B = g_Q;
     const uint64_t x_hi = (uint64_t)(x >> 64);
     if (x > kWideMax)
@@ -923,12 +1031,6 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
     if (const char *tp = std::getenv("PICOUNT_TILE_TRACE"))
         trace_file = std::fopen(tp, "a");
     std::vector<pc_tile> tiles_a, tiles_b;
-    // Each window's tile lists stay unchanged until the final synchronisation:
-    // a copy from pageable memory may read its source only when the stream
-    // reaches it, which under load from other streams can be after the host
-    // has built the next window's lists.
-    std::vector<std::vector<pc_tile>> sent;
-    std::vector<std::vector<uint64_t>> sent_off; // the same for the row offsets
     uint64_t ntiles_total = 0;
     uint64_t *cin = ptr<uint64_t>(B.carry_a), *cout = ptr<uint64_t>(B.carry_b);
     const int bflag = K.batch ? 0 : 0x100;
@@ -954,13 +1056,8 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
             std::vector<uint64_t> off(rows + 1, 0);
             for (uint64_t r = 0; r < rows; r++)
                 off[r + 1] = off[r] + rowlen[r0 + r];
-            hipck(hipMemcpyAsync(B.row_off.p, off.data(), off.size() * 8, hipMemcpyHostToDevice,
-                                 g_stream),
-                  "row offsets");
-            hipck(hipMemcpyAsync(B.blkoff.p, blkoffs[w].data(), blkoffs[w].size() * 4,
-                                 hipMemcpyHostToDevice, g_stream),
-                  "scan blocks");
-            sent_off.push_back(std::move(off));
+            h2d(B.row_off.p, off.data(), off.size() * 8, g_stream, "row offsets");
+            h2d(B.blkoff.p, blkoffs[w].data(), blkoffs[w].size() * 4, g_stream, "scan blocks");
         }
         // rows [r0, min(r1, nA)) are small segments, the rest workgroup segments
         tiles_a.clear();
@@ -981,14 +1078,8 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
         const size_t npart = std::max(tiles_a.size(), tiles_b.size());
         ensure(B.part_tile_h, npart * 16, "tile partials");
         ensure(B.part_tile_p, npart * 16, "tile partials");
-        if (!tiles_a.empty())
-            hipck(hipMemcpyAsync(B.tiles_a.p, tiles_a.data(), tiles_a.size() * sizeof(pc_tile),
-                                 hipMemcpyHostToDevice, g_stream),
-                  "tiles");
-        if (!tiles_b.empty())
-            hipck(hipMemcpyAsync(B.tiles.p, tiles_b.data(), tiles_b.size() * sizeof(pc_tile),
-                                 hipMemcpyHostToDevice, g_stream),
-                  "tiles");
+        h2d(B.tiles_a.p, tiles_a.data(), tiles_a.size() * sizeof(pc_tile), g_stream, "tiles");
+        h2d(B.tiles.p, tiles_b.data(), tiles_b.size() * sizeof(pc_tile), g_stream, "tiles");
         auto sieve_args = [&](bool small) {
             pc_sieve_args A{};
             A.T = T;
@@ -1087,10 +1178,6 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
             hipck(pc_launch_sum128(ptr<pc_s128>(B.part_scan_p), 1, &sums->p2_dot, g_stream),
                   "sum");
         }
-        sent.push_back(std::move(tiles_a));
-        sent.push_back(std::move(tiles_b));
-        tiles_a = std::vector<pc_tile>();
-        tiles_b = std::vector<pc_tile>();
         if (!K.seeded)
             std::swap(cin, cout);
     }
@@ -2218,7 +2305,7 @@ pc_status pc_pi_count_ex(uint64_t x, const pc_config *cfg, pc_result *res)
     pc_status st = guarded([&] {
         Knobs K = knobs_from(cfg);
         if (cfg && (cfg->flags & PC_FLAG_REBUILD_TABLES))
-            drop_tables();
+            drop_tables(false);
         pi_one(x, K, cfg ? cfg->alpha : 0.0, &r, &v);
     });
     if (st == PC_OK && res)
@@ -2235,7 +2322,7 @@ pc_status pc_pi_count_wide(uint64_t x_lo, uint64_t x_hi, const pc_config *cfg, p
             fail(PC_ERANGE, "x must be at most 2^72");
         Knobs K = knobs_from(cfg);
         if (cfg && (cfg->flags & PC_FLAG_REBUILD_TABLES))
-            drop_tables();
+            drop_tables(false);
         pi_one(((pc_u128)x_hi << 64) | x_lo, K, cfg ? cfg->alpha : 0.0, &r, &v);
     });
     if (st == PC_OK && res)
@@ -2250,7 +2337,7 @@ pc_status pc_decompose(uint64_t x, uint64_t y, const pc_config *cfg, pc_result *
         check_y(x, y);
         Knobs K = knobs_from(cfg);
         if (cfg && (cfg->flags & PC_FLAG_REBUILD_TABLES))
-            drop_tables();
+            drop_tables(false);
         run_query(x, y, K, &r);
     });
     if (st == PC_OK && res)
@@ -2305,7 +2392,7 @@ pc_status pc_pi_count_batch_ex(const uint64_t *xs, size_t n, const pc_config *cf
         const double alpha = cfg ? cfg->alpha : 0.0;
         const uint32_t flags = cfg ? cfg->flags : 0u;
         if (flags & PC_FLAG_REBUILD_TABLES)
-            drop_tables();
+            drop_tables(false);
         if (flags & PC_FLAG_BATCH_SEQUENTIAL) {
             if (std::isnan(alpha) || alpha < 0)
                 fail(PC_EINVAL, "alpha must be >= 0 (0 = tuned)");
@@ -2525,7 +2612,7 @@ void pc_shutdown(void)
 {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     slot_release(g_slot);
-    drop_tables(); // waits for the caller-memory batches still queued
+    drop_tables(true); // waits for the caller-memory batches still queued
     async_wait_all();
     for (hipEvent_t e : g_async_spare)
         (void)hipEventDestroy(e);
@@ -2535,6 +2622,7 @@ void pc_shutdown(void)
     g_async_host = nullptr;
     g_async_host_cap = 0;
     drop_query_bufs();
+    g_pin.release();
     if (g_stream2) {
         (void)hipStreamSynchronize(g_stream2);
         (void)hipStreamDestroy(g_stream2);
