@@ -54,20 +54,57 @@ __global__ __launch_bounds__(1024) void k_base_primes(uint32_t *base, uint32_t *
 // ---------------------------------------------------------------------------
 // Segmented odd-only sieve of Eratosthenes over entries [0, nent): entry e
 // covers the odd numbers 64e+1 .. 64e+63.  Writes the prime bits into
-// tab[e].x and their popcount into cnt[e].
+// tab[e].x and their popcount into cnt[e].  The odd primes 3 .. 31 (the first
+// PT_NPRE base primes, over half of all the crossings) are not crossed one
+// multiple at a time: each word starts as the AND of their periodic masks,
+// chosen by the residue of the word's first odd number modulo each prime.
 // ---------------------------------------------------------------------------
 #define PT_WORDS 4096 // entries per workgroup: 131072 odd numbers
 #define PT_T 1024
+#define PT_NPRE 10
+namespace {
+constexpr uint32_t kPreQ[PT_NPRE] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
+constexpr uint32_t kPreOff[PT_NPRE + 1] = {0, 3, 8, 15, 26, 39, 56, 75, 98, 127, 158};
+// bits of 3 .. 31 in the first word (bit j <-> 2j + 1)
+constexpr uint32_t kPrePrimes = (1u << 1) | (1u << 2) | (1u << 3) | (1u << 5) | (1u << 6) |
+                                (1u << 8) | (1u << 9) | (1u << 11) | (1u << 14) | (1u << 15);
+} // namespace
 
 __global__ __launch_bounds__(PT_T) void k_sieve_pitab(uint64_t nent, const uint32_t *base,
                                                     uint32_t nbase, uint2 *tab, uint32_t *cnt)
 {
     __shared__ uint32_t bits[PT_WORDS];
     __shared__ uint32_t first[PT_T]; // start index of each small prime, computed once
+    __shared__ uint32_t keep[kPreOff[PT_NPRE]]; // per pre-sieved prime q and residue r
+    __shared__ uint32_t res0[PT_NPRE];          // the block's first odd number mod q
     const uint32_t t = threadIdx.x;
     const uint64_t e0 = (uint64_t)blockIdx.x * PT_WORDS;
-    for (uint32_t i = t; i < PT_WORDS; i += PT_T)
-        bits[i] = 0xFFFFFFFFu;
+    if (t < kPreOff[PT_NPRE]) {
+        // the word whose first odd number is r mod q keeps bit j unless q | r + 2j
+        uint32_t i = 0;
+        while (t >= kPreOff[i + 1])
+            i++;
+        const uint32_t q = kPreQ[i], r = t - kPreOff[i];
+        uint32_t w = 0xFFFFFFFFu;
+        for (uint32_t j = 0; j < 32; j++)
+            if ((r + 2 * j) % q == 0)
+                w &= ~(1u << j);
+        keep[t] = w;
+    }
+    if (t < PT_NPRE)
+        res0[t] = (uint32_t)((64 * e0 + 1) % kPreQ[t]);
+    __syncthreads();
+    for (uint32_t i = t; i < PT_WORDS; i += PT_T) {
+        uint32_t w = 0xFFFFFFFFu;
+#pragma unroll
+        for (uint32_t k = 0; k < PT_NPRE; k++) {
+            const uint32_t q = kPreQ[k];
+            w &= keep[kPreOff[k] + (res0[k] + (64 % q) * i) % q];
+        }
+        if (e0 == 0 && i == 0)
+            w = (w | kPrePrimes) & ~1u; // 3 .. 31 are prime, 1 is not
+        bits[i] = w;
+    }
     const uint64_t nlo = 64 * e0;                   // first integer covered
     const uint64_t nhi = 64 * (e0 + PT_WORDS) - 1;  // last integer covered
     const uint32_t NBIT = PT_WORDS * 32;
@@ -89,7 +126,8 @@ __global__ __launch_bounds__(PT_T) void k_sieve_pitab(uint64_t nent, const uint3
     if (small)
         first[t] = start(base[t]);
     const uint32_t nsm = (uint32_t)__syncthreads_count(small);
-    for (uint32_t k = 0; k < nsm; k++) {
+    // (every block ends at or above 64 PT_WORDS - 1 > 31^2: nsm > PT_NPRE)
+    for (uint32_t k = PT_NPRE; k < nsm; k++) {
         const uint32_t q = base[k];
         for (uint32_t i = first[k] + t * q; i < NBIT; i += PT_T * q)
             atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
@@ -102,9 +140,6 @@ __global__ __launch_bounds__(PT_T) void k_sieve_pitab(uint64_t nent, const uint3
         for (uint32_t i = start(q); i < NBIT; i += q)
             atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
     }
-    __syncthreads();
-    if (e0 == 0 && t == 0)
-        bits[0] &= ~1u; // 1 is not prime
     __syncthreads();
     for (uint32_t i = t; i < PT_WORDS; i += PT_T) {
         uint64_t e = e0 + i;

@@ -85,3 +85,21 @@ def test_read_table_rejects(pc):
     buf = np.zeros(1, dtype=np.uint64)
     assert pc.lib().pc_read_table(99, 0, 1, buf.ctypes.data) == pc.PC_EINVAL
     assert len(pc.read_table(pc.TABLE_PI, 5, 0)) == 0
+
+
+def test_rebuild_in_place_sequence(pc, oracle_mu_lpf, paper_pow10, paper_pow2):
+    # PC_FLAG_REBUILD_TABLES rebuilds every table into the device memory it
+    # already holds: through a growing and a shrinking pi table (above 2^32 at
+    # 2^65, with the primes past 2^32 as 64-bit values) each query still
+    # returns the paper's pi, and the mu * lpf table read after the rebuilds
+    # equals the oracle's
+    mu, lpf = oracle_mu_lpf
+    rb = pc.FLAG_REBUILD_TABLES
+    seq = [(10**18, paper_pow10[18]), (10**12, paper_pow10[12]), (2**65, paper_pow2[65]),
+           (10**15, paper_pow10[15]), (10**18, paper_pow10[18])]
+    for x, want in seq:
+        say("case: rebuild in place, x =", x)
+        got = pc.pi_count_wide(x, flags=rb).pi if x >> 64 else pc.pi_count_ex(x, flags=rb).pi
+        assert got == want, x
+    got = pc.read_table(pc.TABLE_MULPF, 0, Y_HEADLINE + 1).astype(np.int64)
+    assert (got == expected_mulpf(mu, lpf, 0, Y_HEADLINE + 1)).all()
