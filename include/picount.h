@@ -60,7 +60,7 @@ typedef struct {
     double alpha;          /* y = alpha * icbrt(x), clamped to [icbrt x, isqrt x]; 0 = tuned */
     uint32_t segment_kib;  /* LDS bitmap per sieve segment: 32 or 64                       */
     uint32_t wg_size;      /* sieve workgroup: 256|512 (32 KiB segments), 512|1024 (64)   */
-    uint32_t tile_leaves;  /* leaf items per sieve tile (hot segments split by columns); 0 = 2^21, 0xFFFFFFFF = off */
+    uint32_t tile_leaves;  /* leaf items per sieve tile (hot segments split by columns); 0 = 2^22, 0xFFFFFFFF = off */
     uint32_t flags;        /* PC_FLAG_* below */
     uint64_t carry_budget; /* bytes for per-(segment, prime) counts per window; 0 = auto  */
     uint32_t small_span;   /* one-wavefront segments cover [0, small_span * y); 0 = none    */

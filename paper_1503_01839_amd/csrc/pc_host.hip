@@ -606,7 +606,7 @@ struct Knobs {
     bool batch = true;
     bool seeded = false;             // windows seeded on their own (Section 4), run last to first
     uint64_t carry_budget = 6ull << 30;
-    uint64_t tile_leaves = 1u << 21; // hard-leaf items per tile; 0 = no column splitting
+    uint64_t tile_leaves = 1u << 22; // hard-leaf items per tile; 0 = no column splitting
     uint32_t hot_log2 = 15;          // small one-wavefront segments below hot_span * y
     uint32_t hot_wg = 64;
     uint64_t hot_span = 0;           // 0 = no small segments (the measured best at every size)

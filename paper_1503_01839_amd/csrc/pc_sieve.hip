@@ -78,7 +78,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
     constexpr uint32_t RSL = LOG2_S - (NWV == 1 ? 0 : NWV == 2 ? 1 : NWV == 4 ? 2 : NWV == 8 ? 3 : 4);
     static_assert((1u << RSL) == RS && RS == 64 * BPT * 512, "a region is 64 threads' blocks");
     constexpr uint32_t GCAP = pc_sieve_gcap<LOG2_S, T, CH>(); // gathered leaf items
-    constexpr uint32_t LIGHT = GCAP / 2; // more leaf items: the column is answered workgroup-wide
+    constexpr uint32_t LIGHT = GCAP / 4; // more leaf items: the column is answered workgroup-wide
     constexpr uint32_t XB_P = RS / 32;   // p >= XB_P: at most 32 multiples in a wave's region
     constexpr uint32_t KMAX = 64;         // columns per gather round (as in pc_sieve_waves_per_simd)
     static_assert(GCAP < 2048 && LIGHT < 2048, "gathered-column fields");
@@ -800,7 +800,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(
         // packs the survivors into its 64 slots of gbuf, so the divisions and
         // counts run on full wavefronts without workgroup barriers.
         auto heavy_col = [&](uint32_t j) {
-            constexpr uint32_t HU = 4;
+            constexpr uint32_t HU = 2;
             PC_PH(4);
             __syncthreads(); // every wave has crossed the columns before j
             settle();
