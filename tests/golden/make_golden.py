@@ -15,9 +15,10 @@ Calls nothing but the CPU oracle (``oracle/``) and the paper's Table 1.
 Usage: python tests/golden/make_golden.py [--big] [--tuned]
   --big   adds 1e16 (alpha 1, 2, 4, 8) and 1e18 (alpha 8, 16)
   --tuned adds the alphas the library picks by default: 1e16 (16), 1e17 (24),
-          1e18 (24)
+          1e18 (28; and 24, the default before the sieve's thresholds changed)
   --only-tuned  skips the small sieve-route records (they are kept from the
           existing file)
+  --only-missing  skips every record whose (x, y) the existing file already holds
 """
 import json
 import os
@@ -94,7 +95,20 @@ def job_sliced(x, alpha, n10, ex, nslices=96):
     return rec
 
 
+TUNED = ((10**16, 16, 16), (10**17, 24, 17), (10**18, 24, 18), (10**18, 28, 18))
+
+
+def y_of(x, alpha):
+    return min(alpha * O.icbrt(x), O.isqrt(x))
+
+
 def main():
+    path = os.path.join(HERE, "oracle_decomp.json")
+    old = []
+    if os.path.exists(path):
+        with open(path) as f:
+            old = json.load(f)["records"]
+    have = {(r["x"], r["y"]) for r in old} if "--only-missing" in sys.argv else set()
     specs = []
     if "--only-tuned" not in sys.argv:
         for n in (8, 9, 10, 11, 12):
@@ -107,24 +121,21 @@ def main():
             specs.append((10**16, alpha, "identity", 16))
         specs.append((10**18, 8, "identity", 18))
         specs.append((10**18, 16, "identity", 18))
+    specs = [s for s in specs if (s[0], y_of(s[0], s[1])) not in have]
     # largest first so the pool finishes together
     specs.sort(key=lambda s: -s[0] / s[1])
     with ProcessPoolExecutor(max_workers=int(os.environ.get("GOLDEN_JOBS", "6"))) as ex:
         recs = list(ex.map(job, specs))
         if "--tuned" in sys.argv:
-            for x, alpha, n10 in ((10**16, 16, 16), (10**17, 24, 17), (10**18, 24, 18)):
-                recs.append(job_sliced(x, alpha, n10, ex))
+            for x, alpha, n10 in TUNED:
+                if (x, y_of(x, alpha)) not in have:
+                    recs.append(job_sliced(x, alpha, n10, ex))
     recs.sort(key=lambda r: (r["x"], r["alpha"]))
     pw = paper_pow10()
     for r in recs:  # every record must reproduce the paper where the paper has a value
         for n, v in pw.items():
             if r["x"] == 10**n:
                 assert r["pi"] == v, r
-    path = os.path.join(HERE, "oracle_decomp.json")
-    old = []
-    if os.path.exists(path):
-        with open(path) as f:
-            old = json.load(f)["records"]
     keep = {(r["x"], r["y"]): r for r in old}
     for r in recs:
         keep[(r["x"], r["y"])] = r
