@@ -159,14 +159,17 @@ def lds_rmw_peak():
         return None
 
 
-def traffic_bytes():
+def traffic_bytes(x, y):
     """HBM bytes per sieve launch from the committed counter summary, or None
-    when there is none or the kernel source has changed since."""
+    when there is none, it was taken on another (x, y), or the kernel source
+    has changed since."""
     try:
         kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line)
     except OSError:
         return None
     if kv.get("kernel_sha256", "").strip() != kernel_sha256():
+        return None
+    if kv.get("workload_x_y", "").split() != [str(x), str(y)]:
         return None
     try:
         return float(kv["bytes_per_launch"])
@@ -430,7 +433,7 @@ def main():
     achieved = ops_per_launch / (avg_launch_ms / 1e3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK / 1e12,
             "unit": "T int-ops/s", "frac": achieved / INT_PEAK,
-            "traffic": traffic_bytes() if x == X and default_knobs else None,
+            "traffic": traffic_bytes(x, r.y) if x == X and default_knobs else None,
             "kernel": "k_sieve", "launches": launches, "avg_launch_ms": avg_launch_ms,
             "ops_per_launch": ops_per_launch,
             "work": {"crossings": r.crossings, "prime_visits": visits, "hard_leaves": r.n_hard,
