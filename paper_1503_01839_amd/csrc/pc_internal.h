@@ -69,7 +69,8 @@ struct pc_query {
     int32_t *wP;            // per row: the P2 terms landing in the row
     const uint64_t *carryP; // PC_MODE_LEAVES: exclusive carries of cntP
     // Easy leaves per b (pc_leaf_setup_item), in three kinds:
-    //   candidates (p_b^2 <= y): m = e_start[b] .. + e_count[b] - 1 (bit 63
+    //   candidates (p_b^2 <= y): the integers m prime to p_1..p_c, by their
+    //     wheel numbers k = e_start[b] .. + e_count[b] - 1 (pc_wheel_m; bit 63
     //     of e_count set), e_off the exclusive prefix of e_count over b and
     //     e_total[0] its total;
     //   singles (p_b^2 > y): primes p_k, k = e_start[b] .. + e_scount[b] - 1;

@@ -12,6 +12,7 @@
 
 #include "pc_block.h"
 #include "pc_internal.h"
+#include "pc_leafrange.h"
 
 #define PC_MODEBIT (1ull << 63)
 
@@ -141,8 +142,10 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
                 if (t0 < Q.y)
                     *triv = Q.a - pc_pi_lookup(T.pitab, t0);
             } else if (e1 <= e2) {
-                st = e1;
-                cn = (e2 - e1 + 1) | PC_MODEBIT;
+                // every m with lpf(m) > p_b > p_c is prime to p_1..p_c: only
+                // those are items, by their wheel numbers (pc_wheel_m)
+                st = pc_wheel_count(T, Q, e1 - 1);
+                cn = (pc_wheel_count(T, Q, e2) - st) | PC_MODEBIT;
             }
         }
         Q.e_start[b] = st;
@@ -216,8 +219,9 @@ __device__ __forceinline__ uint32_t pc_item_owner(const pc_query &Q, const uint6
     return lo_b;
 }
 
-// The candidate easy leaves (p_b^2 <= y), items laid end to end over b
-// (e_off = exclusive prefix of the counts, e_total[0] their sum).  The calling
+// The candidate easy leaves (p_b^2 <= y), items (wheel numbers of the m prime
+// to p_1..p_c) laid end to end over b (e_off = exclusive prefix of the counts,
+// e_total[0] their sum).  The calling
 // workgroup (NT threads; every thread calls) takes tiles lb, lb + nlb, ... of
 // NT * PER consecutive items; one search finds the b of a tile's first item,
 // then thread t takes items i0 + t, i0 + t + NT, ... so neighbouring lanes
@@ -251,7 +255,7 @@ __device__ __forceinline__ void pc_easy_tiles(const pc_tables &T, const pc_query
                 Xd = Q.Xd[b];
                 p = T.primes[b];
             }
-            const uint32_t m = (uint32_t)(st + (i - off));
+            const uint32_t m = pc_wheel_m(T, (uint32_t)(st + (i - off)));
             const int32_t v = T.mulpf[m];
             const uint32_t l = v < 0 ? (uint32_t)(-v) : (uint32_t)v;
             if (l <= p) // mu(m) = 0 or lpf(m) <= p_b
