@@ -15,7 +15,7 @@ Calls nothing but the CPU oracle (``oracle/``) and the paper's Table 1.
 Usage: python tests/golden/make_golden.py [--big] [--tuned]
   --big   adds 1e16 (alpha 1, 2, 4, 8) and 1e18 (alpha 8, 16)
   --tuned adds the alphas the library picks by default: 1e16 (16), 1e17 (24),
-          1e18 (28; and 24, the default before the sieve's thresholds changed)
+          1e18 (36; and 24 and 28, the defaults of earlier kernels)
   --only-tuned  skips the small sieve-route records (they are kept from the
           existing file)
   --only-missing  skips every record whose (x, y) the existing file already holds
@@ -95,7 +95,7 @@ def job_sliced(x, alpha, n10, ex, nslices=96):
     return rec
 
 
-TUNED = ((10**16, 16, 16), (10**17, 24, 17), (10**18, 24, 18), (10**18, 28, 18))
+TUNED = ((10**16, 16, 16), (10**17, 24, 17), (10**18, 24, 18), (10**18, 28, 18), (10**18, 36, 18))
 
 
 def y_of(x, alpha):
