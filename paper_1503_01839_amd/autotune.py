@@ -36,7 +36,7 @@ import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HEADER = os.path.join(HERE, "csrc", "pc_alpha_table.h")
-ALPHAS = [1, 1.5, 2, 3, 4, 6, 8, 12, 16, 24, 28, 32, 48, 64, 96]
+ALPHAS = [1, 1.5, 2, 3, 4, 6, 8, 12, 16, 24, 28, 32, 36, 40, 48, 64, 96]
 SHAPES = [(32, 512), (32, 256), (64, 512), (64, 1024)]  # (segment KiB, workgroup threads)
 BATCH_HI = 16.0   # half decades above take the single-query alpha in batches
 BATCH_SEED = 1503

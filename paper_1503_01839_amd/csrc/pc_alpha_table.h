@@ -12,29 +12,29 @@ struct pc_alpha_entry {
 };
 
 static const pc_alpha_entry kAlphaTable[] = {
-    {7.0, 32, 32, 512, 1}, // 0.39 ms
-    {7.5, 32, 32, 512, 8}, // 0.40 ms
+    {7.0, 16, 32, 512, 1}, // 0.38 ms
+    {7.5, 32, 32, 512, 4}, // 0.40 ms
     {8.0, 12, 32, 512, 1}, // 0.43 ms
-    {8.5, 48, 32, 512, 1.5}, // 0.47 ms
-    {9.0, 16, 64, 1024, 3}, // 0.52 ms
-    {9.5, 48, 64, 1024, 8}, // 0.57 ms
-    {10.0, 24, 64, 1024, 6}, // 0.62 ms
-    {10.5, 8, 32, 512, 8}, // 0.66 ms
-    {11.0, 16, 32, 512, 8}, // 0.72 ms
-    {11.5, 1.5, 32, 512, 6}, // 0.76 ms
-    {12.0, 2, 32, 512, 12}, // 0.80 ms
-    {12.5, 4, 32, 512, 8}, // 0.85 ms
-    {13.0, 2, 32, 512, 8}, // 0.97 ms
-    {13.5, 2, 32, 512, 12}, // 1.12 ms
-    {14.0, 6, 32, 512, 12}, // 1.36 ms
-    {14.5, 8, 32, 512, 12}, // 1.71 ms
-    {15.0, 12, 32, 512, 16}, // 2.29 ms
-    {15.5, 12, 32, 512, 16}, // 3.33 ms
-    {16.0, 16, 32, 512, 24}, // 5.29 ms
-    {16.5, 16, 32, 512, 16}, // 8.75 ms
-    {17.0, 24, 32, 512, 24}, // 17.06 ms
-    {17.5, 24, 32, 512, 24}, // 33.92 ms
-    {18.0, 28, 32, 512, 28}, // 69.34 ms
-    {18.5, 32, 32, 512, 32}, // 144.61 ms
-    {19.0, 32, 32, 512, 32}, // 308.42 ms
+    {8.5, 8, 32, 512, 2}, // 0.48 ms
+    {9.0, 8, 32, 512, 3}, // 0.53 ms
+    {9.5, 32, 32, 512, 8}, // 0.60 ms
+    {10.0, 36, 64, 1024, 12}, // 0.62 ms
+    {10.5, 8, 32, 512, 8}, // 0.67 ms
+    {11.0, 16, 32, 512, 8}, // 0.73 ms
+    {11.5, 1.5, 32, 512, 6}, // 0.77 ms
+    {12.0, 2, 32, 512, 12}, // 0.82 ms
+    {12.5, 4, 32, 512, 8}, // 0.86 ms
+    {13.0, 6, 32, 512, 8}, // 1.01 ms
+    {13.5, 4, 32, 512, 12}, // 1.14 ms
+    {14.0, 6, 32, 512, 16}, // 1.38 ms
+    {14.5, 8, 32, 512, 16}, // 1.73 ms
+    {15.0, 12, 32, 512, 24}, // 2.33 ms
+    {15.5, 12, 32, 512, 24}, // 3.37 ms
+    {16.0, 16, 32, 512, 24}, // 5.27 ms
+    {16.5, 16, 32, 512, 16}, // 8.72 ms
+    {17.0, 24, 32, 512, 24}, // 16.05 ms
+    {17.5, 32, 32, 512, 32}, // 31.61 ms
+    {18.0, 36, 32, 512, 36}, // 64.94 ms
+    {18.5, 40, 32, 512, 40}, // 134.61 ms
+    {19.0, 48, 32, 512, 48}, // 281.39 ms
 };

@@ -3,7 +3,7 @@ mu(n) * lpf(n)) read back through pc_read_table and compared entry by entry
 with the CPU oracle's plain sieves.
 
 The mu * lpf table is rebuilt several times at the size the headline query
-uses (y = 2.8e7, pi(10^18) at alpha 28): every build must equal the oracle's,
+uses (y = 3.6e7, pi(10^18) at alpha 36): every build must equal the oracle's,
 since a table kernel whose threads race would differ from build to build.
 """
 import numpy as np
@@ -13,7 +13,7 @@ import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-Y_HEADLINE = 28_000_000
+Y_HEADLINE = 36_000_000
 
 
 def say(*a):
