@@ -124,7 +124,7 @@ pc_status pc_pi_count_ex(uint64_t x, const pc_config *cfg, pc_result *res);
  * quotient, every x / p of P2 and every segment bound stays below 2^64; X_b,
  * S1's x / n and the sums are taken in 128 bits; the pi table reaches
  * isqrt(x) <= 2^36 with the primes above 2^32 held as 64-bit values (about
- * 49 GB of device memory at 2^72, the stored counts cut into 6 GiB windows). */
+ * 54 GB of device memory at 2^72, the stored counts cut into 6 GiB windows). */
 pc_status pc_pi_count_wide(uint64_t x_lo, uint64_t x_hi, const pc_config *cfg, pc_result *res);
 
 /* Hard special-leaf sum S2h = -sum over hard leaves of mu(m) phi(u, b-1),
