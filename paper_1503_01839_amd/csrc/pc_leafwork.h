@@ -68,7 +68,7 @@ __device__ __forceinline__ bool pc_s1_item(const pc_tables &T, const pc_query &Q
 //                   H_b = max(x/p_b^3, x/(p_b (y+1)));
 // for p_b^2 > y every m in the range is prime, so the range is stored as
 // prime indices; otherwise as candidate m (bit 63 of the count).  A prime
-// range is cut at s = 1.5 isqrt(x/p_b): each prime m <= s is a "single"
+// range is cut at s = isqrt(x/p_b): each prime m <= s is a "single"
 // (e_start, e_scount); above s, where u = x/(m p_b) < m and consecutive m
 // share pi(u), the primes m are taken by the value K = pi(u) instead: those
 // with x/(p_b p_{K+1}) < m <= x/(p_b p_K), all with phi(u, b-1) = K - b + 2
@@ -121,7 +121,7 @@ __device__ __forceinline__ void pc_leaf_setup_item(const pc_tables &T, const pc_
             if (p > Q.sqrty) {
                 if (e1 <= e2) {
                     const uint64_t sx = X.hi ? pc_isqrt_wide(X.hi, X.lo) : pc_isqrt(X.lo);
-                    uint64_t s = sx + sx / 2; // single-m items: m <= s
+                    uint64_t s = sx; // single-m items: m <= s
                     if (s < e1 - 1)
                         s = e1 - 1;
                     if (s > e2)
