@@ -54,6 +54,7 @@ std::atomic<size_t> g_dev_bytes{0}, g_dev_peak{0}; // device bytes held, and the
 
 hipStream_t g_stream = nullptr;  // the library stream
 hipStream_t g_stream2 = nullptr; // easy leaves, concurrent with the sieve (same priority)
+hipStream_t g_stream3 = nullptr; // the candidate easy leaves, beside the bands (same priority)
 
 // Completion events of caller-memory batches queued on callers' streams
 // (they read the shared tables), and spare events to record the next ones.
@@ -74,6 +75,8 @@ void dfree(DevBuf &b)
         async_wait_all(); // kernels queued earlier may still read the buffer
         if (g_stream2)
             (void)hipStreamSynchronize(g_stream2);
+        if (g_stream3)
+            (void)hipStreamSynchronize(g_stream3);
         if (g_stream)
             (void)hipStreamSynchronize(g_stream);
         (void)hipFree(b.p);
@@ -224,7 +227,7 @@ uint32_t seed_rec_cols(uint64_t m, uint32_t c, uint32_t nb)
 
 struct QueryBufs {
     DevBuf Ub, Xb, Xd, Xbh, e_start, e_count, e_off, e_scount, e_bk, e_boff, e_tmp, e_total, e_clu,
-        part, sums, fin, qdev;
+        part, part3, sums, fin, qdev;
     DevBuf work, hot, bounds, tiles_a, trace;
     DevBuf tiles, cnt, wgt, carry_rows, carry_a, carry_b, status, ticket, part_tile_h,
         part_tile_p, part_scan_h, part_scan_p, err;
@@ -232,7 +235,7 @@ struct QueryBufs {
 };
 QueryBufs g_Q;
 
-hipEvent_t g_fork = nullptr, g_join = nullptr;
+hipEvent_t g_fork = nullptr, g_join = nullptr, g_join3 = nullptr;
 
 void init_stream()
 {
@@ -240,6 +243,10 @@ void init_stream()
         hipck(hipStreamCreateWithFlags(&g_stream, hipStreamNonBlocking), "hipStreamCreate");
     if (!g_stream2)
         hipck(hipStreamCreateWithFlags(&g_stream2, hipStreamNonBlocking), "hipStreamCreate");
+    if (!g_stream3)
+        hipck(hipStreamCreateWithFlags(&g_stream3, hipStreamNonBlocking), "hipStreamCreate");
+    if (!g_join3)
+        hipck(hipEventCreateWithFlags(&g_join3, hipEventDisableTiming), "hipEventCreate");
     if (!g_fork)
         hipck(hipEventCreateWithFlags(&g_fork, hipEventDisableTiming), "hipEventCreate");
     if (!g_join)
@@ -513,6 +520,8 @@ void drop_tables(bool release)
         async_wait_all();
         if (g_stream2)
             (void)hipStreamSynchronize(g_stream2);
+        if (g_stream3)
+            (void)hipStreamSynchronize(g_stream3);
         if (g_stream)
             (void)hipStreamSynchronize(g_stream);
     }
@@ -527,7 +536,7 @@ void drop_tables(bool release)
 void drop_query_bufs()
 {
     QueryBufs &B = g_Q;
-    DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.Xd, &B.Xbh, &B.e_start, &B.e_count, &B.e_off, &B.e_scount, &B.e_bk, &B.e_boff, &B.e_tmp, &B.e_total, &B.e_clu, &B.part,
+    DevBuf *all[] = {&B.Ub, &B.work, &B.hot, &B.bounds, &B.tiles_a, &B.trace, &B.Xb, &B.Xd, &B.Xbh, &B.e_start, &B.e_count, &B.e_off, &B.e_scount, &B.e_bk, &B.e_boff, &B.e_tmp, &B.e_total, &B.e_clu, &B.part, &B.part3,
                      &B.sums, &B.fin, &B.tiles, &B.cnt, &B.wgt, &B.carry_rows,
                      &B.carry_a, &B.carry_b, &B.status, &B.ticket, &B.part_tile_h,
                      &B.part_tile_p, &B.part_scan_h, &B.part_scan_p, &B.err, &B.qdev,
@@ -884,6 +893,7 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
     const uint32_t ls_blocks = (uint32_t)(a / 256 + 1);
     const uint32_t ez_blocks = 4096;
     ensure(B.part, (size_t)std::max<uint32_t>({s1_blocks, ls_blocks, ez_blocks}) * 16, "partials");
+    ensure(B.part3, (size_t)ez_blocks * 16, "partials");
     auto t1 = clk::now();
     const size_t ev_s1 = timed(
         [&] { hipck(pc_launch_s1(T, Q, ptr<pc_s128>(B.part), s1_blocks, g_stream), "S1"); });
@@ -935,16 +945,21 @@ void run_query(pc_u128 x, uint64_t y, const Knobs &K, pc_result *res)
         forked = true;
         hipck(hipEventRecord(g_fork, g_stream), "hipEventRecord");
         hipck(hipStreamWaitEvent(g_stream2, g_fork, 0), "hipStreamWaitEvent");
+        // the bands (integer issue) and the candidates (table reads) side by
+        // side on two streams, each with its own partials
         ev_easy = timed(
             [&] {
+                hipck(hipStreamWaitEvent(g_stream3, g_fork, 0), "hipStreamWaitEvent");
+                hipck(pc_launch_easy(T, Q, ptr<pc_s128>(B.part3), ez_blocks, g_stream3), "easy");
+                hipck(hipEventRecord(g_join3, g_stream3), "hipEventRecord");
                 hipck(pc_launch_easy_band(T, Q, ptr<pc_s128>(B.part), ez_blocks, g_stream2),
                       "easy");
-                hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ez_blocks, &sums->s2e, g_stream2),
-                      "S2e sum");
-                hipck(pc_launch_easy(T, Q, ptr<pc_s128>(B.part), ez_blocks, g_stream2), "easy");
+                hipck(hipStreamWaitEvent(g_stream2, g_join3, 0), "hipStreamWaitEvent");
             },
             g_stream2);
         hipck(pc_launch_sum128(ptr<pc_s128>(B.part), ez_blocks, &sums->s2e, g_stream2),
+              "S2e sum");
+        hipck(pc_launch_sum128(ptr<pc_s128>(B.part3), ez_blocks, &sums->s2e, g_stream2),
               "S2e sum");
         hipck(hipEventRecord(g_join, g_stream2), "hipEventRecord");
     };
@@ -2623,16 +2638,17 @@ void pc_shutdown(void)
     g_async_host_cap = 0;
     drop_query_bufs();
     g_pin.release();
-    if (g_stream2) {
-        (void)hipStreamSynchronize(g_stream2);
-        (void)hipStreamDestroy(g_stream2);
-        g_stream2 = nullptr;
-    }
+    for (hipStream_t *st : {&g_stream2, &g_stream3})
+        if (*st) {
+            (void)hipStreamSynchronize(*st);
+            (void)hipStreamDestroy(*st);
+            *st = nullptr;
+        }
     if (g_stream) {
         (void)hipStreamDestroy(g_stream);
         g_stream = nullptr;
     }
-    for (hipEvent_t *e : {&g_fork, &g_join})
+    for (hipEvent_t *e : {&g_fork, &g_join, &g_join3})
         if (*e) {
             (void)hipEventDestroy(*e);
             *e = nullptr;
